@@ -1,0 +1,210 @@
+/*
+ * rpy.h -- C ABI of librpy, the MI355X (gfx950) implementation of the
+ * Ewald-summed Rotne-Prager-Yamakawa Brownian-dynamics step of
+ * Jain, Sunthar, Duenweg & Prakash, arXiv:1203.6208.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers to caller-owned memory unless a
+ *    comment says "host".  The library never frees or retains them past the
+ *    call (work is enqueued on the stream; the caller must keep the memory
+ *    alive until the stream reaches that point).
+ *  - All floating-point arrays are IEEE binary64, C-contiguous.
+ *  - Positions are [N][3] (bead nu at offset 3*nu).  Vectors are [m][N][3]:
+ *    right-hand side j starts at offset 3*N*j and component i of bead nu is at
+ *    3*nu + i within it (the flattened block index of the section "Governing
+ *    equation").  Positions are unwrapped; the library wraps them itself.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls only enqueue
+ *    work on it and do not synchronise, unless a comment says "synchronises".
+ *  - Return value: RPY_OK (0) or a negative RPY_E* code.  An error detected
+ *    on the host leaves outputs untouched.  A non-finite position is detected
+ *    on the device; it is reported by the next synchronising call
+ *    (rpy_status, rpy_bounds) as RPY_ENONFINITE.
+ *  - A context is not thread-safe: calls on one context must be ordered on a
+ *    single stream by the caller.  Distinct contexts are independent.
+ */
+#ifndef RPY_H
+#define RPY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RPY_OK = 0,
+    RPY_EINVAL = -1,     /* invalid argument (sizes, parameters, null pointers) */
+    RPY_EGEOM = -2,      /* box too small for the bead radius: 4a >= L */
+    RPY_ENONFINITE = -3, /* NaN or Inf found in positions */
+    RPY_ETOL = -4,       /* square-root error estimate above the tolerance */
+    RPY_ENOMEM = -5,     /* device allocation failed in rpy_create */
+    RPY_EHIP = -6        /* a HIP runtime call failed; see rpy_strerror */
+};
+
+/* Arithmetic of the real-space D.V products (the k-space sums, the
+ * Chebyshev recurrence and all accumulation across tiles stay FP64). */
+enum { RPY_PREC_F64 = 0, RPY_PREC_F32 = 1, RPY_PREC_BF16 = 2 };
+
+/* Chebyshev interval: explicit [d_min, d_max], or the paper's semidilute
+ * rule (section "Decomposition of the diffusion tensor", eq. lmax-lmin-dilute,
+ * fmax, fmin): lmax = 0.35 N^0.6 U+.D.U+/(3N), d_max = lmax,
+ * d_min = lmax / (C N^0.6). */
+enum { RPY_BOUNDS_EXPLICIT = 0, RPY_BOUNDS_PAPER = 1 };
+
+/* Problem statement (sections "Governing equation" and "Implementation of
+ * the Ewald sum"): N beads in a cubic periodic box of side box_l; bead radius
+ * a = sqrt(pi) h*; Ewald parameter alpha; real-space cutoff r_c (a periodic
+ * image enters the real-space sum iff |r| <= r_c); reciprocal cutoff k_c
+ * (the wave vectors are k = 2 pi n / L with n integer, n != 0 and
+ * |n|^2 <= floor((k_c L / (2 pi))^2)).  Beads are stored chain after chain,
+ * beads_per_chain each (n_chains * beads_per_chain == n_beads). */
+typedef struct {
+    int32_t n_beads;
+    int32_t n_chains;
+    int32_t beads_per_chain;
+    int32_t lowp;      /* low-precision copy of D kept by rpy_ewald_build:
+                          RPY_PREC_F64 (none), RPY_PREC_F32 or RPY_PREC_BF16 */
+    int32_t max_rhs;   /* largest m accepted by rpy_apply/chebyshev_sqrt_apply
+                          (1..16) */
+    int32_t reserved;
+    double box_l;
+    double a;
+    double alpha;
+    double r_c;
+    double k_c;
+} rpy_params;
+
+typedef struct rpy_ctx rpy_ctx;
+
+/* Validate p and allocate every device buffer the context needs (the stored
+ * real-space matrix, phase tables, work space).  No later call allocates.
+ * Errors: RPY_EINVAL for n_beads <= 0, box_l <= 0, a <= 0, alpha <= 0,
+ * r_c <= 0, k_c <= 0, an empty wave-vector set, chains that do not tile the
+ * beads, max_rhs outside 1..16 or an unknown lowp; RPY_EGEOM if 4a >= L
+ * (then two images of one pair could overlap); RPY_ENOMEM, RPY_EHIP. */
+int rpy_create(rpy_ctx **out, const rpy_params *p);
+
+/* Free the context and its device memory (synchronises the device). */
+void rpy_destroy(rpy_ctx *c);
+
+/* Build the diffusion tensor for the positions pos [N][3] (device):
+ * wraps positions into the box, tabulates the per-bead Fourier phases, and
+ * writes the real-space part of D -- self term, the lattice sum of M1 over
+ * every image with |r| <= r_c and the overlap correction M* for every image
+ * with |r| < 2a (eq. DFmodified; the reciprocal sum taken with
+ * cos(k.(r_nu - r_mu)), M* as the branch-B minus branch-A difference) --
+ * into the context's symmetric tile storage (plus the low-precision copy if
+ * lowp is set).  The reciprocal-space part is applied per product
+ * (rpy_apply), as in the paper's high-memory algorithm (section "Optimisation
+ * of each Euler time step"). */
+int rpy_ewald_build(rpy_ctx *c, const double *pos, void *stream);
+
+/* out = D . v for m right-hand sides (v, out: device [m][N][3], not
+ * aliased), D being the full periodic diffusion tensor of the last build:
+ * the stored real-space part in arithmetic `prec` (RPY_PREC_*; FP32/BF16 need
+ * the matching lowp copy) plus the reciprocal-space sum in FP64 (eq.
+ * DFmodified).  Errors: RPY_EINVAL (m outside 1..max_rhs, prec not built,
+ * null pointers). */
+int rpy_apply(rpy_ctx *c, const double *v, double *out, int m, int prec,
+              void *stream);
+
+/* Chebyshev interval by the paper's rule from the last build (one FP64
+ * product with U+).  d_min, d_max: HOST outputs.  Synchronises the stream;
+ * returns RPY_ENONFINITE if the last build saw a non-finite position. */
+int rpy_bounds(rpy_ctx *c, double C, double *d_min, double *d_max,
+               void *stream);
+
+/* Fixman-Chebyshev Brownian term (section "Decomposition of the diffusion
+ * tensor", eq. cheb1-cheb3): out = sum_{p<n_cheb} c_p V_p - (c_0/2) dW with
+ * V_0 = dW, V_1 = Y V_0, V_p = 2 Y V_{p-1} - V_{p-2},
+ * Y = (2 D - (d_max + d_min) I) / (d_max - d_min), c_p the coefficients of
+ * the interpolant of sqrt at the n_cheb Chebyshev-Gauss nodes of
+ * [d_min, d_max].  dw, out: device [m][N][3], not aliased.  The n_cheb - 1
+ * products use `prec` for the stored real-space part.  e_f: optional device
+ * [m] output of the error estimate
+ * E_f = sqrt(|dS.dS - dW.D.dW| / dW.D.dW) per right-hand side.
+ * Errors: RPY_EINVAL for n_cheb < 2, d_min <= 0, d_min >= d_max, m outside
+ * 1..max_rhs, prec not built. */
+int chebyshev_sqrt_apply(rpy_ctx *c, const double *dw, double *out, int m,
+                         int n_cheb, double d_min, double d_max, int prec,
+                         double *e_f, void *stream);
+
+/* One Euler-Maruyama step (eq. sde with kappa = 0):
+ *   r <- r + (dt/4) D.F + (1/sqrt 2) dS,  dS ~ sqrt(D) dW by Chebyshev,
+ * with F = Hookean springs (F_mu = Q_mu - Q_{mu-1}) plus, when ev_zstar > 0,
+ * narrow-Gaussian excluded volume between all beads,
+ *   U = zs ds^-3 exp(-r^2 / (2 ds^2)) with zs = ev_zstar, ds = ev_dstar,
+ * for pairs closer than ev_rcut
+ * (minimum image; requires ev_rcut < L/2).
+ * dw: device [N][3] noise with variance dt, or NULL to draw it on the device
+ * from (seed, step) with Philox4x32-10 and Box-Muller (the mapping of
+ * rpy_gaussian_noise with count 3N).
+ * pos: device [N][3], updated in place.  drift, noise, e_f: optional device
+ * outputs ([N][3] D.F, [N][3] dS, [1] E_f).  Bounds follow bounds_rule.
+ * prec selects the arithmetic of the Chebyshev products; the drift and the
+ * bounds always use FP64. */
+typedef struct {
+    double dt;
+    double ev_zstar;    /* 0 disables excluded volume */
+    double ev_dstar;
+    double ev_rcut;
+    double bounds_C;    /* C of the paper's rule */
+    double d_min;       /* explicit bounds (RPY_BOUNDS_EXPLICIT) */
+    double d_max;
+    int32_t n_cheb;
+    int32_t bounds_rule;
+    int32_t prec;
+    int32_t reserved;
+} bd_params;
+
+int bd_step(rpy_ctx *c, double *pos, const bd_params *bp, const double *dw,
+            uint64_t seed, uint64_t step, double *drift, double *noise,
+            double *e_f, void *stream);
+
+/* Synchronise the stream and report a non-finite position seen by an
+ * earlier build (RPY_ENONFINITE, flag then cleared) or RPY_OK. */
+int rpy_status(rpy_ctx *c, void *stream);
+
+/* Copy the stored real-space part of D (FP64) into a dense row-major
+ * device buffer out[3N][3N]. */
+int rpy_real_space_dense(rpy_ctx *c, double *out, void *stream);
+
+/* Per-chain observables (section "Testing and verification"):
+ * re2[c] = |r_last - r_first|^2, rg2[c] = mean over beads of |r - r_cm|^2
+ * (equal to the paper's pair form).  pos: device [N][3]; outputs device
+ * [n_chains]. */
+int rpy_observables(rpy_ctx *c, const double *pos, double *re2, double *rg2,
+                    void *stream);
+
+/* Forces used by bd_step for the given positions: out[N][3] (device). */
+int rpy_forces(rpy_ctx *c, const double *pos, double zstar, double dstar,
+               double rcut, double *out, void *stream);
+
+/* Gaussian noise with variance dt from Philox4x32-10 (same mapping as
+ * bd_step): out[count] device. */
+int rpy_gaussian_noise(double *out, int64_t count, uint64_t seed,
+                       uint64_t step, double dt, void *stream);
+
+/* Philox4x32-10 blocks: ctr_key device [n][6] uint32 (4 counter words then
+ * 2 key words), out device [n][4]. */
+int rpy_philox4x32_10(const uint32_t *ctr_key, uint32_t *out, int64_t n,
+                      void *stream);
+
+/* Host-only helper for tests: the 3x3 real-space block that one pair of
+ * beads with wrapped separation d = r_nu - r_mu (host double[3]) receives
+ * from all its images, computed by the same code the build kernel runs
+ * (self = 1 adds the self term and omits the zero image).  out: host [9]. */
+int rpy_host_pair_block(const rpy_params *p, const double *d, int self,
+                        double *out);
+
+/* Number of wave vectors in the half-space set used per product. */
+int rpy_num_kvectors(const rpy_ctx *c);
+
+/* Human-readable text for an error code (static storage). */
+const char *rpy_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPY_H */

@@ -23,6 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
+_ip = ctypes.POINTER(ctypes.c_int)
 
 
 def build(force: bool = True) -> str:
@@ -55,6 +56,9 @@ def _L():
             "orc_m2_scalar": (d, [d, d, d, d]),
             "orc_wrap": (None, [i, p, d, p]),
             "orc_real_space": (None, [i, p, d, d, d, d, p]),
+            "orc_real_space_rows": (None, [i, p, d, d, d, d, i, _ip, p]),
+            "orc_recip_space_rows": (None, [i, p, d, d, d, i, i, _ip, p]),
+            "orc_self_term_rows": (None, [i, d, d, i, _ip, p]),
             "orc_self_term": (None, [i, d, d, p]),
             "orc_recip_space": (None, [i, p, d, d, d, i, p]),
             "orc_count_kvectors": (i, [i]),
@@ -172,6 +176,21 @@ def diffusion_matrix(pos, L, a, alpha, rc, n2max) -> np.ndarray:
     """Full periodic diffusion matrix D (eq. DFmodified read as a matrix)."""
     return real_space_matrix(pos, L, a, alpha, rc) + recip_space_matrix(
         pos, L, a, alpha, n2max)
+
+
+def diffusion_rows(pos, rows, L, a, alpha, rc, n2max) -> np.ndarray:
+    """Block rows of the full periodic D for the listed beads: [3*len(rows), 3N]
+    (same sums as diffusion_matrix, restricted to those rows)."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    rt = wrap(pos, L)
+    r = np.ascontiguousarray(np.asarray(rows, dtype=np.intc))
+    rp = r.ctypes.data_as(_ip)
+    D = np.zeros((3 * len(r), 3 * n))
+    _L().orc_real_space_rows(n, _ptr(rt), L, a, alpha, rc, len(r), rp, _ptr(D))
+    _L().orc_self_term_rows(n, a, alpha, len(r), rp, _ptr(D))
+    _L().orc_recip_space_rows(n, _ptr(rt), L, a, alpha, int(n2max), len(r), rp, _ptr(D))
+    return D
 
 
 def matvec(D, V) -> np.ndarray:

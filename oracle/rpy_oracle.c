@@ -191,19 +191,22 @@ static void pair_image(const double d[3], double r2, int in_rc, int overlap,
 
 /* ------------------------------------------------------------------------
  * Real-space part of D (eq. DFmodified: second and last sums), brute force
+ * (rows variant: only the block rows of the listed beads, stored densely in
+ * list order as D[3*nrows][3N])
  * over every pair and every periodic image n in [-ni, ni]^3 with
  * ni = ceil(rc/L) + 1.  The image (nu, nu, 0) is omitted (the prime on the
  * lattice sum).  Images with |d| <= rc take M1; images with |d| < 2a add M*.
  * D is accumulated (+=); rt are wrapped positions.
  * ---------------------------------------------------------------------- */
-void orc_real_space(int n, const double *rt, double L, double a, double al,
-                    double rc, double *D)
+void orc_real_space_rows(int n, const double *rt, double L, double a, double al,
+                         double rc, int nrows, const int *rows, double *D)
 {
     int ni = (int)ceil(rc / L) + 1;
     double rc2 = rc * rc, a2x4 = 4.0 * a * a;
     long n3 = 3L * n;
 #pragma omp parallel for schedule(dynamic)
-    for (int nu = 0; nu < n; ++nu) {
+    for (int ir = 0; ir < nrows; ++ir) {
+        int nu = rows[ir];
         for (int mu = 0; mu < n; ++mu) {
             double blk[9] = {0};
             for (int nx = -ni; nx <= ni; ++nx)
@@ -222,9 +225,27 @@ void orc_real_space(int n, const double *rt, double L, double a, double al,
                     }
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j)
-                    D[(3L * nu + i) * n3 + 3L * mu + j] += blk[3 * i + j];
+                    D[(3L * ir + i) * n3 + 3L * mu + j] += blk[3 * i + j];
         }
     }
+}
+
+void orc_real_space(int n, const double *rt, double L, double a, double al,
+                    double rc, double *D)
+{
+    int *rows = (int *)malloc(sizeof(int) * n);
+    for (int i = 0; i < n; ++i) rows[i] = i;
+    orc_real_space_rows(n, rt, L, a, al, rc, n, rows, D);
+    free(rows);
+}
+
+/* Self term on a row subset: D[ir] row block of bead rows[ir]. */
+void orc_self_term_rows(int n, double a, double al, int nrows, const int *rows, double *D)
+{
+    double s = orc_self_coeff(a, al);
+    long n3 = 3L * n;
+    for (int ir = 0; ir < nrows; ++ir)
+        for (int i = 0; i < 3; ++i) D[(3L * ir + i) * n3 + 3L * rows[ir] + i] += s;
 }
 
 /* Self term (eq. DF, first term): D_nu,nu += s(alpha) I. */
@@ -240,14 +261,15 @@ void orc_self_term(int n, double a, double al, double *D)
  * of wave vectors k = 2 pi nvec / L, nvec != 0, |nvec|^2 <= n2max, with a
  * direct cosine per pair: D_nu,mu += m(k) (I - khat khat) cos(k.(r_nu - r_mu)).
  * ---------------------------------------------------------------------- */
-void orc_recip_space(int n, const double *rt, double L, double a, double al,
-                     int n2max, double *D)
+void orc_recip_space_rows(int n, const double *rt, double L, double a, double al,
+                          int n2max, int nrows, const int *rows, double *D)
 {
     double vol = L * L * L;
     int nm = (int)floor(sqrt((double)n2max)) + 1;
     long n3 = 3L * n;
 #pragma omp parallel for schedule(dynamic)
-    for (int nu = 0; nu < n; ++nu) {
+    for (int ir = 0; ir < nrows; ++ir) {
+        int nu = rows[ir];
         for (int nx = -nm; nx <= nm; ++nx)
             for (int ny = -nm; ny <= nm; ++ny)
                 for (int nz = -nm; nz <= nm; ++nz) {
@@ -268,10 +290,19 @@ void orc_recip_space(int n, const double *rt, double L, double a, double al,
                         double w = mk * cos(ph);
                         for (int i = 0; i < 3; ++i)
                             for (int j = 0; j < 3; ++j)
-                                D[(3L * nu + i) * n3 + 3L * mu + j] += w * P[3 * i + j];
+                                D[(3L * ir + i) * n3 + 3L * mu + j] += w * P[3 * i + j];
                     }
                 }
     }
+}
+
+void orc_recip_space(int n, const double *rt, double L, double a, double al,
+                     int n2max, double *D)
+{
+    int *rows = (int *)malloc(sizeof(int) * n);
+    for (int i = 0; i < n; ++i) rows[i] = i;
+    orc_recip_space_rows(n, rt, L, a, al, n2max, n, rows, D);
+    free(rows);
 }
 
 /* Number of wave vectors in the full set (both signs). */

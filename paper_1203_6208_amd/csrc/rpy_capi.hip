@@ -1,0 +1,526 @@
+// rpy_capi.hip -- the C ABI declared in include/rpy.h: parameter validation,
+// one-time allocation, wave-vector tables and the orchestration of every
+// entry point on the caller's stream.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "rpy_internal.h"
+
+using namespace rpy;
+
+struct rpy_ctx {
+    Ctx c;
+    double *F = nullptr;      // [2][3N]: forces, then U+ (all ones)
+    double *Y = nullptr;      // [2][3N]: D.F, D.U+
+    double *dW = nullptr;     // [3N]
+    double *dS = nullptr;     // [3N]
+    double *Bv[2] = {nullptr, nullptr};  // [max_rhs][3N] Chebyshev vectors
+    double *ddw = nullptr;    // [max_rhs][3N] D.dW
+    double *acc = nullptr;    // [max_rhs][3N] scratch accumulator
+};
+
+static thread_local char g_err[256];
+
+static int hip_fail(hipError_t e, const char *what)
+{
+    snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
+    return RPY_EHIP;
+}
+
+#define HIP_TRY(x)                                  \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #x); \
+    } while (0)
+
+static int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return RPY_OK;
+}
+
+namespace rpy {
+
+// Series of the smooth part S = Omega_A - M1 in x^2 (x = alpha r), from
+// erf(x)/x = (2/sqrt pi) sum (-1)^n x^{2n}/(n!(2n+1)) and
+// e^{-x^2} = sum (-1)^n x^{2n}/n!:
+//   f1_n = (-1)^n/n! [3/(2(2n+1)) + 9/2 + 3n]
+//   g1_n = (-1)^n [1/(n+1)! - 1/((n+1)!(2n+3)) - (14 + 20n + 4n(n-1))/n!]
+//   f2_n = (-1)^n/n! [3/(2(2n+1)) - 3/2 - 3n]
+//   g2_n = (-1)^n [3/((n+1)!(2n+3)) - 3/(n+1)! + (2 + 16n + 4n(n-1))/n!]
+// S1 = (A1 sum f1_n x^2n + A3 sum g1_n x^2n)/sqrt(pi), S2 likewise.
+PairConst make_pair_const(double L, double a, double alpha, double rc)
+{
+    PairConst p;
+    memset(&p, 0, sizeof p);
+    p.L = L;
+    p.invL = 1.0 / L;
+    p.a = a;
+    p.alpha = alpha;
+    p.rc = rc;
+    p.rc2 = rc * rc;
+    p.reach = rc > 2.0 * a ? rc : 2.0 * a;
+    p.a2x4 = 4.0 * a * a;
+    p.inv_sqrtpi = 1.0 / sqrt(M_PI);
+    p.A1 = a * alpha;
+    p.A3 = p.A1 * p.A1 * p.A1;
+    p.self_coeff = 1.0 - 6.0 * p.A1 * p.inv_sqrtpi + 40.0 * p.A3 * p.inv_sqrtpi / 3.0;
+    double fact = 1.0;  // n!
+    for (int n = 0; n < NSER; ++n) {
+        if (n > 0) fact *= n;
+        const double fact1 = fact * (n + 1);  // (n+1)!
+        const double sg = (n & 1) ? -1.0 : 1.0;
+        const double f1 = sg / fact * (3.0 / (2.0 * (2 * n + 1)) + 4.5 + 3.0 * n);
+        const double g1 = sg * (1.0 / fact1 - 1.0 / (fact1 * (2 * n + 3))
+                                - (14.0 + 20.0 * n + 4.0 * n * (n - 1)) / fact);
+        const double f2 = sg / fact * (3.0 / (2.0 * (2 * n + 1)) - 1.5 - 3.0 * n);
+        const double g2 = sg * (3.0 / (fact1 * (2 * n + 3)) - 3.0 / fact1
+                                + (2.0 + 16.0 * n + 4.0 * n * (n - 1)) / fact);
+        p.s1[n] = (p.A1 * f1 + p.A3 * g1) * p.inv_sqrtpi;
+        p.s2[n] = (p.A1 * f2 + p.A3 * g2) * p.inv_sqrtpi;
+    }
+    return p;
+}
+
+}  // namespace rpy
+
+static int validate(const rpy_params *p, int *n2max_out)
+{
+    if (!p) return RPY_EINVAL;
+    if (p->n_beads <= 0 || !(p->box_l > 0) || !(p->a > 0) || !(p->alpha > 0) || !(p->r_c > 0) ||
+        !(p->k_c > 0) || !isfinite(p->box_l) || !isfinite(p->a) || !isfinite(p->alpha) ||
+        !isfinite(p->r_c) || !isfinite(p->k_c)) {
+        snprintf(g_err, sizeof g_err, "non-positive or non-finite size or Ewald parameter");
+        return RPY_EINVAL;
+    }
+    if (p->n_chains <= 0 || p->beads_per_chain <= 0 ||
+        (int64_t)p->n_chains * p->beads_per_chain != p->n_beads) {
+        snprintf(g_err, sizeof g_err, "n_chains * beads_per_chain must equal n_beads");
+        return RPY_EINVAL;
+    }
+    if (p->max_rhs < 1 || p->max_rhs > MAX_RHS) {
+        snprintf(g_err, sizeof g_err, "max_rhs must be in 1..%d", MAX_RHS);
+        return RPY_EINVAL;
+    }
+    if (p->lowp != RPY_PREC_F64 && p->lowp != RPY_PREC_F32 && p->lowp != RPY_PREC_BF16) {
+        snprintf(g_err, sizeof g_err, "unknown lowp");
+        return RPY_EINVAL;
+    }
+    if (!(4.0 * p->a < p->box_l)) {
+        snprintf(g_err, sizeof g_err, "box too small: need 4a < L");
+        return RPY_EGEOM;
+    }
+    const double q = p->k_c * p->box_l / (2.0 * M_PI);
+    const double n2 = floor(q * q);
+    if (n2 < 1.0 || n2 > 255.0) {
+        snprintf(g_err, sizeof g_err, "wave-vector cutoff gives |n|^2 <= %.0f (need 1..255)", n2);
+        return RPY_EINVAL;
+    }
+    // real-space images per axis must stay bounded
+    if (p->r_c > 64.0 * p->box_l) {
+        snprintf(g_err, sizeof g_err, "r_c > 64 L");
+        return RPY_EINVAL;
+    }
+    *n2max_out = (int)n2;
+    return RPY_OK;
+}
+
+template <typename T> static int dalloc(T **p, size_t n)
+{
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        snprintf(g_err, sizeof g_err, "hipMalloc(%zu bytes): %s", n * sizeof(T),
+                 hipGetErrorString(e));
+        return RPY_ENOMEM;
+    }
+    return RPY_OK;
+}
+
+extern "C" void rpy_destroy(rpy_ctx *x)
+{
+    if (!x) return;
+    (void)hipDeviceSynchronize();
+    Ctx &c = x->c;
+    void *bufs[] = {c.rt, c.etab, c.kvec, c.kcoef, c.tile_ij, c.d64, c.d32, c.d16, c.part,
+                    c.sfpart, c.tk, c.work, c.scal, c.red, c.flags, c.cell_start, c.cell_beads};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    delete x;
+}
+
+extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
+{
+    if (!out) return RPY_EINVAL;
+    *out = nullptr;
+    int n2max = 0;
+    int rc = validate(p, &n2max);
+    if (rc) return rc;
+    rpy_ctx *x = new (std::nothrow) rpy_ctx();
+    if (!x) return RPY_ENOMEM;
+    Ctx &c = x->c;
+    c.N = p->n_beads;
+    c.n3 = 3 * c.N;
+    c.nchains = p->n_chains;
+    c.bpc = p->beads_per_chain;
+    c.L = p->box_l;
+    c.a = p->a;
+    c.alpha = p->alpha;
+    c.rc = p->r_c;
+    c.kc = p->k_c;
+    c.n2max = n2max;
+    c.nmax = (int)floor(sqrt((double)n2max));
+    while ((c.nmax + 1) * (c.nmax + 1) <= n2max) ++c.nmax;
+    while (c.nmax * c.nmax > n2max) --c.nmax;
+    c.lowp = p->lowp;
+    c.max_rhs = p->max_rhs;
+    c.rhs_cap = c.max_rhs > 2 ? c.max_rhs : 2;
+    c.pc = make_pair_const(c.L, c.a, c.alpha, c.rc);
+    c.nbt = (c.N + TB - 1) / TB;
+    c.ntiles = c.nbt * (c.nbt + 1) / 2;
+    c.n3pad = c.nbt * TS;
+    c.nsfc = (c.N + 63) / 64;
+
+    // half-space wave vectors, lexicographically positive
+    std::vector<KVec> kv;
+    std::vector<KCoef> kc;
+    const double vol = c.L * c.L * c.L;
+    for (int nx = 0; nx <= c.nmax; ++nx)
+        for (int ny = -c.nmax; ny <= c.nmax; ++ny)
+            for (int nz = -c.nmax; nz <= c.nmax; ++nz) {
+                const int n2 = nx * nx + ny * ny + nz * nz;
+                if (n2 == 0 || n2 > n2max) continue;
+                if (nx == 0 && (ny < 0 || (ny == 0 && nz < 0))) continue;
+                const double kx = 2.0 * M_PI * nx / c.L, ky = 2.0 * M_PI * ny / c.L,
+                             kz = 2.0 * M_PI * nz / c.L;
+                const double k2 = kx * kx + ky * ky + kz * kz, k = sqrt(k2);
+                const double al2 = c.alpha * c.alpha;
+                const double mk = (c.a - c.a * c.a * c.a * k2 / 3.0) *
+                                  (1.0 + k2 / (4.0 * al2) + k2 * k2 / (8.0 * al2 * al2)) *
+                                  (6.0 * M_PI / (k2 * vol)) * exp(-k2 / (4.0 * al2));
+                kv.push_back(KVec{nx, ny, nz, 0});
+                kc.push_back(KCoef{2.0 * mk, kx / k, ky / k, kz / k});
+            }
+    c.nk = (int)kv.size();
+
+    std::vector<int2> tij;
+    for (int I = 0; I < c.nbt; ++I)
+        for (int J = I; J < c.nbt; ++J) tij.push_back(make_int2(I, J));
+
+    const size_t te = (size_t)c.ntiles * TILE_ELEMS;
+    const size_t nv = (size_t)c.n3;
+    const size_t mv = (size_t)c.rhs_cap * nv;
+    c.work_elems = 2 * nv + 2 * nv + nv + nv + 2 * mv + mv + mv;
+    const int ncell_cap = 64;
+    const size_t ncells_cap = (size_t)ncell_cap * ncell_cap * ncell_cap;
+    if ((rc = dalloc(&c.rt, nv)) || (rc = dalloc(&c.etab, nv * (c.nmax + 1))) ||
+        (rc = dalloc(&c.kvec, kv.size())) || (rc = dalloc(&c.kcoef, kc.size())) ||
+        (rc = dalloc(&c.tile_ij, tij.size())) || (rc = dalloc(&c.d64, te)) ||
+        (c.lowp == RPY_PREC_F32 && (rc = dalloc(&c.d32, te))) ||
+        (c.lowp == RPY_PREC_BF16 && (rc = dalloc(&c.d16, te))) ||
+        (rc = dalloc(&c.part, (size_t)c.nbt * c.rhs_cap * c.n3pad)) ||
+        (rc = dalloc(&c.sfpart, (size_t)c.nsfc * 6 * c.rhs_cap * c.nk)) ||
+        (rc = dalloc(&c.tk, (size_t)6 * c.rhs_cap * c.nk)) ||
+        (rc = dalloc(&c.work, c.work_elems)) || (rc = dalloc(&c.scal, 8 + MAX_NCHEB)) ||
+        (rc = dalloc(&c.red, 64)) || (rc = dalloc(&c.flags, 4)) ||
+        (rc = dalloc(&c.cell_start, 2 * ncells_cap + 1)) || (rc = dalloc(&c.cell_beads, nv))) {
+        rpy_destroy(x);
+        return rc;
+    }
+    double *w = c.work;
+    x->F = w; w += 2 * nv;
+    x->Y = w; w += 2 * nv;
+    x->dW = w; w += nv;
+    x->dS = w; w += nv;
+    x->Bv[0] = w; w += mv;
+    x->Bv[1] = w; w += mv;
+    x->ddw = w; w += mv;
+    x->acc = w; w += mv;
+    hipError_t e;
+    if ((e = hipMemcpy(c.kvec, kv.data(), kv.size() * sizeof(KVec), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c.kcoef, kc.data(), kc.size() * sizeof(KCoef), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c.tile_ij, tij.data(), tij.size() * sizeof(int2), hipMemcpyHostToDevice)) ||
+        (e = hipMemset(c.flags, 0, 4 * sizeof(int))) ||
+        (e = hipMemset(c.d64, 0, te * sizeof(double)))) {
+        rc = hip_fail(e, "rpy_create upload");
+        rpy_destroy(x);
+        return rc;
+    }
+    launch_fill(x->F + nv, 1.0, nv, 0);   // U+ = (1, 1, ..., 1)
+    if ((e = hipDeviceSynchronize()) != hipSuccess) {
+        rc = hip_fail(e, "rpy_create sync");
+        rpy_destroy(x);
+        return rc;
+    }
+    *out = x;
+    return RPY_OK;
+}
+
+static inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" int rpy_ewald_build(rpy_ctx *x, const double *pos, void *stream)
+{
+    if (!x || !pos) return RPY_EINVAL;
+    launch_wrap_tables(x->c, pos, S(stream));
+    launch_build_tiles(x->c, S(stream));
+    return check_launch("rpy_ewald_build");
+}
+
+static bool prec_ok(const Ctx &c, int prec)
+{
+    return prec == RPY_PREC_F64 || (prec == RPY_PREC_F32 && c.lowp == RPY_PREC_F32) ||
+           (prec == RPY_PREC_BF16 && c.lowp == RPY_PREC_BF16);
+}
+
+// one product of the full periodic D with m vectors (no validation)
+static void product(rpy_ctx *x, const double *v, int m, int prec, const FinArgs &fin,
+                    hipStream_t s)
+{
+    const Ctx &c = x->c;
+    launch_structure_factors(c, v, m, s);
+    launch_symv(c, prec, v, m, s);
+    launch_sf_reduce(c, m, s);
+    launch_finalize(c, fin, s);
+}
+
+extern "C" int rpy_apply(rpy_ctx *x, const double *v, double *out, int m, int prec,
+                         void *stream)
+{
+    if (!x || !v || !out || m < 1 || m > x->c.max_rhs || !prec_ok(x->c, prec)) return RPY_EINVAL;
+    FinArgs f{};
+    f.mode = FIN_APPLY;
+    f.m = m;
+    f.vout = out;
+    product(x, v, m, prec, f, S(stream));
+    return check_launch("rpy_apply");
+}
+
+// Chebyshev recurrence with coefficients already in c.scal.
+static void cheb_run(rpy_ctx *x, const double *dw, double *out, int m, int n_cheb, int prec,
+                     hipStream_t s)
+{
+    const Ctx &c = x->c;
+    for (int p = 1; p < n_cheb; ++p) {
+        FinArgs f{};
+        f.m = m;
+        f.p = p;
+        f.scal = c.scal;
+        f.acc = out;
+        if (p == 1) {
+            f.mode = FIN_CHEB_FIRST;
+            f.vprev = dw;
+            f.vout = x->Bv[1];
+            f.dv = x->ddw;
+        } else {
+            f.mode = FIN_CHEB_NEXT;
+            f.vprev = x->Bv[(p - 1) % 2];
+            f.vprev2 = p == 2 ? dw : x->Bv[p % 2];
+            f.vout = x->Bv[p % 2];
+        }
+        product(x, f.vprev, m, prec, f, s);
+    }
+}
+
+extern "C" int chebyshev_sqrt_apply(rpy_ctx *x, const double *dw, double *out, int m,
+                                    int n_cheb, double d_min, double d_max, int prec,
+                                    double *e_f, void *stream)
+{
+    if (!x || !dw || !out || m < 1 || m > x->c.max_rhs || n_cheb < 2 || n_cheb > MAX_NCHEB ||
+        !(d_min > 0) || !(d_max > d_min) || !isfinite(d_max) || !prec_ok(x->c, prec))
+        return RPY_EINVAL;
+    hipStream_t s = S(stream);
+    launch_cheb_coeffs(x->c, n_cheb, RPY_BOUNDS_EXPLICIT, 0.0, d_min, d_max, nullptr, s);
+    cheb_run(x, dw, out, m, n_cheb, prec, s);
+    if (e_f) launch_sqrt_error(x->c, m, dw, x->ddw, out, e_f, s);
+    return check_launch("chebyshev_sqrt_apply");
+}
+
+extern "C" int rpy_bounds(rpy_ctx *x, double C, double *d_min, double *d_max, void *stream)
+{
+    if (!x || !d_min || !d_max || !(C > 0)) return RPY_EINVAL;
+    hipStream_t s = S(stream);
+    const Ctx &c = x->c;
+    FinArgs f{};
+    f.mode = FIN_APPLY;
+    f.m = 1;
+    f.vout = x->Y + c.n3;
+    product(x, x->F + c.n3, 1, RPY_PREC_F64, f, s);
+    launch_cheb_coeffs(c, 2, RPY_BOUNDS_PAPER, C, 0, 0, x->Y + c.n3, s);
+    int rc = check_launch("rpy_bounds");
+    if (rc) return rc;
+    double h[2];
+    HIP_TRY(hipMemcpyAsync(h, c.scal, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int fl = 0;
+    HIP_TRY(hipMemcpy(&fl, c.flags, sizeof fl, hipMemcpyDeviceToHost));
+    *d_min = h[0];
+    *d_max = h[1];
+    return fl ? RPY_ENONFINITE : RPY_OK;
+}
+
+static int forces(rpy_ctx *x, const double *pos, double zstar, double dstar, double rcut,
+                  double *F, hipStream_t s)
+{
+    Ctx &c = x->c;
+    launch_spring_forces(c, pos, F, s);
+    if (zstar > 0) {
+        const int nc = (int)floor(c.L / rcut);
+        c.ncell = nc >= 3 ? (nc > 64 ? 64 : nc) : 0;
+        launch_cell_list(c, rcut, s);
+        launch_ev_forces(c, zstar, dstar, rcut, F, s);
+    }
+    return RPY_OK;
+}
+
+static int check_ev(const Ctx &c, double zstar, double dstar, double rcut)
+{
+    if (zstar < 0 || !isfinite(zstar)) return RPY_EINVAL;
+    if (zstar > 0 && (!(dstar > 0) || !(rcut > 0) || !(rcut < 0.5 * c.L))) {
+        snprintf(g_err, sizeof g_err, "excluded volume needs d* > 0 and 0 < rcut < L/2");
+        return RPY_EINVAL;
+    }
+    return RPY_OK;
+}
+
+extern "C" int rpy_forces(rpy_ctx *x, const double *pos, double zstar, double dstar,
+                          double rcut, double *out, void *stream)
+{
+    if (!x || !pos || !out) return RPY_EINVAL;
+    int rc = check_ev(x->c, zstar, dstar, rcut);
+    if (rc) return rc;
+    hipStream_t s = S(stream);
+    if (zstar > 0) launch_wrap_tables(x->c, pos, s);
+    forces(x, pos, zstar, dstar, rcut, out, s);
+    return check_launch("rpy_forces");
+}
+
+extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const double *dw,
+                       uint64_t seed, uint64_t step, double *drift, double *noise,
+                       double *e_f, void *stream)
+{
+    if (!x || !pos || !bp) return RPY_EINVAL;
+    Ctx &c = x->c;
+    if (!(bp->dt > 0) || !isfinite(bp->dt) || bp->n_cheb < 2 || bp->n_cheb > MAX_NCHEB ||
+        !prec_ok(c, bp->prec))
+        return RPY_EINVAL;
+    if (bp->bounds_rule == RPY_BOUNDS_EXPLICIT) {
+        if (!(bp->d_min > 0) || !(bp->d_max > bp->d_min) || !isfinite(bp->d_max))
+            return RPY_EINVAL;
+    } else if (bp->bounds_rule == RPY_BOUNDS_PAPER) {
+        if (!(bp->bounds_C > 0)) return RPY_EINVAL;
+    } else {
+        return RPY_EINVAL;
+    }
+    int rc = check_ev(c, bp->ev_zstar, bp->ev_dstar, bp->ev_rcut);
+    if (rc) return rc;
+    hipStream_t s = S(stream);
+    const size_t nv = (size_t)c.n3;
+    launch_wrap_tables(c, pos, s);
+    forces(x, pos, bp->ev_zstar, bp->ev_dstar, bp->ev_rcut, x->F, s);
+    launch_build_tiles(c, s);
+    FinArgs f{};
+    f.mode = FIN_APPLY;
+    f.vout = x->Y;
+    if (bp->bounds_rule == RPY_BOUNDS_PAPER) {
+        f.m = 2;   // [F, U+] in one pass over D
+        product(x, x->F, 2, RPY_PREC_F64, f, s);
+        launch_cheb_coeffs(c, bp->n_cheb, RPY_BOUNDS_PAPER, bp->bounds_C, 0, 0, x->Y + nv, s);
+    } else {
+        f.m = 1;
+        product(x, x->F, 1, RPY_PREC_F64, f, s);
+        launch_cheb_coeffs(c, bp->n_cheb, RPY_BOUNDS_EXPLICIT, 0, bp->d_min, bp->d_max, nullptr,
+                           s);
+    }
+    const double *w = dw;
+    if (!w) {
+        launch_noise(x->dW, (int64_t)nv, seed, step, bp->dt, s);
+        w = x->dW;
+    }
+    cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s);
+    if (e_f) launch_sqrt_error(c, 1, w, x->ddw, x->dS, e_f, s);
+    if (drift) launch_copy(drift, x->Y, nv, s);
+    if (noise) launch_copy(noise, x->dS, nv, s);
+    launch_euler(c, pos, bp->dt, x->Y, x->dS, s);
+    return check_launch("bd_step");
+}
+
+extern "C" int rpy_status(rpy_ctx *x, void *stream)
+{
+    if (!x) return RPY_EINVAL;
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    int fl = 0;
+    HIP_TRY(hipMemcpy(&fl, x->c.flags, sizeof fl, hipMemcpyDeviceToHost));
+    if (fl) {
+        HIP_TRY(hipMemset(x->c.flags, 0, sizeof(int)));
+        snprintf(g_err, sizeof g_err, "non-finite position");
+        return RPY_ENONFINITE;
+    }
+    return RPY_OK;
+}
+
+extern "C" int rpy_real_space_dense(rpy_ctx *x, double *out, void *stream)
+{
+    if (!x || !out) return RPY_EINVAL;
+    launch_dense_copy(x->c, out, S(stream));
+    return check_launch("rpy_real_space_dense");
+}
+
+extern "C" int rpy_observables(rpy_ctx *x, const double *pos, double *re2, double *rg2,
+                               void *stream)
+{
+    if (!x || !pos || !re2 || !rg2) return RPY_EINVAL;
+    launch_observables(x->c, pos, re2, rg2, S(stream));
+    return check_launch("rpy_observables");
+}
+
+extern "C" int rpy_gaussian_noise(double *out, int64_t count, uint64_t seed, uint64_t step,
+                                  double dt, void *stream)
+{
+    if (!out || count < 0 || !(dt > 0)) return RPY_EINVAL;
+    launch_noise(out, count, seed, step, dt, S(stream));
+    return check_launch("rpy_gaussian_noise");
+}
+
+extern "C" int rpy_philox4x32_10(const uint32_t *ck, uint32_t *out, int64_t n, void *stream)
+{
+    if (!ck || !out || n < 0) return RPY_EINVAL;
+    launch_philox(ck, out, n, S(stream));
+    return check_launch("rpy_philox4x32_10");
+}
+
+extern "C" int rpy_host_pair_block(const rpy_params *p, const double *d, int self, double *out)
+{
+    int n2 = 0;
+    if (!d || !out) return RPY_EINVAL;
+    int rc = validate(p, &n2);
+    if (rc) return rc;
+    const PairConst pc = make_pair_const(p->box_l, p->a, p->alpha, p->r_c);
+    double b[6];
+    pair_block(d[0], d[1], d[2], self != 0, pc, b);
+    const double v[9] = {b[0], b[1], b[2], b[1], b[3], b[4], b[2], b[4], b[5]};
+    memcpy(out, v, sizeof v);
+    return RPY_OK;
+}
+
+extern "C" int rpy_num_kvectors(const rpy_ctx *x) { return x ? x->c.nk : -1; }
+
+extern "C" const char *rpy_strerror(int code)
+{
+    switch (code) {
+    case RPY_OK: return "ok";
+    case RPY_EINVAL: return g_err[0] ? g_err : "invalid argument";
+    case RPY_EGEOM: return "box too small for the bead radius (need 4a < L)";
+    case RPY_ENONFINITE: return "non-finite position";
+    case RPY_ETOL: return "square-root error estimate above tolerance";
+    case RPY_ENOMEM: return g_err[0] ? g_err : "device allocation failed";
+    case RPY_EHIP: return g_err[0] ? g_err : "HIP runtime error";
+    default: return "unknown error";
+    }
+}

@@ -1,0 +1,269 @@
+// rpy_internal.h -- internal declarations of librpy (gfx950).
+//
+// Storage of the real-space diffusion matrix: the 3N x 3N matrix is cut into
+// square tiles of TB = 64 beads (TS = 192 rows/columns).  Only the tiles
+// (I, J) with I <= J are stored (D is symmetric), each TS x TS row-major and
+// contiguous, in the order t = I*nbt - I*(I-1)/2 + (J - I).  Rows and columns
+// past 3N are zero.  A product y = D.x reads every stored tile once and
+// produces both A_IJ x_J (rows of I) and A_IJ^T x_I (rows of J); the partial
+// results land in part[K][j][row] so that row r of y is the fixed-order sum
+// over K of part[K][j][r] (K = the tile column the contribution came from).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rpy.h"
+
+#define RPY_HD __host__ __device__
+
+namespace rpy {
+
+constexpr int TB = 64;          // beads per tile side
+constexpr int TS = 3 * TB;      // matrix rows per tile side
+constexpr int TILE_ELEMS = TS * TS;
+constexpr int NSER = 20;        // terms of the small-r series of S(r)
+constexpr double XSER = 0.75;   // use the series for alpha*r below this
+constexpr int MAX_RHS = 16;
+constexpr int MAX_NCHEB = 512;
+
+// ---------------------------------------------------------------- pair terms
+// Constants of the real-space pair kernel.  Passed by value to kernels.
+struct PairConst {
+    double L, invL;
+    double a, alpha;
+    double rc, rc2;        // real-space cutoff
+    double reach;          // max(rc, 2a): images beyond it contribute nothing
+    double a2x4;           // (2a)^2
+    double self_coeff;     // 1 - 6 a al/sqrt(pi) + 40 a^3 al^3 / (3 sqrt(pi))
+    double A1, A3;         // a*alpha and (a*alpha)^3
+    double inv_sqrtpi;
+    double s1[NSER], s2[NSER];  // series of S1, S2 in (alpha r)^2
+};
+
+// Real-space Ewald kernel M1 (eq. M1) written in x = alpha r:
+//   c1 = erfc(x)(3a/4r + a^3/2r^3)
+//        + e^{-x^2}/sqrt(pi) [A1 (3x^2 - 9/2) + A3 (4x^4 - 20x^2 + 14 + 1/x^2)]
+//   c2 = erfc(x)(3a/4r - 3a^3/2r^3)
+//        + e^{-x^2}/sqrt(pi) [A1 (3/2 - 3x^2) + A3 (-4x^4 + 16x^2 - 2 - 3/x^2)]
+RPY_HD inline void m1_coeffs(double r, const PairConst &p, double &c1, double &c2)
+{
+    const double x = p.alpha * r;
+    const double x2 = x * x;
+    const double e = erfc(x);
+    const double g = exp(-x2) * p.inv_sqrtpi;
+    const double ar = p.a / r;
+    const double ar3 = ar * ar * ar;
+    const double ix2 = 1.0 / x2;
+    c1 = e * (0.75 * ar + 0.5 * ar3)
+       + g * (p.A1 * (3.0 * x2 - 4.5) + p.A3 * ((4.0 * x2 - 20.0) * x2 + 14.0 + ix2));
+    c2 = e * (0.75 * ar - 1.5 * ar3)
+       + g * (p.A1 * (1.5 - 3.0 * x2) + p.A3 * ((16.0 - 4.0 * x2) * x2 - 2.0 - 3.0 * ix2));
+}
+
+// Smooth part S = Omega_A - M1 (the piece the reciprocal sum carries), an
+// even entire function of x = alpha r.  For x < XSER its power series in x^2
+// (coefficients from the series of erf and exp, see make_pair_const); else
+//   S1 = A1 [3/4 erf(x)/x - (3x^2 - 9/2) e^{-x^2}/sqrt(pi)]
+//      + A3 [1/2 erf(x)/x^3 - (4x^4 - 20x^2 + 14 + 1/x^2) e^{-x^2}/sqrt(pi)]
+//   S2 = A1 [3/4 erf(x)/x - (3/2 - 3x^2) e^{-x^2}/sqrt(pi)]
+//      + A3 [-3/2 erf(x)/x^3 - (-4x^4 + 16x^2 - 2 - 3/x^2) e^{-x^2}/sqrt(pi)]
+RPY_HD inline void smooth_part(double x, const PairConst &p, double &s1, double &s2)
+{
+    const double x2 = x * x;
+    if (x < XSER) {
+        double u = p.s1[NSER - 1], v = p.s2[NSER - 1];
+        for (int n = NSER - 2; n >= 0; --n) {
+            u = u * x2 + p.s1[n];
+            v = v * x2 + p.s2[n];
+        }
+        s1 = u;
+        s2 = v;
+    } else {
+        const double ef = erf(x);
+        const double g = exp(-x2) * p.inv_sqrtpi;
+        const double ex1 = ef / x, ex3 = ef / (x * x2), ix2 = 1.0 / x2;
+        s1 = p.A1 * (0.75 * ex1 - (3.0 * x2 - 4.5) * g)
+           + p.A3 * (0.5 * ex3 - ((4.0 * x2 - 20.0) * x2 + 14.0 + ix2) * g);
+        s2 = p.A1 * (0.75 * ex1 - (1.5 - 3.0 * x2) * g)
+           + p.A3 * (-1.5 * ex3 - ((16.0 - 4.0 * x2) * x2 - 2.0 - 3.0 * ix2) * g);
+    }
+}
+
+// Contribution of one periodic image d of a pair to the symmetric 3x3
+// block b = {xx, xy, xz, yy, yz, zz}:
+//   |d| <= rc, |d| >= 2a : M1(d)
+//   |d| <= rc, |d| <  2a : M1 + M* = Omega_B - S   (stable at small r)
+//   |d| >  rc, |d| <  2a : M* = Omega_B - Omega_A  (eq. cor5)
+RPY_HD inline void add_image(double dx, double dy, double dz, const PairConst &p,
+                             double b[6])
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const bool in_rc = r2 <= p.rc2;
+    const bool ov = r2 < p.a2x4;
+    if (!in_rc && !ov) return;
+    const double r = sqrt(r2);
+    double c1, c2;
+    if (!ov) {
+        m1_coeffs(r, p, c1, c2);
+    } else {
+        const double xa = r / p.a;
+        const double ob1 = 1.0 - 0.28125 * xa;   // 9/32
+        const double ob2 = 0.09375 * xa;         // 3/32
+        if (in_rc) {
+            double s1, s2;
+            smooth_part(p.alpha * r, p, s1, s2);
+            c1 = ob1 - s1;
+            c2 = ob2 - s2;
+        } else {
+            const double ar = p.a / r, ar3 = ar * ar * ar;
+            c1 = ob1 - (0.75 * ar + 0.5 * ar3);
+            c2 = ob2 - (0.75 * ar - 1.5 * ar3);
+        }
+    }
+    b[0] += c1;
+    b[3] += c1;
+    b[5] += c1;
+    if (r2 > 0.0) {
+        const double w = c2 / r2;
+        b[0] += w * dx * dx;
+        b[1] += w * dx * dy;
+        b[2] += w * dx * dz;
+        b[3] += w * dy * dy;
+        b[4] += w * dy * dz;
+        b[5] += w * dz * dz;
+    }
+}
+
+RPY_HD inline int image_lo(double d, const PairConst &p)
+{
+    return (int)ceil((-p.reach - d) * p.invL - 1e-12);
+}
+RPY_HD inline int image_hi(double d, const PairConst &p)
+{
+    return (int)floor((p.reach - d) * p.invL + 1e-12);
+}
+
+// Sum over all periodic images of one pair with wrapped separation d0
+// (components in (-L, L)); for a bead with itself, the zero image is
+// omitted and the self term added (eq. DF, first term and primed sum).
+RPY_HD inline void pair_block(double d0x, double d0y, double d0z, bool self,
+                              const PairConst &p, double b[6])
+{
+    for (int k = 0; k < 6; ++k) b[k] = 0.0;
+    const int xl = image_lo(d0x, p), xh = image_hi(d0x, p);
+    const int yl = image_lo(d0y, p), yh = image_hi(d0y, p);
+    const int zl = image_lo(d0z, p), zh = image_hi(d0z, p);
+    for (int nx = xl; nx <= xh; ++nx) {
+        const double dx = d0x + nx * p.L;
+        for (int ny = yl; ny <= yh; ++ny) {
+            const double dy = d0y + ny * p.L;
+            for (int nz = zl; nz <= zh; ++nz) {
+                if (self && nx == 0 && ny == 0 && nz == 0) continue;
+                add_image(dx, dy, d0z + nz * p.L, p, b);
+            }
+        }
+    }
+    if (self) {
+        b[0] += p.self_coeff;
+        b[3] += p.self_coeff;
+        b[5] += p.self_coeff;
+    }
+}
+
+PairConst make_pair_const(double L, double a, double alpha, double rc);
+
+// --------------------------------------------------------------- k-space
+// Half-space wave-vector set: n with |n|^2 <= n2max and n > 0 in
+// lexicographic (x, y, z) order; each carries weight 2 m(k) (the +-k pair)
+// and khat.
+struct KVec {
+    int nx, ny, nz, pad;
+};
+struct KCoef {
+    double w;          // 2 m(k)
+    double hx, hy, hz; // khat
+};
+
+// -------------------------------------------------------------- context
+struct Ctx {
+    // problem
+    int N, n3, nchains, bpc;
+    double L, a, alpha, rc, kc;
+    int n2max, nmax;   // |n|^2 cutoff and max |component|
+    int nk;            // half-space wave vectors
+    int lowp, max_rhs;
+    int rhs_cap;       // stride of the per-RHS work buffers: max(max_rhs, 2)
+    PairConst pc;
+    // tiling
+    int nbt;           // bead tiles per side
+    int ntiles;        // stored tiles
+    int n3pad;         // nbt * TS
+    int nsfc;          // structure-factor bead chunks
+    // device buffers
+    double *rt = nullptr;        // wrapped positions [N][3]
+    double2 *etab = nullptr;     // phases [N][3][nmax+1]
+    KVec *kvec = nullptr;        // [nk]
+    KCoef *kcoef = nullptr;      // [nk]
+    int2 *tile_ij = nullptr;     // [ntiles]
+    double *d64 = nullptr;       // [ntiles][TS*TS]
+    float *d32 = nullptr;
+    uint16_t *d16 = nullptr;
+    double *part = nullptr;      // [nbt][max_rhs][n3pad]
+    double *sfpart = nullptr;    // [nsfc][nk][6*max_rhs]
+    double *tk = nullptr;        // [nk][6*max_rhs]
+    double *work = nullptr;      // vectors, see capi
+    double *scal = nullptr;      // scalars: [0]=dmin [1]=dmax [2]=ya [3]=yb [8..]=coeffs
+    double *red = nullptr;       // reduction outputs
+    int *flags = nullptr;        // [0] nonfinite
+    // cell list for excluded volume
+    int ncell;                   // cells per side (0: no cell list)
+    int *cell_start = nullptr;   // [ncell^3 + 1]
+    int *cell_beads = nullptr;   // [N]
+    size_t work_elems = 0;
+    double ev_rcut_built = 0.0;
+};
+
+// ------------------------------------------------------------ launchers
+// build
+void launch_wrap_tables(const Ctx &c, const double *pos, hipStream_t s);
+void launch_build_tiles(const Ctx &c, hipStream_t s);
+void launch_dense_copy(const Ctx &c, double *out, hipStream_t s);
+// products
+void launch_structure_factors(const Ctx &c, const double *v, int m, hipStream_t s);
+void launch_sf_reduce(const Ctx &c, int m, hipStream_t s);
+void launch_symv(const Ctx &c, int prec, const double *v, int m, hipStream_t s);
+// finalize modes
+enum FinMode { FIN_APPLY = 0, FIN_CHEB_FIRST = 1, FIN_CHEB_NEXT = 2 };
+struct FinArgs {
+    int mode;
+    int m;
+    int p;                 // Chebyshev index of the vector being produced
+    const double *vprev;   // V_{p-1} [m][3N]
+    const double *vprev2;  // V_{p-2}
+    double *vout;          // V_p, or D.v for FIN_APPLY
+    double *acc;           // sum c_p V_p
+    double *dv;            // optional: D.V_{p-1} copy (FIN_CHEB_FIRST)
+    const double *scal;    // device scalars (ya, yb, coeffs)
+};
+void launch_finalize(const Ctx &c, const FinArgs &f, hipStream_t s);
+void launch_cheb_coeffs(const Ctx &c, int n_cheb, int rule, double C, double dmin,
+                        double dmax, const double *du, hipStream_t s);
+void launch_sqrt_error(const Ctx &c, int m, const double *dw, const double *ddw,
+                       const double *ds, double *e_f, hipStream_t s);
+void launch_fill(double *p, double v, size_t n, hipStream_t s);
+void launch_copy(double *dst, const double *src, size_t n, hipStream_t s);
+// step
+void launch_spring_forces(const Ctx &c, const double *pos, double *F, hipStream_t s);
+void launch_cell_list(const Ctx &c, double rcut, hipStream_t s);
+void launch_ev_forces(const Ctx &c, double zstar, double dstar, double rcut, double *F,
+                      hipStream_t s);
+void launch_noise(double *out, int64_t count, uint64_t seed, uint64_t step, double dt,
+                  hipStream_t s);
+void launch_philox(const uint32_t *ck, uint32_t *out, int64_t n, hipStream_t s);
+void launch_euler(const Ctx &c, double *pos, double dt, const double *ud,
+                  const double *ds, hipStream_t s);
+void launch_observables(const Ctx &c, const double *pos, double *re2, double *rg2,
+                        hipStream_t s);
+
+}  // namespace rpy

@@ -1,0 +1,298 @@
+// rpy_step.hip -- forces, noise, Euler update and chain observables of the
+// Brownian-dynamics step (arXiv:1203.6208, section "Governing equation" and
+// section "Testing and verification").
+#include "rpy_internal.h"
+
+namespace rpy {
+
+// Hookean springs: F_mu = Q_mu - Q_{mu-1}, Q_mu = r_{mu+1} - r_mu within a
+// chain (unwrapped positions).  Overwrites F.
+__global__ void k_springs(int N, int bpc, const double *__restrict__ pos, double *__restrict__ F)
+{
+    const int mu = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mu >= N) return;
+    const int b = mu % bpc;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double f = 0.0;
+        if (b + 1 < bpc) f += pos[3 * (mu + 1) + i] - pos[3 * mu + i];
+        if (b > 0) f -= pos[3 * mu + i] - pos[3 * (mu - 1) + i];
+        F[3 * mu + i] = f;
+    }
+}
+
+void launch_spring_forces(const Ctx &c, const double *pos, double *F, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_springs, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, c.bpc, pos, F);
+}
+
+// --------------------------------------------------------------- cell list
+// Cells of side >= rcut (ncell per axis, at least 3 so the 27-cell stencil
+// visits distinct cells); beads sorted by cell, by index inside a cell.
+__device__ inline int cell_of(const double *rt, int nu, double L, int nc)
+{
+    int cx = (int)(rt[3 * nu] / L * nc), cy = (int)(rt[3 * nu + 1] / L * nc),
+        cz = (int)(rt[3 * nu + 2] / L * nc);
+    cx = min(max(cx, 0), nc - 1);
+    cy = min(max(cy, 0), nc - 1);
+    cz = min(max(cz, 0), nc - 1);
+    return (cz * nc + cy) * nc + cx;
+}
+
+__global__ void k_cell_zero(int n, int *a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
+__global__ void k_cell_count(int N, double L, int nc, const double *__restrict__ rt, int *count)
+{
+    const int nu = blockIdx.x * blockDim.x + threadIdx.x;
+    if (nu >= N) return;
+    atomicAdd(&count[cell_of(rt, nu, L, nc)], 1);
+}
+
+// Exclusive scan of the counts (one workgroup), start[ncells] = N; the
+// counts are reset to serve as insertion cursors.
+__global__ __launch_bounds__(1024) void k_cell_scan(int ncells, int *count, int *start)
+{
+    __shared__ int part[1024];
+    const int tid = threadIdx.x;
+    const int per = (ncells + 1023) / 1024;
+    const int lo = min(tid * per, ncells), hi = min(lo + per, ncells);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += count[i];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int i = 0; i < 1024; ++i) {
+            const int t = part[i];
+            part[i] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    int run = part[tid];
+    for (int i = lo; i < hi; ++i) {
+        start[i] = run;
+        run += count[i];
+        count[i] = 0;
+    }
+    if (tid == 1023) start[ncells] = run;
+}
+
+__global__ void k_cell_fill(int N, double L, int nc, const double *__restrict__ rt,
+                            const int *__restrict__ start, int *cursor, int *beads)
+{
+    const int nu = blockIdx.x * blockDim.x + threadIdx.x;
+    if (nu >= N) return;
+    const int c = cell_of(rt, nu, L, nc);
+    const int slot = atomicAdd(&cursor[c], 1);
+    beads[start[c] + slot] = nu;
+}
+
+// insertion sort of each cell's bead list (deterministic summation order)
+__global__ void k_cell_sort(int ncells, const int *__restrict__ start, int *beads)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const int lo = start[c], hi = start[c + 1];
+    for (int i = lo + 1; i < hi; ++i) {
+        const int v = beads[i];
+        int j = i - 1;
+        while (j >= lo && beads[j] > v) {
+            beads[j + 1] = beads[j];
+            --j;
+        }
+        beads[j + 1] = v;
+    }
+}
+
+void launch_cell_list(const Ctx &c, double rcut, hipStream_t s)
+{
+    (void)rcut;
+    const int nc = c.ncell;
+    if (nc < 3) return;
+    const int ncells = nc * nc * nc;
+    int *count = reinterpret_cast<int *>(c.cell_start) + ncells + 1;  // cursor area
+    hipLaunchKernelGGL(k_cell_zero, dim3((ncells + 255) / 256), dim3(256), 0, s, ncells, count);
+    hipLaunchKernelGGL(k_cell_count, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, c.L, nc, c.rt,
+                       count);
+    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, ncells, count, c.cell_start);
+    hipLaunchKernelGGL(k_cell_fill, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, c.L, nc, c.rt,
+                       c.cell_start, count, c.cell_beads);
+    hipLaunchKernelGGL(k_cell_sort, dim3((ncells + 255) / 256), dim3(256), 0, s, ncells,
+                       c.cell_start, c.cell_beads);
+}
+
+// Narrow-Gaussian excluded volume, minimum image (rcut < L/2):
+//   F_nu += (z*/d*^5) d exp(-|d|^2 / (2 d*^2)), d = r_nu - r_mu, |d| <= rcut.
+__global__ void k_ev_forces(int N, double L, int nc, const double *__restrict__ rt,
+                            const int *__restrict__ start, const int *__restrict__ beads,
+                            double pref, double inv2d2, double rcut2, double *__restrict__ F)
+{
+    const int nu = blockIdx.x * blockDim.x + threadIdx.x;
+    if (nu >= N) return;
+    const double x = rt[3 * nu], y = rt[3 * nu + 1], z = rt[3 * nu + 2];
+    const double invL = 1.0 / L;
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    auto visit = [&](int mu) {
+        if (mu == nu) return;
+        double dx = x - rt[3 * mu], dy = y - rt[3 * mu + 1], dz = z - rt[3 * mu + 2];
+        dx -= L * rint(dx * invL);
+        dy -= L * rint(dy * invL);
+        dz -= L * rint(dz * invL);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 > rcut2) return;
+        const double w = pref * exp(-r2 * inv2d2);
+        f0 += w * dx;
+        f1 += w * dy;
+        f2 += w * dz;
+    };
+    if (nc >= 3) {
+        const int c = cell_of(rt, nu, L, nc);
+        const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+        for (int oz = -1; oz <= 1; ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const int ex = (cx + ox + nc) % nc, ey = (cy + oy + nc) % nc,
+                              ez = (cz + oz + nc) % nc;
+                    const int cc = (ez * nc + ey) * nc + ex;
+                    for (int i = start[cc]; i < start[cc + 1]; ++i) visit(beads[i]);
+                }
+    } else {
+        for (int mu = 0; mu < N; ++mu) visit(mu);
+    }
+    F[3 * nu] += f0;
+    F[3 * nu + 1] += f1;
+    F[3 * nu + 2] += f2;
+}
+
+void launch_ev_forces(const Ctx &c, double zstar, double dstar, double rcut, double *F,
+                      hipStream_t s)
+{
+    const double d2 = dstar * dstar;
+    const double pref = zstar / (d2 * d2 * dstar);
+    hipLaunchKernelGGL(k_ev_forces, dim3((c.N + 127) / 128), dim3(128), 0, s, c.N, c.L, c.ncell,
+                       c.rt, c.cell_start, c.cell_beads, pref, 1.0 / (2.0 * d2), rcut * rcut, F);
+}
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): round function
+// (c0,c1,c2,c3) -> (hi(B c2) ^ c1 ^ k0, lo(B c2), hi(A c0) ^ c3 ^ k1, lo(A c0))
+// with A = 0xD2511F53, B = 0xCD9E8D57, key bumped by (0x9E3779B9, 0xBB67AE85).
+__device__ inline uint4 philox10(uint4 c, uint2 k)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__global__ void k_philox(const uint32_t *__restrict__ ck, uint32_t *__restrict__ out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t *p = ck + 6 * i;
+    const uint4 r = philox10(make_uint4(p[0], p[1], p[2], p[3]), make_uint2(p[4], p[5]));
+    out[4 * i] = r.x;
+    out[4 * i + 1] = r.y;
+    out[4 * i + 2] = r.z;
+    out[4 * i + 3] = r.w;
+}
+
+void launch_philox(const uint32_t *ck, uint32_t *out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ck, out, n);
+}
+
+// Gaussian noise: element e uses block g = e/4, counter (g, step lo, step hi,
+// 0x52505942), key (seed lo, seed hi); u = (x + 1/2) 2^-32; Box-Muller
+// z0 = rho cos(2 pi u1), z1 = rho sin(2 pi u1), rho = sqrt(-2 ln u0), z2/z3
+// from (u2, u3).  Scaled by sqrt(dt).
+__global__ void k_noise(double *__restrict__ out, int64_t count, uint64_t seed, uint64_t step,
+                        double sdt)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (4 * g >= count) return;
+    const uint4 x = philox10(make_uint4((uint32_t)g, (uint32_t)step, (uint32_t)(step >> 32),
+                                        0x52505942u),
+                             make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+    const double k = 1.0 / 4294967296.0;
+    const double u0 = ((double)x.x + 0.5) * k, u1 = ((double)x.y + 0.5) * k;
+    const double u2 = ((double)x.z + 0.5) * k, u3 = ((double)x.w + 0.5) * k;
+    const double rho0 = sqrt(-2.0 * log(u0)), rho1 = sqrt(-2.0 * log(u2));
+    double s1, c1, s3, c3;
+    sincospi(2.0 * u1, &s1, &c1);
+    sincospi(2.0 * u3, &s3, &c3);
+    const double z[4] = {rho0 * c1, rho0 * s1, rho1 * c3, rho1 * s3};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (4 * g + j < count) out[4 * g + j] = z[j] * sdt;
+}
+
+void launch_noise(double *out, int64_t count, uint64_t seed, uint64_t step, double dt,
+                  hipStream_t s)
+{
+    const int64_t ng = (count + 3) / 4;
+    hipLaunchKernelGGL(k_noise, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, out, count,
+                       seed, step, sqrt(dt));
+}
+
+// Euler-Maruyama update r += (dt/4) D.F + dS/sqrt(2) (eq. sde, kappa = 0).
+__global__ void k_euler(int n3, double *__restrict__ pos, double dt4,
+                        const double *__restrict__ ud, const double *__restrict__ ds)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    pos[i] = pos[i] + dt4 * ud[i] + ds[i] / 1.4142135623730951;
+}
+
+void launch_euler(const Ctx &c, double *pos, double dt, const double *ud, const double *ds,
+                  hipStream_t s)
+{
+    hipLaunchKernelGGL(k_euler, dim3((c.n3 + 255) / 256), dim3(256), 0, s, c.n3, pos, dt / 4.0,
+                       ud, ds);
+}
+
+// One thread per chain: R_e^2 and R_g^2 = mean |r - r_cm|^2.
+__global__ void k_observables(int nchains, int bpc, const double *__restrict__ pos,
+                              double *__restrict__ re2, double *__restrict__ rg2)
+{
+    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= nchains) return;
+    const double *x = pos + (size_t)3 * ch * bpc;
+    double cm[3] = {0, 0, 0};
+    for (int b = 0; b < bpc; ++b)
+        for (int i = 0; i < 3; ++i) cm[i] += x[3 * b + i];
+    for (int i = 0; i < 3; ++i) cm[i] /= bpc;
+    double g = 0.0;
+    for (int b = 0; b < bpc; ++b)
+        for (int i = 0; i < 3; ++i) {
+            const double d = x[3 * b + i] - cm[i];
+            g += d * d;
+        }
+    double e = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double d = x[3 * (bpc - 1) + i] - x[i];
+        e += d * d;
+    }
+    re2[ch] = e;
+    rg2[ch] = g / bpc;
+}
+
+void launch_observables(const Ctx &c, const double *pos, double *re2, double *rg2,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_observables, dim3((c.nchains + 127) / 128), dim3(128), 0, s, c.nchains,
+                       c.bpc, pos, re2, rg2);
+}
+
+}  // namespace rpy

@@ -1,0 +1,272 @@
+"""Thin ctypes binding of ``librpy.so`` (declared in ``include/rpy.h``).
+
+Argument marshalling only: every entry point forwards torch tensors' device
+pointers and the current HIP stream to the C ABI of the same name.  All
+computation happens in the HIP kernels of the library.  Importing this module
+raises if the library has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpy.so")
+
+RPY_OK, RPY_EINVAL, RPY_EGEOM, RPY_ENONFINITE, RPY_ETOL, RPY_ENOMEM, RPY_EHIP = 0, -1, -2, -3, -4, -5, -6
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+BOUNDS_EXPLICIT, BOUNDS_PAPER = 0, 1
+
+
+class RpyError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what} failed with {code}: {rpy_strerror(code)}")
+        self.code = code
+
+
+class RpyParams(ctypes.Structure):
+    _fields_ = [("n_beads", ctypes.c_int32), ("n_chains", ctypes.c_int32),
+                ("beads_per_chain", ctypes.c_int32), ("lowp", ctypes.c_int32),
+                ("max_rhs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("box_l", ctypes.c_double), ("a", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("r_c", ctypes.c_double),
+                ("k_c", ctypes.c_double)]
+
+
+class BdParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("ev_zstar", ctypes.c_double),
+                ("ev_dstar", ctypes.c_double), ("ev_rcut", ctypes.c_double),
+                ("bounds_C", ctypes.c_double), ("d_min", ctypes.c_double),
+                ("d_max", ctypes.c_double), ("n_cheb", ctypes.c_int32),
+                ("bounds_rule", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_v = ctypes.c_void_p
+_d = ctypes.c_double
+_i = ctypes.c_int
+_P = ctypes.POINTER
+_SIG = {
+    "rpy_create": (_i, [_P(_v), _P(RpyParams)]),
+    "rpy_destroy": (None, [_v]),
+    "rpy_ewald_build": (_i, [_v, _v, _v]),
+    "rpy_apply": (_i, [_v, _v, _v, _i, _i, _v]),
+    "rpy_bounds": (_i, [_v, _d, _P(_d), _P(_d), _v]),
+    "chebyshev_sqrt_apply": (_i, [_v, _v, _v, _i, _i, _d, _d, _i, _v, _v]),
+    "bd_step": (_i, [_v, _v, _P(BdParams), _v, ctypes.c_uint64, ctypes.c_uint64, _v, _v, _v, _v]),
+    "rpy_status": (_i, [_v, _v]),
+    "rpy_real_space_dense": (_i, [_v, _v, _v]),
+    "rpy_observables": (_i, [_v, _v, _v, _v, _v]),
+    "rpy_forces": (_i, [_v, _v, _d, _d, _d, _v, _v]),
+    "rpy_gaussian_noise": (_i, [_v, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, _d, _v]),
+    "rpy_philox4x32_10": (_i, [_v, _v, ctypes.c_int64, _v]),
+    "rpy_host_pair_block": (_i, [_P(RpyParams), _P(_d), _i, _P(_d)]),
+    "rpy_num_kvectors": (_i, [_v]),
+    "rpy_strerror": (ctypes.c_char_p, [_i]),
+}
+for _name, (_res, _args) in _SIG.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtype=torch.float64):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name}: need a contiguous {dtype} tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(code: int, what: str):
+    if code != RPY_OK:
+        raise RpyError(code, what)
+
+
+def rpy_strerror(code: int) -> str:
+    return _lib.rpy_strerror(int(code)).decode()
+
+
+def make_params(*, n_beads, n_chains, beads_per_chain, box_l, a, alpha, r_c, k_c,
+                lowp="f64", max_rhs=1) -> RpyParams:
+    return RpyParams(int(n_beads), int(n_chains), int(beads_per_chain), PREC[lowp],
+                     int(max_rhs), 0, float(box_l), float(a), float(alpha), float(r_c),
+                     float(k_c))
+
+
+def rpy_create(params: RpyParams) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(_lib.rpy_create(ctypes.byref(h), ctypes.byref(params)), "rpy_create")
+    return h
+
+
+def rpy_destroy(ctx) -> None:
+    _lib.rpy_destroy(ctx)
+
+
+def rpy_ewald_build(ctx, pos: torch.Tensor, stream=None) -> None:
+    _check(_lib.rpy_ewald_build(ctx, _dev(pos, "pos"), _stream(stream)), "rpy_ewald_build")
+
+
+def rpy_apply(ctx, v: torch.Tensor, out: torch.Tensor, m: int, prec="f64", stream=None):
+    _check(_lib.rpy_apply(ctx, _dev(v, "v"), _dev(out, "out"), int(m), PREC[prec],
+                          _stream(stream)), "rpy_apply")
+    return out
+
+
+def rpy_bounds(ctx, C: float, stream=None):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.rpy_bounds(ctx, float(C), ctypes.byref(lo), ctypes.byref(hi), _stream(stream)),
+           "rpy_bounds")
+    return lo.value, hi.value
+
+
+def chebyshev_sqrt_apply(ctx, dw: torch.Tensor, out: torch.Tensor, m: int, n_cheb: int,
+                         d_min: float, d_max: float, prec="f64", e_f: torch.Tensor = None,
+                         stream=None):
+    _check(_lib.chebyshev_sqrt_apply(ctx, _dev(dw, "dw"), _dev(out, "out"), int(m), int(n_cheb),
+                                     float(d_min), float(d_max), PREC[prec], _dev(e_f, "e_f"),
+                                     _stream(stream)), "chebyshev_sqrt_apply")
+    return out
+
+
+def make_bd_params(*, dt, n_cheb, bounds_rule=BOUNDS_EXPLICIT, d_min=0.0, d_max=0.0,
+                   bounds_C=8.0, prec="f64", ev=None) -> BdParams:
+    ev = ev or {}
+    return BdParams(float(dt), float(ev.get("zstar", 0.0)), float(ev.get("dstar", 0.0)),
+                    float(ev.get("rcut", 0.0)), float(bounds_C), float(d_min), float(d_max),
+                    int(n_cheb), int(bounds_rule), PREC[prec], 0)
+
+
+def bd_step(ctx, pos: torch.Tensor, bp: BdParams, dw: torch.Tensor = None, seed: int = 0,
+            step: int = 0, drift: torch.Tensor = None, noise: torch.Tensor = None,
+            e_f: torch.Tensor = None, stream=None) -> None:
+    _check(_lib.bd_step(ctx, _dev(pos, "pos"), ctypes.byref(bp), _dev(dw, "dw"),
+                        ctypes.c_uint64(seed), ctypes.c_uint64(step), _dev(drift, "drift"),
+                        _dev(noise, "noise"), _dev(e_f, "e_f"), _stream(stream)), "bd_step")
+
+
+def rpy_status(ctx, stream=None) -> int:
+    return _lib.rpy_status(ctx, _stream(stream))
+
+
+def rpy_real_space_dense(ctx, out: torch.Tensor, stream=None):
+    _check(_lib.rpy_real_space_dense(ctx, _dev(out, "out"), _stream(stream)),
+           "rpy_real_space_dense")
+    return out
+
+
+def rpy_observables(ctx, pos, re2, rg2, stream=None):
+    _check(_lib.rpy_observables(ctx, _dev(pos, "pos"), _dev(re2, "re2"), _dev(rg2, "rg2"),
+                                _stream(stream)), "rpy_observables")
+
+
+def rpy_forces(ctx, pos, zstar, dstar, rcut, out, stream=None):
+    _check(_lib.rpy_forces(ctx, _dev(pos, "pos"), float(zstar), float(dstar), float(rcut),
+                           _dev(out, "out"), _stream(stream)), "rpy_forces")
+    return out
+
+
+def rpy_gaussian_noise(out: torch.Tensor, seed: int, step: int, dt: float, stream=None):
+    _check(_lib.rpy_gaussian_noise(_dev(out, "out"), out.numel(), ctypes.c_uint64(seed),
+                                   ctypes.c_uint64(step), float(dt), _stream(stream)),
+           "rpy_gaussian_noise")
+    return out
+
+
+def rpy_philox4x32_10(ctr_key: torch.Tensor, out: torch.Tensor, stream=None):
+    n = ctr_key.numel() // 6
+    _check(_lib.rpy_philox4x32_10(_dev(ctr_key, "ctr_key", torch.int32), _dev(out, "out", torch.int32),
+                                  n, _stream(stream)), "rpy_philox4x32_10")
+    return out
+
+
+def rpy_host_pair_block(params: RpyParams, d, self_pair: bool):
+    dd = (ctypes.c_double * 3)(*[float(x) for x in d])
+    out = (ctypes.c_double * 9)()
+    _check(_lib.rpy_host_pair_block(ctypes.byref(params), dd, int(bool(self_pair)), out),
+           "rpy_host_pair_block")
+    return [out[i] for i in range(9)]
+
+
+def rpy_num_kvectors(ctx) -> int:
+    return _lib.rpy_num_kvectors(ctx)
+
+
+class Context:
+    """Owns one rpy_ctx; methods forward to the entry points above."""
+
+    def __init__(self, **kw):
+        self.params = make_params(**kw)
+        self.n = self.params.n_beads
+        self.handle = rpy_create(self.params)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            rpy_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build(self, pos, stream=None):
+        rpy_ewald_build(self.handle, pos, stream)
+
+    def apply(self, v, prec="f64", stream=None):
+        v = v.reshape(-1, self.n, 3).contiguous()
+        out = torch.empty_like(v)
+        rpy_apply(self.handle, v, out, v.shape[0], prec, stream)
+        return out
+
+    def sqrt_apply(self, dw, n_cheb, d_min, d_max, prec="f64", want_ef=False, stream=None):
+        dw = dw.reshape(-1, self.n, 3).contiguous()
+        out = torch.empty_like(dw)
+        ef = torch.empty(dw.shape[0], dtype=torch.float64, device=dw.device) if want_ef else None
+        chebyshev_sqrt_apply(self.handle, dw, out, dw.shape[0], n_cheb, d_min, d_max, prec, ef,
+                             stream)
+        return (out, ef) if want_ef else out
+
+    def bounds(self, C, stream=None):
+        return rpy_bounds(self.handle, C, stream)
+
+    def real_space_dense(self, stream=None):
+        out = torch.empty((3 * self.n, 3 * self.n), dtype=torch.float64, device="cuda")
+        return rpy_real_space_dense(self.handle, out, stream)
+
+    def step(self, pos, bp, dw=None, seed=0, step=0, want=False, stream=None):
+        drift = noise = ef = None
+        if want:
+            drift = torch.empty_like(pos)
+            noise = torch.empty_like(pos)
+            ef = torch.empty(1, dtype=torch.float64, device=pos.device)
+        bd_step(self.handle, pos, bp, dw, seed, step, drift, noise, ef, stream)
+        return (drift, noise, ef) if want else None
+
+    def status(self, stream=None):
+        return rpy_status(self.handle, stream)
+
+    def num_kvectors(self):
+        return rpy_num_kvectors(self.handle)
+
+
+def context_for(workload, lowp="f64", max_rhs=1) -> Context:
+    """Context for an ``inputs.Workload``."""
+    return Context(n_beads=workload.n, n_chains=workload.nchains,
+                   beads_per_chain=workload.bpc, box_l=workload.L, a=workload.a,
+                   alpha=workload.alpha, r_c=workload.rc, k_c=workload.kc, lowp=lowp,
+                   max_rhs=max_rhs)

@@ -1,0 +1,320 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs (arXiv:1203.6208).  FP64 forms must agree to rel 1e-12
+(norm-wise over the compared block); see each test for what is compared.
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1203_6208_amd import inputs  # noqa: E402
+from paper_1203_6208_amd import rpy  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+TOL = 1e-12
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _cuda(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+@pytest.fixture(scope="module")
+def n100(orc):
+    w = inputs.workload("n100")
+    pos = w.positions()
+    D = orc.diffusion_matrix(pos, w.L, w.a, w.alpha, w.rc, w.n2max)
+    Drs = orc.real_space_matrix(pos, w.L, w.a, w.alpha, w.rc)
+    return w, pos, D, Drs
+
+
+def test_philox_known_answers():
+    _say("philox KAT")
+    vec = json.load(open(os.path.join(GOLD, "philox_kat.json")))["vectors"]
+    ck = np.array([[int(x, 16) for x in v["ctr"] + v["key"]] for v in vec], dtype=np.uint32)
+    t = torch.from_numpy(ck.view(np.int32)).cuda()
+    out = torch.empty((len(vec), 4), dtype=torch.int32, device="cuda")
+    rpy.rpy_philox4x32_10(t, out)
+    got = out.cpu().numpy().view(np.uint32)
+    want = np.array([[int(x, 16) for x in v["out"]] for v in vec], dtype=np.uint32)
+    assert (got == want).all()
+
+
+def test_noise_matches_oracle(orc):
+    _say("noise")
+    for count in (12, 301, 30000):
+        out = torch.empty(count, dtype=torch.float64, device="cuda")
+        rpy.rpy_gaussian_noise(out, seed=123456789012, step=7, dt=1e-3)
+        ref = orc.gaussian_noise(count, 123456789012, 7, 1e-3)
+        assert _rel(out.cpu().numpy(), ref) < 1e-13
+
+
+def test_build_real_space_n100(n100):
+    """Stored real-space part (self + M1 lattice sum + overlap terms) equals the
+    oracle element by element (N = 100: two tiles, ragged tail)."""
+    _say("build n100")
+    w, pos, D, Drs = n100
+    ctx = rpy.context_for(w)
+    ctx.build(_cuda(pos))
+    got = ctx.real_space_dense().cpu().numpy()
+    assert _rel(got, Drs) < TOL
+
+
+def _adversarial(L, a, n=70, seed=1):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, L, (n, 3))
+    pos[1] = pos[0]                                    # coincident
+    pos[3] = pos[2] + np.array([1e-9, 0, 0])           # nearly coincident
+    pos[5] = pos[4] + 2 * a * (1 - 1e-9) * np.array([0.6, 0.8, 0])  # inside contact
+    pos[7] = pos[6] + 2 * a * (1 + 1e-9) * np.array([0, 0.6, 0.8])  # outside contact
+    pos[9] = pos[8] + np.array([0.0, 0.0, L - 0.3 * a])  # overlap across the boundary
+    pos[11] = pos[10] + np.array([0.5 * L, 0.5 * L, 0.5 * L])  # farthest
+    pos[12] = np.array([0.0, 0.0, 0.0])                # on the box corner
+    pos[13] = np.array([L, L, L]) * (1 - 1e-16)        # wraps to just inside
+    pos[20:] += rng.integers(-3, 4, size=(n - 20, 3)) * L  # unwrapped images
+    return pos
+
+
+@pytest.mark.parametrize("alphaL", [6.0, 3.0])
+def test_build_adversarial(orc, alphaL):
+    """Coincident and nearly coincident beads, pairs at 2a(1 -+ 1e-9), overlap
+    through the periodic boundary, positions on the box faces and far
+    outside the box, N = 70 (a full tile plus a ragged one)."""
+    _say(f"build adversarial alphaL={alphaL}")
+    w = inputs.workload("n100")
+    L, a = w.L, w.a
+    al = alphaL / L
+    rc = 3.5 / al
+    kc = 2 * al * 3.5
+    pos = _adversarial(L, a)
+    n = pos.shape[0]
+    ctx = rpy.Context(n_beads=n, n_chains=7, beads_per_chain=10, box_l=L, a=a, alpha=al, r_c=rc,
+                      k_c=kc, max_rhs=2)
+    ctx.build(_cuda(pos))
+    got = ctx.real_space_dense().cpu().numpy()
+    ref = orc.real_space_matrix(pos, L, a, al, rc)
+    assert _rel(got, ref) < TOL
+    n2 = inputs.wavevector_cutoff(kc, L)
+    Dfull = ref + orc.recip_space_matrix(pos, L, a, al, n2)
+    v = np.random.default_rng(3).standard_normal((2, n, 3))
+    out = ctx.apply(_cuda(v)).cpu().numpy()
+    assert _rel(out.reshape(2, -1), orc.matvec(Dfull, v.reshape(2, -1))) < TOL
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5])
+def test_apply_n100(n100, m):
+    """D.v with the reciprocal sum applied per product, m right-hand sides
+    (chunked 4 + 1 for m = 5)."""
+    _say(f"apply n100 m={m}")
+    w, pos, D, _ = n100
+    ctx = rpy.context_for(w, max_rhs=8)
+    ctx.build(_cuda(pos))
+    v = np.random.default_rng(m).standard_normal((m, w.n, 3))
+    out = ctx.apply(_cuda(v)).cpu().numpy()
+    ref = np.asarray(orc_matvec(D, v))
+    assert _rel(out.reshape(m, -1), ref) < TOL
+
+
+def orc_matvec(D, v):
+    import oracle
+    return oracle.matvec(D, v.reshape(v.shape[0], -1))
+
+
+def test_kvector_count(n100):
+    w = n100[0]
+    ctx = rpy.context_for(w)
+    assert ctx.num_kvectors() == 618
+
+
+def test_cheb_n100(n100, orc):
+    """Fixman-Chebyshev dS for 3 noise vectors, N_Ch = 20, bounds bracketing
+    the exact spectrum; and E_f."""
+    _say("cheb n100")
+    w, pos, D, _ = n100
+    lam = np.linalg.eigvalsh(D)
+    lo, hi = 0.9 * lam[0], 1.1 * lam[-1]
+    ctx = rpy.context_for(w, max_rhs=4)
+    ctx.build(_cuda(pos))
+    dw = w.noise(m=3)
+    out, ef = ctx.sqrt_apply(_cuda(dw), 20, lo, hi, want_ef=True)
+    ref = orc.cheb_sqrt(D, dw.reshape(3, -1), 20, lo, hi)
+    assert _rel(out.cpu().numpy().reshape(3, -1), ref) < TOL
+    for j in range(3):
+        e_ref = orc.sqrt_error(D, dw[j].ravel(), ref[j])
+        # E_f^2 is a difference of two O(1) dot products: compare it absolutely
+        assert abs(ef[j].item() ** 2 - e_ref ** 2) < 1e-12
+
+
+def test_bounds_rule_n100(n100, orc):
+    w, pos, D, _ = n100
+    ctx = rpy.context_for(w)
+    ctx.build(_cuda(pos))
+    lo, hi = ctx.bounds(8.0)
+    rlo, rhi = orc.bounds_rule(D, w.n, 8.0)
+    assert abs(lo - rlo) < TOL * rlo and abs(hi - rhi) < TOL * rhi
+
+
+@pytest.mark.parametrize("rule", ["explicit", "paper"])
+def test_bd_steps_n100(orc, rule):
+    """Ten Euler steps with host-drawn noise; positions, drift and dS after
+    every step against the oracle trajectory."""
+    _say(f"bd steps n100 {rule}")
+    w = inputs.workload("n100")
+    pos = w.positions()
+    ctx = rpy.context_for(w)
+    tpos = _cuda(pos)
+    kw = dict(dt=w.dt, n_cheb=w.nch)
+    okw = dict(nchains=w.nchains, bpc=w.bpc, L=w.L, a=w.a, alpha=w.alpha, rc=w.rc,
+               n2max=w.n2max, dt=w.dt, nch=w.nch)
+    if rule == "explicit":
+        kw.update(bounds_rule=rpy.BOUNDS_EXPLICIT, d_min=0.05, d_max=6.0)
+        okw.update(dmin=0.05, dmax=6.0)
+    else:
+        kw.update(bounds_rule=rpy.BOUNDS_PAPER, bounds_C=8.0)
+        okw.update(bounds_C=8.0)
+    bp = rpy.make_bd_params(**kw)
+    for step in range(10):
+        dw = w.noise(seed=5000 + step)[0]
+        drift, noise, ef = ctx.step(tpos, bp, dw=_cuda(dw), want=True)
+        ref = orc.bd_step(pos, dw=dw, **okw)
+        assert _rel(drift.cpu().numpy(), ref["drift"]) < TOL
+        assert _rel(noise.cpu().numpy(), ref["ds"]) < TOL
+        assert _rel(tpos.cpu().numpy(), ref["pos"]) < TOL
+        assert abs(ef.item() ** 2 - ref["ef"] ** 2) < 1e-12
+        pos = ref["pos"]
+    assert ctx.status() == 0
+
+
+def test_bd_step_device_noise(orc):
+    """bd_step drawing its own Philox noise matches the oracle's generator."""
+    _say("bd step device noise")
+    w = inputs.workload("n100")
+    pos = w.positions()
+    ctx = rpy.context_for(w)
+    tpos = _cuda(pos)
+    bp = rpy.make_bd_params(dt=w.dt, n_cheb=w.nch, d_min=0.05, d_max=6.0)
+    for step in range(3):
+        ctx.step(tpos, bp, seed=99, step=step)
+        pos = orc.bd_step(pos, nchains=w.nchains, bpc=w.bpc, L=w.L, a=w.a, alpha=w.alpha,
+                          rc=w.rc, n2max=w.n2max, dt=w.dt, nch=w.nch, dmin=0.05, dmax=6.0,
+                          seed=99, step=step)["pos"]
+        assert _rel(tpos.cpu().numpy(), pos) < TOL
+
+
+def test_forces_with_excluded_volume(orc):
+    """Springs plus narrow-Gaussian EV (cell list, 27-cell stencil) for the
+    N = 4000 geometry; compared with the oracle's all-images sum."""
+    _say("forces ev n4000")
+    w = inputs.workload("n4000")
+    pos = w.positions()
+    ctx = rpy.context_for(w)
+    ev = w.ev
+    out = torch.empty((w.n, 3), dtype=torch.float64, device="cuda")
+    rpy.rpy_forces(ctx.handle, _cuda(pos), ev["zstar"], ev["dstar"], ev["rcut"], out)
+    ref = orc.spring_forces(pos, w.nchains, w.bpc) + orc.ev_forces(
+        pos, w.L, ev["zstar"], ev["dstar"], ev["rcut"])
+    assert _rel(out.cpu().numpy(), ref) < TOL
+
+
+def test_observables(orc):
+    w = inputs.workload("n1000")
+    pos = w.positions()
+    ctx = rpy.context_for(w)
+    re2 = torch.empty(w.nchains, dtype=torch.float64, device="cuda")
+    rg2 = torch.empty_like(re2)
+    rpy.rpy_observables(ctx.handle, _cuda(pos), re2, rg2)
+    r_re, r_rg = orc.chain_observables(pos, w.nchains, w.bpc)
+    assert _rel(re2.cpu().numpy(), r_re) < TOL and _rel(rg2.cpu().numpy(), r_rg) < TOL
+
+
+def test_nonfinite_position_reported():
+    """A NaN coordinate is flagged on the device and reported by rpy_status."""
+    w = inputs.workload("n100")
+    pos = w.positions()
+    pos[17, 1] = np.nan
+    ctx = rpy.context_for(w)
+    ctx.build(_cuda(pos))
+    assert ctx.status() == rpy.RPY_ENONFINITE
+    assert ctx.status() == 0
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 2e-6), ("bf16", 2e-2)])
+def test_precision_forms_n100(n100, prec, tol):
+    """FP32 / BF16 stored real-space part with FP32 accumulation inside each
+    tile; error of D.v and of dS against the FP64 oracle within the bound of
+    the element rounding (2^-24, 2^-9 relative per element) times the
+    row-norm growth."""
+    _say(f"precision {prec}")
+    w, pos, D, _ = n100
+    ctx = rpy.context_for(w, lowp=prec, max_rhs=4)
+    ctx.build(_cuda(pos))
+    v = np.random.default_rng(11).standard_normal((2, w.n, 3))
+    out = ctx.apply(_cuda(v), prec=prec).cpu().numpy().reshape(2, -1)
+    ref = orc_matvec(D, v)
+    assert _rel(out, ref) < tol
+    lam = np.linalg.eigvalsh(D)
+    lo, hi = 0.9 * lam[0], 1.1 * lam[-1]
+    dw = w.noise(m=2)
+    ds = ctx.sqrt_apply(_cuda(dw), 20, lo, hi, prec=prec).cpu().numpy().reshape(2, -1)
+    import oracle
+    ref = oracle.cheb_sqrt(D, dw.reshape(2, -1), 20, lo, hi)
+    assert _rel(ds, ref) < 5 * tol
+
+
+def test_apply_n1000(orc):
+    """N = 1000 (16 tiles per side): full D.v against the dense oracle."""
+    _say("apply n1000")
+    w = inputs.workload("n1000")
+    pos = w.positions()
+    D = orc.diffusion_matrix(pos, w.L, w.a, w.alpha, w.rc, w.n2max)
+    ctx = rpy.context_for(w, max_rhs=2)
+    ctx.build(_cuda(pos))
+    v = np.random.default_rng(5).standard_normal((2, w.n, 3))
+    out = ctx.apply(_cuda(v)).cpu().numpy().reshape(2, -1)
+    assert _rel(out, orc_matvec(D, v)) < TOL
+    got = ctx.real_space_dense().cpu().numpy()
+    Drs = orc.real_space_matrix(pos, w.L, w.a, w.alpha, w.rc)
+    assert _rel(got, Drs) < TOL
+
+
+def test_full_size_n4000_sampled_rows(orc):
+    """The bench workload (N = 4000, 63 tiles per side): sampled block rows of
+    D.v and of one Chebyshev step against oracle rows."""
+    _say("n4000 sampled rows")
+    w = inputs.workload("n4000")
+    pos = w.positions()
+    rows = [0, 1, 63, 64, 1999, 3968, 3999]
+    R = orc.diffusion_rows(pos, rows, w.L, w.a, w.alpha, w.rc, w.n2max)
+    ctx = rpy.context_for(w)
+    ctx.build(_cuda(pos))
+    v = np.random.default_rng(8).standard_normal((1, w.n, 3))
+    out = ctx.apply(_cuda(v)).cpu().numpy().reshape(w.n, 3)
+    ref = (R @ v.reshape(-1)).reshape(len(rows), 3)
+    assert _rel(out[rows], ref) < TOL
+    # N_Ch = 2: dS = c0/2 dW + c1 Y dW, rows from the oracle's rows of D
+    lo, hi = 0.02, 20.0
+    dw = w.noise()
+    ds = ctx.sqrt_apply(_cuda(dw), 2, lo, hi).cpu().numpy().reshape(w.n, 3)
+    c = orc.cheb_coeffs(2, lo, hi)
+    dwf = dw.reshape(-1)
+    y = (2 * (R @ dwf) - (hi + lo) * dwf.reshape(w.n, 3)[rows].reshape(-1)) / (hi - lo)
+    ref = 0.5 * c[0] * dwf.reshape(w.n, 3)[rows].reshape(-1) + c[1] * y
+    assert _rel(ds[rows].reshape(-1), ref) < TOL
