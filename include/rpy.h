@@ -197,6 +197,25 @@ int rpy_philox4x32_10(const uint32_t *ctr_key, uint32_t *out, int64_t n,
 int rpy_host_pair_block(const rpy_params *p, const double *d, int self,
                         double *out);
 
+/* Kernel timing for measurement.  rpy_profile_enable(c, cap) creates, once,
+ * cap HIP event pairs per kernel class and from then on records a pair around
+ * every launch of that class on the caller's stream (cap = 0 stops
+ * recording; the events are kept until rpy_destroy).  rpy_profile_read
+ * synchronises the device, returns the number of recorded launches of class
+ * `kind` (RPY_PROF_*) and their summed duration in milliseconds (host
+ * outputs), and resets that class.  Launches beyond cap are not recorded. */
+enum {
+    RPY_PROF_SYMV = 0,      /* real-space tile product, any precision */
+    RPY_PROF_BUILD = 1,     /* real-space tile build */
+    RPY_PROF_SF = 2,        /* structure-factor partials */
+    RPY_PROF_SFRED = 3,     /* structure-factor reduction */
+    RPY_PROF_FINAL = 4,     /* reduction + reciprocal sum + recurrence */
+    RPY_PROF_OTHER = 5,     /* forces, noise, coefficients, update */
+    RPY_PROF_KINDS = 6
+};
+int rpy_profile_enable(rpy_ctx *c, int cap);
+int rpy_profile_read(rpy_ctx *c, int kind, int64_t *count, double *total_ms);
+
 /* Number of wave vectors in the half-space set used per product. */
 int rpy_num_kvectors(const rpy_ctx *c);
 

@@ -63,6 +63,7 @@ def _L():
             "orc_recip_space": (None, [i, p, d, d, d, i, p]),
             "orc_count_kvectors": (i, [i]),
             "orc_matvec": (None, [i, p, i, p, p]),
+            "orc_rows_matvec": (None, [i, i, p, p, p]),
             "orc_cheb_coeffs": (None, [i, d, d, p]),
             "orc_cheb_sqrt": (None, [i, p, i, p, i, d, d, p]),
             "orc_sqrt_error": (d, [i, p, p, p]),
@@ -202,6 +203,14 @@ def matvec(D, V) -> np.ndarray:
     out = np.empty_like(V2)
     _L().orc_matvec(D.shape[0], _ptr(D), V2.shape[0], _ptr(V2), _ptr(out))
     return out.reshape(shp)
+
+
+def rows_matvec(R, v) -> np.ndarray:
+    """R . v for a block of rows R [r, c] and a vector v [c] (plain loop)."""
+    R, v = _f64(R), _f64(v).ravel()
+    out = np.empty(R.shape[0])
+    _L().orc_rows_matvec(R.shape[0], R.shape[1], _ptr(R), _ptr(v), _ptr(out))
+    return out
 
 
 # ---------------------------------------------------------------- chebyshev

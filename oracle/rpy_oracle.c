@@ -332,6 +332,17 @@ void orc_matvec(int n3, const double *D, int m, const double *V, double *out)
         }
 }
 
+/* out = R . v for a block of rows R [nrows][ncols] (same plain loop). */
+void orc_rows_matvec(int nrows, int ncols, const double *R, const double *v, double *out)
+{
+#pragma omp parallel for
+    for (int i = 0; i < nrows; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < ncols; ++k) s += R[(long)i * ncols + k] * v[k];
+        out[i] = s;
+    }
+}
+
 /* ------------------------------------------------------------------------
  * Chebyshev coefficients (section "Decomposition of the diffusion tensor",
  * eq. cheb1): c_p = (2/N) sum_{j=1..N} f(cos th_j) cos(p th_j),

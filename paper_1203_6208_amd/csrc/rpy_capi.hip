@@ -13,8 +13,16 @@
 
 using namespace rpy;
 
+struct Prof {
+    int cap = 0;          // event pairs per kind (0: recording off)
+    int alloc = 0;        // pairs created
+    hipEvent_t *ev[RPY_PROF_KINDS] = {};
+    int n[RPY_PROF_KINDS] = {};
+};
+
 struct rpy_ctx {
     Ctx c;
+    Prof prof;
     double *F = nullptr;      // [2][3N]: forces, then U+ (all ones)
     double *Y = nullptr;      // [2][3N]: D.F, D.U+
     double *dW = nullptr;     // [3N]
@@ -153,6 +161,10 @@ extern "C" void rpy_destroy(rpy_ctx *x)
                     c.sfpart, c.tk, c.work, c.scal, c.red, c.flags, c.cell_start, c.cell_beads};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
+    for (int k = 0; k < RPY_PROF_KINDS; ++k) {
+        for (int i = 0; i < 2 * x->prof.alloc; ++i) (void)hipEventDestroy(x->prof.ev[k][i]);
+        delete[] x->prof.ev[k];
+    }
     delete x;
 }
 
@@ -265,11 +277,34 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
 
 static inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Event pair around one launch of kind k (no-op when recording is off).
+struct ProfScope {
+    rpy_ctx *x;
+    int k;
+    hipStream_t s;
+    bool on;
+    ProfScope(rpy_ctx *x_, int k_, hipStream_t s_) : x(x_), k(k_), s(s_)
+    {
+        on = x->prof.cap > 0 && x->prof.n[k] < x->prof.cap;
+        if (on) (void)hipEventRecord(x->prof.ev[k][2 * x->prof.n[k]], s);
+    }
+    ~ProfScope()
+    {
+        if (on) {
+            (void)hipEventRecord(x->prof.ev[k][2 * x->prof.n[k] + 1], s);
+            ++x->prof.n[k];
+        }
+    }
+};
+
 extern "C" int rpy_ewald_build(rpy_ctx *x, const double *pos, void *stream)
 {
     if (!x || !pos) return RPY_EINVAL;
     launch_wrap_tables(x->c, pos, S(stream));
-    launch_build_tiles(x->c, S(stream));
+    {
+        ProfScope ps(x, RPY_PROF_BUILD, S(stream));
+        launch_build_tiles(x->c, S(stream));
+    }
     return check_launch("rpy_ewald_build");
 }
 
@@ -284,10 +319,22 @@ static void product(rpy_ctx *x, const double *v, int m, int prec, const FinArgs 
                     hipStream_t s)
 {
     const Ctx &c = x->c;
-    launch_structure_factors(c, v, m, s);
-    launch_symv(c, prec, v, m, s);
-    launch_sf_reduce(c, m, s);
-    launch_finalize(c, fin, s);
+    {
+        ProfScope ps(x, RPY_PROF_SF, s);
+        launch_structure_factors(c, v, m, s);
+    }
+    {
+        ProfScope ps(x, RPY_PROF_SYMV, s);
+        launch_symv(c, prec, v, m, s);
+    }
+    {
+        ProfScope ps(x, RPY_PROF_SFRED, s);
+        launch_sf_reduce(c, m, s);
+    }
+    {
+        ProfScope ps(x, RPY_PROF_FINAL, s);
+        launch_finalize(c, fin, s);
+    }
 }
 
 extern "C" int rpy_apply(rpy_ctx *x, const double *v, double *out, int m, int prec,
@@ -422,9 +469,15 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
     if (rc) return rc;
     hipStream_t s = S(stream);
     const size_t nv = (size_t)c.n3;
-    launch_wrap_tables(c, pos, s);
-    forces(x, pos, bp->ev_zstar, bp->ev_dstar, bp->ev_rcut, x->F, s);
-    launch_build_tiles(c, s);
+    {
+        ProfScope ps(x, RPY_PROF_OTHER, s);
+        launch_wrap_tables(c, pos, s);
+        forces(x, pos, bp->ev_zstar, bp->ev_dstar, bp->ev_rcut, x->F, s);
+    }
+    {
+        ProfScope ps(x, RPY_PROF_BUILD, s);
+        launch_build_tiles(c, s);
+    }
     FinArgs f{};
     f.mode = FIN_APPLY;
     f.vout = x->Y;
@@ -506,6 +559,43 @@ extern "C" int rpy_host_pair_block(const rpy_params *p, const double *d, int sel
     pair_block(d[0], d[1], d[2], self != 0, pc, b);
     const double v[9] = {b[0], b[1], b[2], b[1], b[3], b[4], b[2], b[4], b[5]};
     memcpy(out, v, sizeof v);
+    return RPY_OK;
+}
+
+extern "C" int rpy_profile_enable(rpy_ctx *x, int cap)
+{
+    if (!x || cap < 0) return RPY_EINVAL;
+    Prof &p = x->prof;
+    if (cap > p.alloc) {
+        for (int k = 0; k < RPY_PROF_KINDS; ++k) {
+            hipEvent_t *ev = new (std::nothrow) hipEvent_t[2 * (size_t)cap];
+            if (!ev) return RPY_ENOMEM;
+            for (int i = 0; i < 2 * p.alloc; ++i) ev[i] = p.ev[k][i];
+            for (int i = 2 * p.alloc; i < 2 * cap; ++i) HIP_TRY(hipEventCreate(&ev[i]));
+            delete[] p.ev[k];
+            p.ev[k] = ev;
+        }
+        p.alloc = cap;
+    }
+    p.cap = cap;
+    for (int k = 0; k < RPY_PROF_KINDS; ++k) p.n[k] = 0;
+    return RPY_OK;
+}
+
+extern "C" int rpy_profile_read(rpy_ctx *x, int kind, int64_t *count, double *total_ms)
+{
+    if (!x || kind < 0 || kind >= RPY_PROF_KINDS || !count || !total_ms) return RPY_EINVAL;
+    HIP_TRY(hipDeviceSynchronize());
+    Prof &p = x->prof;
+    double t = 0.0;
+    for (int i = 0; i < p.n[kind]; ++i) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.ev[kind][2 * i], p.ev[kind][2 * i + 1]));
+        t += ms;
+    }
+    *count = p.n[kind];
+    *total_ms = t;
+    p.n[kind] = 0;
     return RPY_OK;
 }
 

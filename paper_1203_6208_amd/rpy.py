@@ -68,6 +68,8 @@ _SIG = {
     "rpy_philox4x32_10": (_i, [_v, _v, ctypes.c_int64, _v]),
     "rpy_host_pair_block": (_i, [_P(RpyParams), _P(_d), _i, _P(_d)]),
     "rpy_num_kvectors": (_i, [_v]),
+    "rpy_profile_enable": (_i, [_v, _i]),
+    "rpy_profile_read": (_i, [_v, _i, _P(ctypes.c_int64), _P(_d)]),
     "rpy_strerror": (ctypes.c_char_p, [_i]),
 }
 for _name, (_res, _args) in _SIG.items():
@@ -199,6 +201,20 @@ def rpy_host_pair_block(params: RpyParams, d, self_pair: bool):
     _check(_lib.rpy_host_pair_block(ctypes.byref(params), dd, int(bool(self_pair)), out),
            "rpy_host_pair_block")
     return [out[i] for i in range(9)]
+
+
+PROF_SYMV, PROF_BUILD, PROF_SF, PROF_SFRED, PROF_FINAL, PROF_OTHER = range(6)
+
+
+def rpy_profile_enable(ctx, cap: int) -> None:
+    _check(_lib.rpy_profile_enable(ctx, int(cap)), "rpy_profile_enable")
+
+
+def rpy_profile_read(ctx, kind: int):
+    n, t = ctypes.c_int64(), ctypes.c_double()
+    _check(_lib.rpy_profile_read(ctx, int(kind), ctypes.byref(n), ctypes.byref(t)),
+           "rpy_profile_read")
+    return n.value, t.value
 
 
 def rpy_num_kvectors(ctx) -> int:
