@@ -205,13 +205,12 @@ int rpy_host_pair_block(const rpy_params *p, const double *d, int self,
  * `kind` (RPY_PROF_*) and their summed duration in milliseconds (host
  * outputs), and resets that class.  Launches beyond cap are not recorded. */
 enum {
-    RPY_PROF_SYMV = 0,      /* real-space tile product, any precision */
+    RPY_PROF_SYMV = 0,      /* tile product (+ structure-factor partials) */
     RPY_PROF_BUILD = 1,     /* real-space tile build */
-    RPY_PROF_SF = 2,        /* structure-factor partials */
-    RPY_PROF_SFRED = 3,     /* structure-factor reduction */
-    RPY_PROF_FINAL = 4,     /* reduction + reciprocal sum + recurrence */
-    RPY_PROF_OTHER = 5,     /* forces, noise, coefficients, update */
-    RPY_PROF_KINDS = 6
+    RPY_PROF_KSPACE = 2,    /* structure-factor reduction */
+    RPY_PROF_EPI = 3,       /* reciprocal back-projection + recurrence epilogue */
+    RPY_PROF_OTHER = 4,     /* forces, noise, coefficients, update */
+    RPY_PROF_KINDS = 5
 };
 int rpy_profile_enable(rpy_ctx *c, int cap);
 int rpy_profile_read(rpy_ctx *c, int kind, int64_t *count, double *total_ms);

@@ -5,8 +5,6 @@
 
 namespace rpy {
 
-constexpr int SF_CHUNK = 64;   // beads per structure-factor partial
-constexpr int FIN_BEADS = 16;  // beads per finalize workgroup (16 slices each)
 
 // e^{i 2 pi n.s} for bead table tab[3][nmax+1] (n_x >= 0 on the half space).
 __device__ inline double2 kphase(const KVec &kv, const double2 *tab, int nm1)
@@ -20,119 +18,15 @@ __device__ inline double2 kphase(const KVec &kv, const double2 *tab, int nm1)
     return make_double2(xy.x * ez.x - xy.y * ez.y, xy.x * ez.y + xy.y * ez.x);
 }
 
-// ------------------------------------------------------- structure factors
-// Partial structure factors of V over one chunk of SF_CHUNK beads:
-//   C_k = sum_mu cos(k.r_mu) V_mu,  S_k = sum_mu sin(k.r_mu) V_mu.
-// Grid (chunk, k-block); one thread per wave vector; the chunk's phase tables
-// and vectors are staged in LDS.  Output sfpart[chunk][(j*6 + comp)][k].
-template <int M>
-__global__ __launch_bounds__(256) void k_structure_factors(
-    int N, int n3, int nk, int nmax, const KVec *__restrict__ kvec,
-    const double2 *__restrict__ etab, const double *__restrict__ v, int j0, int max_rhs,
-    double *__restrict__ sfpart)
-{
-    extern __shared__ double smem[];
-    const int nm1 = nmax + 1;
-    double2 *stab = reinterpret_cast<double2 *>(smem);          // [SF_CHUNK][3*nm1]
-    double *sv = smem + 2 * SF_CHUNK * 3 * nm1;                  // [SF_CHUNK][M][3]
-    const int chunk = blockIdx.x;
-    const int b0 = chunk * SF_CHUNK;
-    const int nb = min(SF_CHUNK, N - b0);
-    for (int e = threadIdx.x; e < nb * 3 * nm1; e += blockDim.x)
-        stab[e] = etab[(size_t)b0 * 3 * nm1 + e];
-    for (int e = threadIdx.x; e < nb * 3 * M; e += blockDim.x) {
-        const int b = e / (3 * M), r = e % (3 * M), j = r / 3, c = r % 3;
-        sv[e] = v[(size_t)(j0 + j) * n3 + 3 * (b0 + b) + c];
+// ------------------------------------------------------------------ SYMV
+#define RPY_RHS_GROUPS(m, BODY)                                              \
+    for (int j0 = 0; j0 < (m);) {                                            \
+        const int mc = ((m) - j0) >= 4 ? 4 : ((m) - j0) >= 2 ? 2 : 1;        \
+        if (mc == 4) { constexpr int MC = 4; BODY; }                         \
+        else if (mc == 2) { constexpr int MC = 2; BODY; }                    \
+        else { constexpr int MC = 1; BODY; }                                 \
+        j0 += mc;                                                            \
     }
-    __syncthreads();
-    const int k = blockIdx.y * blockDim.x + threadIdx.x;
-    if (k >= nk) return;
-    const KVec kv = kvec[k];
-    double acc[6 * M];
-#pragma unroll
-    for (int q = 0; q < 6 * M; ++q) acc[q] = 0.0;
-    for (int b = 0; b < nb; ++b) {
-        const double2 e = kphase(kv, stab + b * 3 * nm1, nm1);
-#pragma unroll
-        for (int j = 0; j < M; ++j)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double x = sv[b * 3 * M + 3 * j + c];
-                acc[6 * j + c] += e.x * x;
-                acc[6 * j + 3 + c] += e.y * x;
-            }
-    }
-    double *o = sfpart + (size_t)chunk * 6 * max_rhs * nk;
-#pragma unroll
-    for (int j = 0; j < M; ++j)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) o[(size_t)(6 * (j0 + j) + q) * nk + k] = acc[6 * j + q];
-}
-
-void launch_structure_factors(const Ctx &c, const double *v, int m, hipStream_t s)
-{
-    const int nm1 = c.nmax + 1;
-    for (int j0 = 0; j0 < m;) {
-        const int mc = (m - j0) >= 4 ? 4 : (m - j0) >= 2 ? 2 : 1;
-        const dim3 g(c.nsfc, (c.nk + 255) / 256), b(256);
-        const size_t lds = sizeof(double) * (2 * SF_CHUNK * 3 * nm1 + SF_CHUNK * 3 * mc);
-        if (mc == 4)
-            hipLaunchKernelGGL(k_structure_factors<4>, g, b, lds, s, c.N, c.n3, c.nk, c.nmax,
-                               c.kvec, c.etab, v, j0, c.rhs_cap, c.sfpart);
-        else if (mc == 2)
-            hipLaunchKernelGGL(k_structure_factors<2>, g, b, lds, s, c.N, c.n3, c.nk, c.nmax,
-                               c.kvec, c.etab, v, j0, c.rhs_cap, c.sfpart);
-        else
-            hipLaunchKernelGGL(k_structure_factors<1>, g, b, lds, s, c.N, c.n3, c.nk, c.nmax,
-                               c.kvec, c.etab, v, j0, c.rhs_cap, c.sfpart);
-        j0 += mc;
-    }
-}
-
-// Sum the chunk partials in chunk order and apply the reciprocal kernel:
-//   Tc_k = 2 m(k) (I - khat khat) C_k,  Ts_k = 2 m(k) (I - khat khat) S_k.
-// Block (64 wave vectors) x (4 chunk lanes); grid (k-blocks, m).
-__global__ __launch_bounds__(256) void k_sf_reduce(int nk, int nsfc, int max_rhs,
-                                                   const KCoef *__restrict__ kcoef,
-                                                   const double *__restrict__ sfpart,
-                                                   double *__restrict__ tk)
-{
-    __shared__ double red[4][6][64];
-    const int kx = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int k = blockIdx.x * 64 + kx;
-    const int j = blockIdx.y;
-    double s[6] = {0, 0, 0, 0, 0, 0};
-    if (k < nk) {
-        for (int ch = q; ch < nsfc; ch += 4) {
-            const double *o = sfpart + (size_t)ch * 6 * max_rhs * nk + (size_t)6 * j * nk + k;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) s[c] += o[(size_t)c * nk];
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) red[q][c][kx] = s[c];
-    __syncthreads();
-    if (q != 0 || k >= nk) return;
-    double t[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) t[c] = ((red[0][c][kx] + red[1][c][kx]) + red[2][c][kx]) + red[3][c][kx];
-    const KCoef kc = kcoef[k];
-    const double hc = kc.hx * t[0] + kc.hy * t[1] + kc.hz * t[2];
-    const double hs = kc.hx * t[3] + kc.hy * t[4] + kc.hz * t[5];
-    double *o = tk + (size_t)6 * j * nk + k;
-    o[0 * (size_t)nk] = kc.w * (t[0] - kc.hx * hc);
-    o[1 * (size_t)nk] = kc.w * (t[1] - kc.hy * hc);
-    o[2 * (size_t)nk] = kc.w * (t[2] - kc.hz * hc);
-    o[3 * (size_t)nk] = kc.w * (t[3] - kc.hx * hs);
-    o[4 * (size_t)nk] = kc.w * (t[4] - kc.hy * hs);
-    o[5 * (size_t)nk] = kc.w * (t[5] - kc.hz * hs);
-}
-
-void launch_sf_reduce(const Ctx &c, int m, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_sf_reduce, dim3((c.nk + 63) / 64, m), dim3(256), 0, s, c.nk, c.nsfc,
-                       c.rhs_cap, c.kcoef, c.sfpart, c.tk);
-}
 
 // ------------------------------------------------------------------ SYMV
 // Element types of the stored tiles.  Each lane of a 16-lane row group owns
@@ -194,28 +88,91 @@ template <typename A> __device__ inline A sum16(A x)
     return x;
 }
 
-// One workgroup (4 waves) per stored tile (I, J).  Wave w, row group g
-// (16 lanes), lane q: rows r = 16 it + 4 w + g, it = 0..11.  Row sums give
-// A_IJ x_J -> part[J][j][rows of I]; column sums (off-diagonal tiles only)
-// give A_IJ^T x_I -> part[I][j][rows of J].
+// Structure-factor partials of the product's input vector, carried by the
+// first `nsf` workgroups of the product kernel (they only read v, so they
+// run beside the tile stream).  Workgroup b: bead chunk b / nkb (SF_BEADS
+// beads), wave-vector block b % nkb; one thread per wave vector:
+//   sfpart[chunk][6 j + c][k] = sum_mu {cos, sin}(k.r_mu) v_mu,c.
+template <int M>
+__device__ inline void sf_partial_block(int b, int nkb, int N, int n3, int nk, int nmax,
+                                        int rhs_cap, int j0, const KVec *__restrict__ kvec,
+                                        const double2 *__restrict__ etab,
+                                        const double *__restrict__ v, double *__restrict__ sfpart,
+                                        double *smem)
+{
+    const int nm1 = nmax + 1;
+    const int chunk = b / nkb, kb = b % nkb;
+    const int b0 = chunk * SF_BEADS;
+    const int nb = min(SF_BEADS, N - b0);
+    double2 *stab = reinterpret_cast<double2 *>(smem);          // [SF_BEADS][3*nm1]
+    double *sv = smem + 2 * SF_BEADS * 3 * nm1;                  // [SF_BEADS][M][3]
+    for (int e = threadIdx.x; e < nb * 3 * nm1; e += blockDim.x)
+        stab[e] = etab[(size_t)b0 * 3 * nm1 + e];
+    for (int e = threadIdx.x; e < nb * 3 * M; e += blockDim.x) {
+        const int bl = e / (3 * M), r = e % (3 * M), j = r / 3, c = r % 3;
+        sv[e] = v[(size_t)(j0 + j) * n3 + 3 * (b0 + bl) + c];
+    }
+    __syncthreads();
+    const int k = kb * blockDim.x + threadIdx.x;
+    if (k >= nk) return;
+    const KVec kv = kvec[k];
+    double acc[M][6];
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[j][c] = 0.0;
+#pragma unroll 4
+    for (int bl = 0; bl < nb; ++bl) {
+        const double2 e = kphase(kv, stab + bl * 3 * nm1, nm1);
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double x = sv[bl * 3 * M + 3 * j + c];
+                acc[j][c] += e.x * x;
+                acc[j][3 + c] += e.y * x;
+            }
+    }
+    double *o = sfpart + ((size_t)chunk * 6 * rhs_cap + 6 * j0) * nk + k;
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[(size_t)(6 * j + c) * nk] = acc[j][c];
+}
+
+// Product kernel.  Workgroups [0, nsf) compute structure-factor partials of
+// v (above); each further workgroup (4 waves) takes one stored tile (I, J).
+// Wave w, row group g (16 lanes), lane q: rows r = 16 it + 4 w + g,
+// it = 0..11.  Row sums give A_IJ x_J -> part[J][j][rows of I]; column sums
+// (off-diagonal tiles only) give A_IJ^T x_I -> part[I][j][rows of J].
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_symv(int n3, int n3pad, int max_rhs,
+__global__ __launch_bounds__(256) void k_symv(int N, int n3, int n3pad, int rhs_cap, int j0,
+                                              int nsf, int nkb, int nk, int nmax,
+                                              const KVec *__restrict__ kvec,
+                                              const double2 *__restrict__ etab,
+                                              double *__restrict__ sfpart,
                                               const int2 *__restrict__ tile_ij,
                                               const T *__restrict__ tiles,
                                               const double *__restrict__ v,
                                               double *__restrict__ part)
 {
     using A = typename TileT<T>::acc_t;
-    __shared__ A sx[M][TS];
-    __shared__ double scol[4][M][TS];
-    const int t = blockIdx.x;
+    extern __shared__ double smem[];
+    if ((int)blockIdx.x < nsf) {
+        sf_partial_block<M>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
+                            sfpart, smem);
+        return;
+    }
+    A(*sx)[TS] = reinterpret_cast<A(*)[TS]>(smem);                       // [M][TS]
+    double(*scol)[M][TS] = reinterpret_cast<double(*)[M][TS]>(smem + M * TS);  // [4][M][TS]
+    const int t = blockIdx.x - nsf;
     const int2 ij = tile_ij[t];
     const int I = ij.x, J = ij.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane >> 4, q = lane & 15;
     for (int e = threadIdx.x; e < M * TS; e += blockDim.x) {
         const int j = e / TS, r = e % TS, row = I * TS + r;
-        sx[j][r] = row < n3 ? (A)v[(size_t)j * n3 + row] : (A)0;
+        sx[j][r] = row < n3 ? (A)v[(size_t)(j0 + j) * n3 + row] : (A)0;
     }
     A xj[M][12];
 #pragma unroll
@@ -223,7 +180,7 @@ __global__ __launch_bounds__(256) void k_symv(int n3, int n3pad, int max_rhs,
 #pragma unroll
         for (int e = 0; e < 12; ++e) {
             const int col = J * TS + TileT<T>::col(q, e);
-            xj[j][e] = col < n3 ? (A)v[(size_t)j * n3 + col] : (A)0;
+            xj[j][e] = col < n3 ? (A)v[(size_t)(j0 + j) * n3 + col] : (A)0;
         }
     A cacc[M][12];
 #pragma unroll
@@ -244,7 +201,8 @@ __global__ __launch_bounds__(256) void k_symv(int n3, int n3pad, int max_rhs,
 #pragma unroll
             for (int e = 0; e < 12; ++e) rs += a[e] * xj[j][e];
             rs = sum16(rs);
-            if (q == 0) part[((size_t)J * max_rhs + j) * n3pad + I * TS + r] = (double)rs;
+            if (q == 0)
+                part[((size_t)J * rhs_cap + j0 + j) * n3pad + I * TS + r] = (double)rs;
             if (offd) {
                 const A xr = sx[j][r];
 #pragma unroll
@@ -267,135 +225,222 @@ __global__ __launch_bounds__(256) void k_symv(int n3, int n3pad, int max_rhs,
     for (int e = threadIdx.x; e < M * TS; e += blockDim.x) {
         const int j = e / TS, cidx = e % TS;
         const double s = ((scol[0][j][cidx] + scol[1][j][cidx]) + scol[2][j][cidx]) + scol[3][j][cidx];
-        part[((size_t)I * max_rhs + j) * n3pad + J * TS + cidx] = s;
+        part[((size_t)I * rhs_cap + j0 + j) * n3pad + J * TS + cidx] = s;
     }
+}
+
+template <typename T, int M> static size_t symv_lds(const Ctx &c)
+{
+    // sx occupies M*TS double slots (whatever A is), then scol[4][M][TS]
+    const size_t tile = sizeof(double) * M * TS + sizeof(double) * 4 * M * TS;
+    const size_t sf = sizeof(double) * (2 * SF_BEADS * 3 * (c.nmax + 1) + SF_BEADS * 3 * M);
+    return tile > sf ? tile : sf;
+}
+
+template <typename T, int M>
+static void symv_launch(const Ctx &c, const T *tiles, const double *v, int j0, hipStream_t s)
+{
+    const int nkb = (c.nk + 255) / 256;
+    const int nsf = c.nsfc * nkb;
+    const size_t lds = symv_lds<T, M>(c);
+    hipLaunchKernelGGL((k_symv<T, M>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N,
+                       c.n3, c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab,
+                       c.sfpart, c.tile_ij, tiles, v, c.part);
 }
 
 template <typename T>
-static void symv_typed(const Ctx &c, const T *tiles, const double *v, int m, hipStream_t s)
+static void symv_group(const Ctx &c, const T *tiles, const double *v, int j0, int mc,
+                       hipStream_t s)
 {
-    for (int j0 = 0; j0 < m;) {
-        const int mc = (m - j0) >= 4 ? 4 : (m - j0) >= 2 ? 2 : 1;
-        double *part = c.part + (size_t)j0 * c.n3pad;
-        const double *vj = v + (size_t)j0 * c.n3;
-        const dim3 g(c.ntiles), b(256);
-        if (mc == 4)
-            hipLaunchKernelGGL((k_symv<T, 4>), g, b, 0, s, c.n3, c.n3pad, c.rhs_cap, c.tile_ij,
-                               tiles, vj, part);
-        else if (mc == 2)
-            hipLaunchKernelGGL((k_symv<T, 2>), g, b, 0, s, c.n3, c.n3pad, c.rhs_cap, c.tile_ij,
-                               tiles, vj, part);
-        else
-            hipLaunchKernelGGL((k_symv<T, 1>), g, b, 0, s, c.n3, c.n3pad, c.rhs_cap, c.tile_ij,
-                               tiles, vj, part);
-        j0 += mc;
-    }
+    if (mc == 4) symv_launch<T, 4>(c, tiles, v, j0, s);
+    else if (mc == 2) symv_launch<T, 2>(c, tiles, v, j0, s);
+    else symv_launch<T, 1>(c, tiles, v, j0, s);
 }
 
-void launch_symv(const Ctx &c, int prec, const double *v, int m, hipStream_t s)
+void launch_symv(const Ctx &c, int prec, const double *v, int j0, int mc, hipStream_t s)
 {
     if (prec == RPY_PREC_F32)
-        symv_typed<float>(c, c.d32, v, m, s);
+        symv_group<float>(c, c.d32, v, j0, mc, s);
     else if (prec == RPY_PREC_BF16)
-        symv_typed<uint16_t>(c, c.d16, v, m, s);
+        symv_group<uint16_t>(c, c.d16, v, j0, mc, s);
     else
-        symv_typed<double>(c, c.d64, v, m, s);
+        symv_group<double>(c, c.d64, v, j0, mc, s);
 }
 
-// ------------------------------------------------------------- finalize
-// 16 beads per workgroup, 16 lanes per bead.  Lane q of bead nu sums the
-// tile partials K = q, q+16, ... and the reciprocal terms k = q, q+16, ...:
-//   y = sum_K part[K] + sum_k cos(k.r_nu) Tc_k + sin(k.r_nu) Ts_k,
-// the 16 lanes are combined, then the epilogue of `mode` writes the result.
-template <int M>
-__global__ __launch_bounds__(256) void k_finalize(int N, int n3, int n3pad, int nbt, int nk,
-                                                  int nmax, int max_rhs,
-                                                  const KVec *__restrict__ kvec,
-                                                  const double2 *__restrict__ etab,
-                                                  const double *__restrict__ part,
-                                                  const double *__restrict__ tk, int j0,
-                                                  FinArgs f)
+// ------------------------------------------------- structure-factor reduction
+// Workgroup (16 wave vectors) x (64 chunk groups: 16 waves x 4 lane quarters);
+// grid (k blocks, 2 M): y = (rhs j, cos or sin half).  Lane quarter `sub` of
+// wave g sums the chunks 4 g + sub, +64, ...; an xor tree over the quarters
+// and the 16 waves in LDS combine them in a fixed order, then
+//   T_k = 2 m(k) (I - khat khat) C_k  (or S_k)
+// goes to tk[k][j][3 half + c].
+__global__ __launch_bounds__(1024) void k_sf_reduce(int nk, int nsfc, int rhs_cap, int j0,
+                                                    const KCoef *__restrict__ kcoef,
+                                                    const double *__restrict__ sfpart,
+                                                    double *__restrict__ tk)
 {
-    const int nm1 = nmax + 1;
-    extern __shared__ double2 stab[];   // [FIN_BEADS][3*nm1]
-    const int b0 = blockIdx.x * FIN_BEADS;
-    const int nb = min(FIN_BEADS, N - b0);
-    for (int e = threadIdx.x; e < nb * 3 * nm1; e += blockDim.x)
-        stab[e] = etab[(size_t)b0 * 3 * nm1 + e];
+    __shared__ double red[16][3][16];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int kk = lane & 15, sub = lane >> 4;
+    const int k = blockIdx.x * 16 + kk;
+    const int j = blockIdx.y >> 1, half = blockIdx.y & 1;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (k < nk) {
+        const size_t cstride = (size_t)6 * rhs_cap * nk;
+        const double *o = sfpart + (size_t)(6 * (j0 + j) + 3 * half) * nk + k;
+        for (int ch = 4 * g + sub; ch < nsfc; ch += 64) {
+            s0 += o[ch * cstride];
+            s1 += o[ch * cstride + nk];
+            s2 += o[ch * cstride + 2 * (size_t)nk];
+        }
+    }
+    s0 += __shfl_xor(s0, 16);
+    s0 += __shfl_xor(s0, 32);
+    s1 += __shfl_xor(s1, 16);
+    s1 += __shfl_xor(s1, 32);
+    s2 += __shfl_xor(s2, 16);
+    s2 += __shfl_xor(s2, 32);
+    if (sub == 0) {
+        red[g][0][kk] = s0;
+        red[g][1][kk] = s1;
+        red[g][2][kk] = s2;
+    }
     __syncthreads();
-    const int bl = threadIdx.x >> 4, q = threadIdx.x & 15;
-    const int nu = b0 + bl;
-    const bool live = bl < nb;
+    if (threadIdx.x >= 16 || k >= nk) return;
+    double t[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double a = 0.0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) a += red[w][c][kk];
+        t[c] = a;
+    }
+    const KCoef kc = kcoef[k];
+    const double h = kc.hx * t[0] + kc.hy * t[1] + kc.hz * t[2];
+    double *o = tk + ((size_t)k * rhs_cap + j0 + j) * 6 + 3 * half;
+    o[0] = kc.w * (t[0] - kc.hx * h);
+    o[1] = kc.w * (t[1] - kc.hy * h);
+    o[2] = kc.w * (t[2] - kc.hz * h);
+}
+
+void launch_sf_reduce(const Ctx &c, int m, hipStream_t s)
+{
+    RPY_RHS_GROUPS(m, hipLaunchKernelGGL(k_sf_reduce, dim3((c.nk + 15) / 16, 2 * MC), dim3(1024),
+                                         0, s, c.nk, c.nsfc, c.rhs_cap, j0, c.kcoef, c.sfpart,
+                                         c.tk));
+}
+
+// ------------------------------------- reciprocal back-projection + epilogue
+// Workgroup: 16 beads x 64 slices (16 waves; lane = bead (low 4 bits) and
+// sub-slice (high 2 bits); slice u = 4 wave + sub).  Slice u owns the wave
+// vectors [u nk/64, (u+1) nk/64) and the tile columns K = u, u+64, ...:
+//   y_u = sum_K part[K][j][3 nu + c] + sum_k cos(k.r_nu) Tc_k + sin(k.r_nu) Ts_k
+// with k.r_nu = 2 pi n.s_nu.  The wave vectors are sorted by (n_x, n_y) and
+// then n_z, so inside a run of equal (n_x, n_y) the phase advances by
+// e^{i 2 pi s_z}.  Slices are combined in a fixed order (xor tree over the
+// sub-slices, then the 16 waves in LDS), then the epilogue of `mode`:
+//   EPI_APPLY      out = y
+//   EPI_CHEB_FIRST V_1 = ya y - yb V_0, acc = (c_0/2) V_0 + c_1 V_1, dv = y
+//   EPI_CHEB_NEXT  V_p = 2 (ya y - yb V_{p-1}) - V_{p-2}, acc += c_p V_p
+constexpr int EPI_BEADS = 16;
+constexpr int EPI_SLICES = 64;
+template <int M>
+__global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, int nbt, int nk,
+                                                     int rhs_cap, int j0,
+                                                     const KVec *__restrict__ kvec,
+                                                     const double *__restrict__ sfr,
+                                                     const double *__restrict__ part,
+                                                     const double *__restrict__ tk, EpiArgs f)
+{
+    __shared__ double red[16][3][EPI_BEADS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int bl = lane & 15, sub = lane >> 4;
+    const int u = 4 * w + sub;
+    const int nu = blockIdx.x * EPI_BEADS + bl;
+    const bool live = nu < N;
+    const double sx = live ? sfr[3 * nu] : 0.0, sy = live ? sfr[3 * nu + 1] : 0.0,
+                 sz = live ? sfr[3 * nu + 2] : 0.0;
     double y[M][3];
 #pragma unroll
     for (int j = 0; j < M; ++j) y[j][0] = y[j][1] = y[j][2] = 0.0;
     if (live) {
-        for (int K = q; K < nbt; K += 16) {
+        for (int K = u; K < nbt; K += EPI_SLICES) {
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                const double *pp = part + ((size_t)K * max_rhs + j0 + j) * n3pad + 3 * nu;
+                const double *pp = part + ((size_t)K * rhs_cap + j0 + j) * n3pad + 3 * nu;
                 y[j][0] += pp[0];
                 y[j][1] += pp[1];
                 y[j][2] += pp[2];
             }
         }
-        const double2 *tab = stab + bl * 3 * nm1;
-        for (int k = q; k < nk; k += 16) {
-            const double2 e = kphase(kvec[k], tab, nm1);
+    }
+    const int klo = (int)((long)u * nk / EPI_SLICES), khi = (int)((long)(u + 1) * nk / EPI_SLICES);
+    double ezr, ezi;
+    sincospi(2.0 * sz, &ezi, &ezr);
+    double cs = 1.0, sn = 0.0;
+    int px = -(1 << 30), py = 0, pz = 0;
+    for (int k = klo; k < khi; ++k) {
+        const KVec kv = kvec[k];
+        if (kv.nx == px && kv.ny == py && kv.nz == pz + 1) {
+            const double c2 = cs * ezr - sn * ezi;
+            sn = cs * ezi + sn * ezr;
+            cs = c2;
+        } else {
+            sincospi(2.0 * (kv.nx * sx + kv.ny * sy + kv.nz * sz), &sn, &cs);
+        }
+        px = kv.nx;
+        py = kv.ny;
+        pz = kv.nz;
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-                const double *tt = tk + (size_t)6 * (j0 + j) * nk + k;
+        for (int j = 0; j < M; ++j) {
+            const double *tt = tk + ((size_t)k * rhs_cap + j0 + j) * 6;
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    y[j][c] += e.x * tt[(size_t)c * nk] + e.y * tt[(size_t)(3 + c) * nk];
-            }
+            for (int c = 0; c < 3; ++c) y[j][c] += cs * tt[c] + sn * tt[3 + c];
         }
     }
-#pragma unroll
-    for (int j = 0; j < M; ++j)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) y[j][c] = sum16(y[j][c]);
-    if (!live) return;
     const double ya = f.scal ? f.scal[2] : 0.0, yb = f.scal ? f.scal[3] : 0.0;
 #pragma unroll
-    for (int j = 0; j < M; ++j)
+    for (int j = 0; j < M; ++j) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            if ((3 * j + c) % 16 != q) continue;
-            const size_t o = (size_t)(j0 + j) * n3 + 3 * nu + c;
-            if (f.mode == FIN_APPLY) {
-                f.vout[o] = y[j][c];
-            } else if (f.mode == FIN_CHEB_FIRST) {
-                const double v0 = f.vprev[o];
-                const double v1 = ya * y[j][c] - yb * v0;
-                f.vout[o] = v1;
-                f.acc[o] = 0.5 * f.scal[8] * v0 + f.scal[9] * v1;
-                if (f.dv) f.dv[o] = y[j][c];
-            } else {
-                const double vp = 2.0 * (ya * y[j][c] - yb * f.vprev[o]) - f.vprev2[o];
-                f.vout[o] = vp;
-                f.acc[o] += f.scal[8 + f.p] * vp;
+            double v = y[j][c];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (sub == 0) red[w][c][bl] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3 * EPI_BEADS) {
+            const int b = threadIdx.x / 3, c = threadIdx.x % 3;
+            const int bead = blockIdx.x * EPI_BEADS + b;
+            if (bead < N) {
+                double yy = 0.0;
+#pragma unroll
+                for (int ww = 0; ww < 16; ++ww) yy += red[ww][c][b];
+                const size_t o = (size_t)(j0 + j) * n3 + 3 * bead + c;
+                if (f.mode == EPI_APPLY) {
+                    f.vout[o] = yy;
+                } else if (f.mode == EPI_CHEB_FIRST) {
+                    const double v0 = f.vprev[o];
+                    const double v1 = ya * yy - yb * v0;
+                    f.vout[o] = v1;
+                    f.acc[o] = 0.5 * f.scal[8] * v0 + f.scal[9] * v1;
+                    if (f.dv) f.dv[o] = yy;
+                } else {
+                    const double vp = 2.0 * (ya * yy - yb * f.vprev[o]) - f.vprev2[o];
+                    f.vout[o] = vp;
+                    f.acc[o] += f.scal[8 + f.p] * vp;
+                }
             }
         }
+        __syncthreads();
+    }
 }
 
-void launch_finalize(const Ctx &c, const FinArgs &f, hipStream_t s)
+void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
 {
-    const size_t lds = sizeof(double2) * FIN_BEADS * 3 * (c.nmax + 1);
-    const dim3 g((c.N + FIN_BEADS - 1) / FIN_BEADS), b(256);
-    for (int j0 = 0; j0 < f.m;) {
-        const int mc = (f.m - j0) >= 4 ? 4 : (f.m - j0) >= 2 ? 2 : 1;
-        if (mc == 4)
-            hipLaunchKernelGGL(k_finalize<4>, g, b, lds, s, c.N, c.n3, c.n3pad, c.nbt, c.nk,
-                               c.nmax, c.rhs_cap, c.kvec, c.etab, c.part, c.tk, j0, f);
-        else if (mc == 2)
-            hipLaunchKernelGGL(k_finalize<2>, g, b, lds, s, c.N, c.n3, c.n3pad, c.nbt, c.nk,
-                               c.nmax, c.rhs_cap, c.kvec, c.etab, c.part, c.tk, j0, f);
-        else
-            hipLaunchKernelGGL(k_finalize<1>, g, b, lds, s, c.N, c.n3, c.n3pad, c.nbt, c.nk,
-                               c.nmax, c.rhs_cap, c.kvec, c.etab, c.part, c.tk, j0, f);
-        j0 += mc;
-    }
+    const dim3 g((c.N + EPI_BEADS - 1) / EPI_BEADS), b(1024);
+    RPY_RHS_GROUPS(f.m, hipLaunchKernelGGL(k_kspace_epi<MC>, g, b, 0, s, c.N, c.n3, c.n3pad, c.nbt,
+                                           c.nk, c.rhs_cap, j0, c.kvec, c.sfr, c.part, c.tk, f));
 }
 
 // ------------------------------------------------- Chebyshev coefficients

@@ -9,8 +9,8 @@ namespace rpy {
 // A non-finite coordinate raises flags[0] and is replaced by 0 so that every
 // later kernel still runs on finite data.
 __global__ void k_wrap_tables(int N, double L, int nmax, const double *__restrict__ pos,
-                              double *__restrict__ rt, double2 *__restrict__ etab,
-                              int *__restrict__ flags)
+                              double *__restrict__ rt, double *__restrict__ sfr,
+                              double2 *__restrict__ etab, int *__restrict__ flags)
 {
     const int nu = blockIdx.x * blockDim.x + threadIdx.x;
     if (nu >= N) return;
@@ -24,6 +24,7 @@ __global__ void k_wrap_tables(int N, double L, int nmax, const double *__restric
         double s = r / L;
         s = s - floor(s);
         rt[3 * nu + i] = L * s;
+        sfr[3 * nu + i] = s;
         double2 *tab = etab + (size_t)(3 * nu + i) * (nmax + 1);
         for (int j = 0; j <= nmax; ++j) {
             double sn, cs;
@@ -38,7 +39,7 @@ void launch_wrap_tables(const Ctx &c, const double *pos, hipStream_t s)
 {
     const int bs = 256;
     hipLaunchKernelGGL(k_wrap_tables, dim3((c.N + bs - 1) / bs), dim3(bs), 0, s, c.N, c.L,
-                       c.nmax, pos, c.rt, c.etab, c.flags);
+                       c.nmax, pos, c.rt, c.sfr, c.etab, c.flags);
 }
 
 __device__ inline uint16_t to_bf16(double d)

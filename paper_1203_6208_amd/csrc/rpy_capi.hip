@@ -158,7 +158,8 @@ extern "C" void rpy_destroy(rpy_ctx *x)
     (void)hipDeviceSynchronize();
     Ctx &c = x->c;
     void *bufs[] = {c.rt, c.etab, c.kvec, c.kcoef, c.tile_ij, c.d64, c.d32, c.d16, c.part,
-                    c.sfpart, c.tk, c.work, c.scal, c.red, c.flags, c.cell_start, c.cell_beads};
+                    c.sfpart, c.tk, c.sfr, c.work, c.scal, c.red, c.flags, c.cell_start,
+                    c.cell_beads};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int k = 0; k < RPY_PROF_KINDS; ++k) {
@@ -198,7 +199,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     c.nbt = (c.N + TB - 1) / TB;
     c.ntiles = c.nbt * (c.nbt + 1) / 2;
     c.n3pad = c.nbt * TS;
-    c.nsfc = (c.N + 63) / 64;
+    c.nsfc = (c.N + SF_BEADS - 1) / SF_BEADS;
 
     // half-space wave vectors, lexicographically positive
     std::vector<KVec> kv;
@@ -240,6 +241,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
         (rc = dalloc(&c.part, (size_t)c.nbt * c.rhs_cap * c.n3pad)) ||
         (rc = dalloc(&c.sfpart, (size_t)c.nsfc * 6 * c.rhs_cap * c.nk)) ||
         (rc = dalloc(&c.tk, (size_t)6 * c.rhs_cap * c.nk)) ||
+        (rc = dalloc(&c.sfr, nv)) ||
         (rc = dalloc(&c.work, c.work_elems)) || (rc = dalloc(&c.scal, 8 + MAX_NCHEB)) ||
         (rc = dalloc(&c.red, 64)) || (rc = dalloc(&c.flags, 4)) ||
         (rc = dalloc(&c.cell_start, 2 * ncells_cap + 1)) || (rc = dalloc(&c.cell_beads, nv))) {
@@ -314,35 +316,33 @@ static bool prec_ok(const Ctx &c, int prec)
            (prec == RPY_PREC_BF16 && c.lowp == RPY_PREC_BF16);
 }
 
-// one product of the full periodic D with m vectors (no validation)
-static void product(rpy_ctx *x, const double *v, int m, int prec, const FinArgs &fin,
+// One product of the full periodic D with the m vectors v; `f` selects the
+// epilogue.  Three kernels: tile product (+ structure-factor partials of v),
+// structure-factor reduction, reciprocal back-projection + epilogue.
+static void product(rpy_ctx *x, const double *v, int m, int prec, const EpiArgs &f,
                     hipStream_t s)
 {
     const Ctx &c = x->c;
-    {
-        ProfScope ps(x, RPY_PROF_SF, s);
-        launch_structure_factors(c, v, m, s);
-    }
-    {
+    for (int j0 = 0; j0 < m;) {
+        const int mc = (m - j0) >= 4 ? 4 : (m - j0) >= 2 ? 2 : 1;
         ProfScope ps(x, RPY_PROF_SYMV, s);
-        launch_symv(c, prec, v, m, s);
+        launch_symv(c, prec, v, j0, mc, s);
+        j0 += mc;
     }
     {
-        ProfScope ps(x, RPY_PROF_SFRED, s);
+        ProfScope ps(x, RPY_PROF_KSPACE, s);
         launch_sf_reduce(c, m, s);
     }
-    {
-        ProfScope ps(x, RPY_PROF_FINAL, s);
-        launch_finalize(c, fin, s);
-    }
+    ProfScope ps(x, RPY_PROF_EPI, s);
+    launch_kspace_epi(c, f, s);
 }
 
 extern "C" int rpy_apply(rpy_ctx *x, const double *v, double *out, int m, int prec,
                          void *stream)
 {
     if (!x || !v || !out || m < 1 || m > x->c.max_rhs || !prec_ok(x->c, prec)) return RPY_EINVAL;
-    FinArgs f{};
-    f.mode = FIN_APPLY;
+    EpiArgs f{};
+    f.mode = EPI_APPLY;
     f.m = m;
     f.vout = out;
     product(x, v, m, prec, f, S(stream));
@@ -355,18 +355,18 @@ static void cheb_run(rpy_ctx *x, const double *dw, double *out, int m, int n_che
 {
     const Ctx &c = x->c;
     for (int p = 1; p < n_cheb; ++p) {
-        FinArgs f{};
+        EpiArgs f{};
         f.m = m;
         f.p = p;
         f.scal = c.scal;
         f.acc = out;
         if (p == 1) {
-            f.mode = FIN_CHEB_FIRST;
+            f.mode = EPI_CHEB_FIRST;
             f.vprev = dw;
             f.vout = x->Bv[1];
             f.dv = x->ddw;
         } else {
-            f.mode = FIN_CHEB_NEXT;
+            f.mode = EPI_CHEB_NEXT;
             f.vprev = x->Bv[(p - 1) % 2];
             f.vprev2 = p == 2 ? dw : x->Bv[p % 2];
             f.vout = x->Bv[p % 2];
@@ -394,8 +394,8 @@ extern "C" int rpy_bounds(rpy_ctx *x, double C, double *d_min, double *d_max, vo
     if (!x || !d_min || !d_max || !(C > 0)) return RPY_EINVAL;
     hipStream_t s = S(stream);
     const Ctx &c = x->c;
-    FinArgs f{};
-    f.mode = FIN_APPLY;
+    EpiArgs f{};
+    f.mode = EPI_APPLY;
     f.m = 1;
     f.vout = x->Y + c.n3;
     product(x, x->F + c.n3, 1, RPY_PREC_F64, f, s);
@@ -478,8 +478,8 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
         ProfScope ps(x, RPY_PROF_BUILD, s);
         launch_build_tiles(c, s);
     }
-    FinArgs f{};
-    f.mode = FIN_APPLY;
+    EpiArgs f{};
+    f.mode = EPI_APPLY;
     f.vout = x->Y;
     if (bp->bounds_rule == RPY_BOUNDS_PAPER) {
         f.m = 2;   // [F, U+] in one pass over D

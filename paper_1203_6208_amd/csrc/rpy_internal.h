@@ -26,6 +26,8 @@ constexpr int NSER = 20;        // terms of the small-r series of S(r)
 constexpr double XSER = 0.75;   // use the series for alpha*r below this
 constexpr int MAX_RHS = 16;
 constexpr int MAX_NCHEB = 512;
+constexpr int KSLICE = 16;      // wave-vector / tile-column slices of the back-projection
+constexpr int SF_BEADS = 64;    // beads per structure-factor partial
 
 // ---------------------------------------------------------------- pair terms
 // Constants of the real-space pair kernel.  Passed by value to kernels.
@@ -199,9 +201,10 @@ struct Ctx {
     int nbt;           // bead tiles per side
     int ntiles;        // stored tiles
     int n3pad;         // nbt * TS
-    int nsfc;          // structure-factor bead chunks
+    int nsfc;          // structure-factor bead chunks (SF_BEADS beads each)
     // device buffers
     double *rt = nullptr;        // wrapped positions [N][3]
+    double *sfr = nullptr;       // fractional coordinates s = r/L - floor(r/L) [N][3]
     double2 *etab = nullptr;     // phases [N][3][nmax+1]
     KVec *kvec = nullptr;        // [nk]
     KCoef *kcoef = nullptr;      // [nk]
@@ -209,9 +212,9 @@ struct Ctx {
     double *d64 = nullptr;       // [ntiles][TS*TS]
     float *d32 = nullptr;
     uint16_t *d16 = nullptr;
-    double *part = nullptr;      // [nbt][max_rhs][n3pad]
-    double *sfpart = nullptr;    // [nsfc][nk][6*max_rhs]
-    double *tk = nullptr;        // [nk][6*max_rhs]
+    double *part = nullptr;      // [nbt][rhs_cap][n3pad] tile-column partials
+    double *sfpart = nullptr;    // [nsfc][6*rhs_cap][nk] structure-factor partials
+    double *tk = nullptr;        // [nk][rhs_cap][6] 2 m(k) P_k (C_k, S_k)
     double *work = nullptr;      // vectors, see capi
     double *scal = nullptr;      // scalars: [0]=dmin [1]=dmax [2]=ya [3]=yb [8..]=coeffs
     double *red = nullptr;       // reduction outputs
@@ -229,24 +232,25 @@ struct Ctx {
 void launch_wrap_tables(const Ctx &c, const double *pos, hipStream_t s);
 void launch_build_tiles(const Ctx &c, hipStream_t s);
 void launch_dense_copy(const Ctx &c, double *out, hipStream_t s);
-// products
-void launch_structure_factors(const Ctx &c, const double *v, int m, hipStream_t s);
-void launch_sf_reduce(const Ctx &c, int m, hipStream_t s);
-void launch_symv(const Ctx &c, int prec, const double *v, int m, hipStream_t s);
-// finalize modes
-enum FinMode { FIN_APPLY = 0, FIN_CHEB_FIRST = 1, FIN_CHEB_NEXT = 2 };
-struct FinArgs {
+// products: the tile-product kernel also computes the structure-factor
+// partials of its input; launch_sf_reduce turns them into tk; the final
+// kernel adds the reciprocal back-projection to the tile partials and applies
+// the epilogue of `mode`.
+enum EpiMode { EPI_APPLY = 0, EPI_CHEB_FIRST = 1, EPI_CHEB_NEXT = 2 };
+struct EpiArgs {
     int mode;
     int m;
     int p;                 // Chebyshev index of the vector being produced
     const double *vprev;   // V_{p-1} [m][3N]
     const double *vprev2;  // V_{p-2}
-    double *vout;          // V_p, or D.v for FIN_APPLY
+    double *vout;          // V_p, or D.v for EPI_APPLY
     double *acc;           // sum c_p V_p
-    double *dv;            // optional: D.V_{p-1} copy (FIN_CHEB_FIRST)
+    double *dv;            // optional: D.V_0 (EPI_CHEB_FIRST)
     const double *scal;    // device scalars (ya, yb, coeffs)
 };
-void launch_finalize(const Ctx &c, const FinArgs &f, hipStream_t s);
+void launch_symv(const Ctx &c, int prec, const double *v, int j0, int mc, hipStream_t s);
+void launch_sf_reduce(const Ctx &c, int m, hipStream_t s);
+void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s);
 void launch_cheb_coeffs(const Ctx &c, int n_cheb, int rule, double C, double dmin,
                         double dmax, const double *du, hipStream_t s);
 void launch_sqrt_error(const Ctx &c, int m, const double *dw, const double *ddw,

@@ -52,28 +52,27 @@ __global__ void k_cell_count(int N, double L, int nc, const double *__restrict__
     atomicAdd(&count[cell_of(rt, nu, L, nc)], 1);
 }
 
-// Exclusive scan of the counts (one workgroup), start[ncells] = N; the
-// counts are reset to serve as insertion cursors.
+// Exclusive scan of the counts (one workgroup, Hillis-Steele over the
+// per-thread partial sums), start[ncells] = N; the counts are reset to serve
+// as insertion cursors.
 __global__ __launch_bounds__(1024) void k_cell_scan(int ncells, int *count, int *start)
 {
-    __shared__ int part[1024];
+    __shared__ int part[2][1024];
     const int tid = threadIdx.x;
     const int per = (ncells + 1023) / 1024;
     const int lo = min(tid * per, ncells), hi = min(lo + per, ncells);
     int s = 0;
     for (int i = lo; i < hi; ++i) s += count[i];
-    part[tid] = s;
+    int cur = 0;
+    part[0][tid] = s;
     __syncthreads();
-    if (tid == 0) {
-        int run = 0;
-        for (int i = 0; i < 1024; ++i) {
-            const int t = part[i];
-            part[i] = run;
-            run += t;
-        }
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = part[cur][tid] + (tid >= off ? part[cur][tid - off] : 0);
+        part[cur ^ 1][tid] = v;
+        cur ^= 1;
+        __syncthreads();
     }
-    __syncthreads();
-    int run = part[tid];
+    int run = part[cur][tid] - s;   // exclusive prefix
     for (int i = lo; i < hi; ++i) {
         start[i] = run;
         run += count[i];
@@ -92,20 +91,37 @@ __global__ void k_cell_fill(int N, double L, int nc, const double *__restrict__ 
     beads[start[c] + slot] = nu;
 }
 
-// insertion sort of each cell's bead list (deterministic summation order)
-__global__ void k_cell_sort(int ncells, const int *__restrict__ start, int *beads)
+// One workgroup per cell: order the cell's beads by index (each entry's rank
+// among the distinct indices) so that every later sum over a cell runs in a
+// fixed order.  Cells above SORT_CAP entries fall back to a serial sort.
+constexpr int SORT_CAP = 1024;
+__global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start, int *beads)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncells) return;
-    const int lo = start[c], hi = start[c + 1];
-    for (int i = lo + 1; i < hi; ++i) {
-        const int v = beads[i];
-        int j = i - 1;
-        while (j >= lo && beads[j] > v) {
-            beads[j + 1] = beads[j];
-            --j;
+    __shared__ int sb[SORT_CAP];
+    const int c = blockIdx.x;
+    const int lo = start[c], n = start[c + 1] - lo;
+    if (n <= 1) return;
+    if (n > SORT_CAP) {
+        if (threadIdx.x == 0) {
+            for (int i = lo + 1; i < lo + n; ++i) {
+                const int v = beads[i];
+                int j = i - 1;
+                while (j >= lo && beads[j] > v) {
+                    beads[j + 1] = beads[j];
+                    --j;
+                }
+                beads[j + 1] = v;
+            }
         }
-        beads[j + 1] = v;
+        return;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = beads[lo + i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int v = sb[i];
+        int r = 0;
+        for (int j = 0; j < n; ++j) r += sb[j] < v;
+        beads[lo + r] = v;
     }
 }
 
@@ -122,47 +138,129 @@ void launch_cell_list(const Ctx &c, double rcut, hipStream_t s)
     hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, ncells, count, c.cell_start);
     hipLaunchKernelGGL(k_cell_fill, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, c.L, nc, c.rt,
                        c.cell_start, count, c.cell_beads);
-    hipLaunchKernelGGL(k_cell_sort, dim3((ncells + 255) / 256), dim3(256), 0, s, ncells,
-                       c.cell_start, c.cell_beads);
+    hipLaunchKernelGGL(k_cell_sort, dim3(ncells), dim3(256), 0, s, c.cell_start, c.cell_beads);
 }
 
 // Narrow-Gaussian excluded volume, minimum image (rcut < L/2):
 //   F_nu += (z*/d*^5) d exp(-|d|^2 / (2 d*^2)), d = r_nu - r_mu, |d| <= rcut.
-__global__ void k_ev_forces(int N, double L, int nc, const double *__restrict__ rt,
-                            const int *__restrict__ start, const int *__restrict__ beads,
-                            double pref, double inv2d2, double rcut2, double *__restrict__ F)
+// One workgroup per home cell: the beads of the 27 surrounding cells are
+// staged in LDS (batches of EV_CAP); each wave takes home beads in turn and
+// its 64 lanes split the candidates; a fixed xor tree combines the lanes.
+constexpr int EV_CAP = 1024;
+constexpr int EV_HMAX = 8;   // home beads per wave held in registers per pass
+__global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double *__restrict__ rt,
+                                                  const int *__restrict__ start,
+                                                  const int *__restrict__ beads, double pref,
+                                                  double inv2d2, double rcut2,
+                                                  double *__restrict__ F)
 {
-    const int nu = blockIdx.x * blockDim.x + threadIdx.x;
-    if (nu >= N) return;
-    const double x = rt[3 * nu], y = rt[3 * nu + 1], z = rt[3 * nu + 2];
-    const double invL = 1.0 / L;
-    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-    auto visit = [&](int mu) {
-        if (mu == nu) return;
-        double dx = x - rt[3 * mu], dy = y - rt[3 * mu + 1], dz = z - rt[3 * mu + 2];
-        dx -= L * rint(dx * invL);
-        dy -= L * rint(dy * invL);
-        dz -= L * rint(dz * invL);
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 > rcut2) return;
-        const double w = pref * exp(-r2 * inv2d2);
-        f0 += w * dx;
-        f1 += w * dy;
-        f2 += w * dz;
-    };
-    if (nc >= 3) {
-        const int c = cell_of(rt, nu, L, nc);
-        const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+    __shared__ double sx[EV_CAP], sy[EV_CAP], sz[EV_CAP];
+    __shared__ int sid[EV_CAP];
+    __shared__ int nbr[27];
+    __shared__ int nbr_off[28];
+    const int c = blockIdx.x;
+    const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+    if (threadIdx.x == 0) {
+        int q = 0, tot = 0;
         for (int oz = -1; oz <= 1; ++oz)
             for (int oy = -1; oy <= 1; ++oy)
                 for (int ox = -1; ox <= 1; ++ox) {
                     const int ex = (cx + ox + nc) % nc, ey = (cy + oy + nc) % nc,
                               ez = (cz + oz + nc) % nc;
                     const int cc = (ez * nc + ey) * nc + ex;
-                    for (int i = start[cc]; i < start[cc + 1]; ++i) visit(beads[i]);
+                    nbr[q] = cc;
+                    nbr_off[q] = tot;
+                    tot += start[cc + 1] - start[cc];
+                    ++q;
                 }
-    } else {
-        for (int mu = 0; mu < N; ++mu) visit(mu);
+        nbr_off[27] = tot;
+    }
+    __syncthreads();
+    const int hlo = start[c], nh = start[c + 1] - hlo;
+    const int total = nbr_off[27];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const double invL = 1.0 / L;
+    for (int h0 = 0; h0 < nh; h0 += 4 * EV_HMAX) {
+        double acc[EV_HMAX][3];
+#pragma unroll
+        for (int i = 0; i < EV_HMAX; ++i) acc[i][0] = acc[i][1] = acc[i][2] = 0.0;
+        for (int b0 = 0; b0 < total; b0 += EV_CAP) {
+            const int nb = min(EV_CAP, total - b0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < nb; e += blockDim.x) {
+                const int g = b0 + e;
+                int q = 0;
+                while (nbr_off[q + 1] <= g) ++q;
+                const int mu = beads[start[nbr[q]] + (g - nbr_off[q])];
+                sid[e] = mu;
+                sx[e] = rt[3 * mu];
+                sy[e] = rt[3 * mu + 1];
+                sz[e] = rt[3 * mu + 2];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < EV_HMAX; ++i) {
+                const int hi = h0 + 4 * i + w;
+                if (hi < nh) {
+                    const int nu = beads[hlo + hi];
+                    const double x = rt[3 * nu], y = rt[3 * nu + 1], z = rt[3 * nu + 2];
+                    for (int e = lane; e < nb; e += 64) {
+                        if (sid[e] == nu) continue;
+                        double dx = x - sx[e], dy = y - sy[e], dz = z - sz[e];
+                        dx -= L * rint(dx * invL);
+                        dy -= L * rint(dy * invL);
+                        dz -= L * rint(dz * invL);
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 > rcut2) continue;
+                        const double wgt = pref * exp(-r2 * inv2d2);
+                        acc[i][0] += wgt * dx;
+                        acc[i][1] += wgt * dy;
+                        acc[i][2] += wgt * dz;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < EV_HMAX; ++i) {
+            const int hi = h0 + 4 * i + w;
+            double f0 = acc[i][0], f1 = acc[i][1], f2 = acc[i][2];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                f0 += __shfl_xor(f0, o);
+                f1 += __shfl_xor(f1, o);
+                f2 += __shfl_xor(f2, o);
+            }
+            if (hi < nh && lane == 0) {
+                const int nu = beads[hlo + hi];
+                F[3 * nu] += f0;
+                F[3 * nu + 1] += f1;
+                F[3 * nu + 2] += f2;
+            }
+        }
+    }
+}
+
+// Without a cell list (fewer than 3 cells per side): all pairs per bead.
+__global__ void k_ev_pairs(int N, double L, const double *__restrict__ rt, double pref,
+                           double inv2d2, double rcut2, double *__restrict__ F)
+{
+    const int nu = blockIdx.x * blockDim.x + threadIdx.x;
+    if (nu >= N) return;
+    const double x = rt[3 * nu], y = rt[3 * nu + 1], z = rt[3 * nu + 2];
+    const double invL = 1.0 / L;
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    for (int mu = 0; mu < N; ++mu) {
+        if (mu == nu) continue;
+        double dx = x - rt[3 * mu], dy = y - rt[3 * mu + 1], dz = z - rt[3 * mu + 2];
+        dx -= L * rint(dx * invL);
+        dy -= L * rint(dy * invL);
+        dz -= L * rint(dz * invL);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 > rcut2) continue;
+        const double w = pref * exp(-r2 * inv2d2);
+        f0 += w * dx;
+        f1 += w * dy;
+        f2 += w * dz;
     }
     F[3 * nu] += f0;
     F[3 * nu + 1] += f1;
@@ -174,8 +272,14 @@ void launch_ev_forces(const Ctx &c, double zstar, double dstar, double rcut, dou
 {
     const double d2 = dstar * dstar;
     const double pref = zstar / (d2 * d2 * dstar);
-    hipLaunchKernelGGL(k_ev_forces, dim3((c.N + 127) / 128), dim3(128), 0, s, c.N, c.L, c.ncell,
-                       c.rt, c.cell_start, c.cell_beads, pref, 1.0 / (2.0 * d2), rcut * rcut, F);
+    if (c.ncell >= 3) {
+        const int ncells = c.ncell * c.ncell * c.ncell;
+        hipLaunchKernelGGL(k_ev_cells, dim3(ncells), dim3(256), 0, s, c.L, c.ncell, c.rt,
+                           c.cell_start, c.cell_beads, pref, 1.0 / (2.0 * d2), rcut * rcut, F);
+    } else {
+        hipLaunchKernelGGL(k_ev_pairs, dim3((c.N + 127) / 128), dim3(128), 0, s, c.N, c.L, c.rt,
+                           pref, 1.0 / (2.0 * d2), rcut * rcut, F);
+    }
 }
 
 // ------------------------------------------------------------------ Philox

@@ -203,7 +203,7 @@ def rpy_host_pair_block(params: RpyParams, d, self_pair: bool):
     return [out[i] for i in range(9)]
 
 
-PROF_SYMV, PROF_BUILD, PROF_SF, PROF_SFRED, PROF_FINAL, PROF_OTHER = range(6)
+PROF_SYMV, PROF_BUILD, PROF_KSPACE, PROF_EPI, PROF_OTHER = range(5)
 
 
 def rpy_profile_enable(ctx, cap: int) -> None:
