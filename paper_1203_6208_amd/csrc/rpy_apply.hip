@@ -40,9 +40,9 @@ template <> struct TileT<double> {
     {
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
-            const double2 v = *reinterpret_cast<const double2 *>(row + 32 * s + 2 * q);
-            a[2 * s] = v.x;
-            a[2 * s + 1] = v.y;
+            const double *p = row + 32 * s + 2 * q;
+            a[2 * s] = __builtin_nontemporal_load(p);
+            a[2 * s + 1] = __builtin_nontemporal_load(p + 1);
         }
     }
 };
@@ -53,11 +53,11 @@ template <> struct TileT<float> {
     {
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const float4 v = *reinterpret_cast<const float4 *>(row + 64 * s + 4 * q);
-            a[4 * s] = v.x;
-            a[4 * s + 1] = v.y;
-            a[4 * s + 2] = v.z;
-            a[4 * s + 3] = v.w;
+            const float *p = row + 64 * s + 4 * q;
+            a[4 * s] = __builtin_nontemporal_load(p);
+            a[4 * s + 1] = __builtin_nontemporal_load(p + 1);
+            a[4 * s + 2] = __builtin_nontemporal_load(p + 2);
+            a[4 * s + 3] = __builtin_nontemporal_load(p + 3);
         }
     }
 };
@@ -70,8 +70,12 @@ template <> struct TileT<uint16_t> {
     }
     __device__ static void load(const uint16_t *row, int q, acc_t a[12])
     {
-        const uint4 v = *reinterpret_cast<const uint4 *>(row + 8 * q);
-        const uint2 u = *reinterpret_cast<const uint2 *>(row + 128 + 4 * q);
+        typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+        typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+        const u4v v4 = __builtin_nontemporal_load(reinterpret_cast<const u4v *>(row + 8 * q));
+        const u2v v2 = __builtin_nontemporal_load(reinterpret_cast<const u2v *>(row + 128 + 4 * q));
+        const uint4 v = make_uint4(v4.x, v4.y, v4.z, v4.w);
+        const uint2 u = make_uint2(v2.x, v2.y);
         a[0] = bf(v.x, 0); a[1] = bf(v.x, 1);
         a[2] = bf(v.y, 0); a[3] = bf(v.y, 1);
         a[4] = bf(v.z, 0); a[5] = bf(v.z, 1);
@@ -346,13 +350,29 @@ constexpr int EPI_BEADS = 16;
 constexpr int EPI_SLICES = 64;
 template <int M>
 __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, int nbt, int nk,
-                                                     int rhs_cap, int j0,
+                                                     int rhs_cap, int j0, int staged,
                                                      const KVec *__restrict__ kvec,
                                                      const double *__restrict__ sfr,
                                                      const double *__restrict__ part,
-                                                     const double *__restrict__ tk, EpiArgs f)
+                                                     const double *__restrict__ tk_g, EpiArgs f)
 {
     __shared__ double red[16][3][EPI_BEADS];
+    // when `staged`, the wave vectors and this launch's 6 M values of tk per
+    // k are copied to LDS once per workgroup: [nk] KVec then [nk][M][6]
+    extern __shared__ double lds[];
+    const KVec *kv_s = staged ? reinterpret_cast<const KVec *>(lds) : kvec;
+    const double *tk_s = staged ? lds + 2 * nk : tk_g + (size_t)j0 * 6;
+    const int tk_ld = staged ? 6 * M : 6 * rhs_cap;
+    if (staged) {
+        KVec *kd = reinterpret_cast<KVec *>(lds);
+        for (int e = threadIdx.x; e < nk; e += blockDim.x) kd[e] = kvec[e];
+        double *td = lds + 2 * nk;
+        for (int e = threadIdx.x; e < nk * 6 * M; e += blockDim.x) {
+            const int k = e / (6 * M), r = e % (6 * M);
+            td[e] = tk_g[((size_t)k * rhs_cap + j0) * 6 + r];
+        }
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int bl = lane & 15, sub = lane >> 4;
     const int u = 4 * w + sub;
@@ -380,7 +400,7 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
     double cs = 1.0, sn = 0.0;
     int px = -(1 << 30), py = 0, pz = 0;
     for (int k = klo; k < khi; ++k) {
-        const KVec kv = kvec[k];
+        const KVec kv = kv_s[k];
         if (kv.nx == px && kv.ny == py && kv.nz == pz + 1) {
             const double c2 = cs * ezr - sn * ezi;
             sn = cs * ezi + sn * ezr;
@@ -391,12 +411,11 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
         px = kv.nx;
         py = kv.ny;
         pz = kv.nz;
+        const double *tt = tk_s + (size_t)k * tk_ld;
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const double *tt = tk + ((size_t)k * rhs_cap + j0 + j) * 6;
+        for (int j = 0; j < M; ++j)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) y[j][c] += cs * tt[c] + sn * tt[3 + c];
-        }
+            for (int c = 0; c < 3; ++c) y[j][c] += cs * tt[6 * j + c] + sn * tt[6 * j + 3 + c];
     }
     const double ya = f.scal ? f.scal[2] : 0.0, yb = f.scal ? f.scal[3] : 0.0;
 #pragma unroll
@@ -439,8 +458,12 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
 void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
 {
     const dim3 g((c.N + EPI_BEADS - 1) / EPI_BEADS), b(1024);
-    RPY_RHS_GROUPS(f.m, hipLaunchKernelGGL(k_kspace_epi<MC>, g, b, 0, s, c.N, c.n3, c.n3pad, c.nbt,
-                                           c.nk, c.rhs_cap, j0, c.kvec, c.sfr, c.part, c.tk, f));
+    RPY_RHS_GROUPS(f.m, {
+        const size_t lds = sizeof(double) * (size_t)c.nk * (2 + 6 * MC);
+        const int staged = lds <= 48 * 1024;
+        hipLaunchKernelGGL(k_kspace_epi<MC>, g, b, staged ? lds : 0, s, c.N, c.n3, c.n3pad, c.nbt,
+                           c.nk, c.rhs_cap, j0, staged, c.kvec, c.sfr, c.part, c.tk, f);
+    });
 }
 
 // ------------------------------------------------- Chebyshev coefficients
@@ -448,48 +471,60 @@ void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
 // scal[3] = (d_max + d_min)/(d_max - d_min), scal[8 + p] = c_p with
 //   c_p = (2/n) sum_{j=1..n} sqrt(h x_j + m) cos(p theta_j),
 //   theta_j = pi (j - 1/2)/n, x_j = cos theta_j, h = (d_max-d_min)/2, m = (d_max+d_min)/2.
-// rule = RPY_BOUNDS_PAPER derives the interval from du = D.U+ first.
-__global__ __launch_bounds__(256) void k_cheb_coeffs(int nbeads, int n, int rule, double C,
-                                                     double dmin, double dmax,
-                                                     const double *__restrict__ du,
-                                                     double *__restrict__ scal)
+// rule = RPY_BOUNDS_PAPER derives the interval from du = D.U+ first.  One
+// workgroup: a fixed-order tree reduction, then wave w sums the nodes of
+// coefficients p = w, w+16, ... with a lane-parallel sum.
+__global__ __launch_bounds__(1024) void k_cheb_coeffs(int nbeads, int n, int rule, double C,
+                                                      double dmin, double dmax,
+                                                      const double *__restrict__ du,
+                                                      double *__restrict__ scal)
 {
-    __shared__ double red[256];
+    __shared__ double red[1024];
     __shared__ double bounds[2];
+    const int tid = threadIdx.x;
     if (rule == RPY_BOUNDS_PAPER) {
         const int n3 = 3 * nbeads;
-        double s = 0.0;
-        for (int i = threadIdx.x; i < n3; i += blockDim.x) s += du[i];
-        red[threadIdx.x] = s;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int i = tid;
+        for (; i + 3 * 1024 < n3; i += 4 * 1024) {
+            s0 += du[i];
+            s1 += du[i + 1024];
+            s2 += du[i + 2048];
+            s3 += du[i + 3072];
+        }
+        for (; i < n3; i += 1024) s0 += du[i];
+        red[tid] = (s0 + s1) + (s2 + s3);
         __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        for (int h = 512; h > 0; h >>= 1) {
+            if (tid < h) red[tid] += red[tid + h];
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             const double lf = red[0] / n3;
             const double np6 = pow((double)nbeads, 0.6);
             const double lmax = 0.35 * np6 * lf;
             bounds[0] = lmax / (C * np6);
             bounds[1] = lmax;
         }
-    } else if (threadIdx.x == 0) {
+    } else if (tid == 0) {
         bounds[0] = dmin;
         bounds[1] = dmax;
     }
     __syncthreads();
     const double lo = bounds[0], hi = bounds[1];
     const double h = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
-    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    const int lane = tid & 63, w = tid >> 6;
+    for (int p = w; p < n; p += 16) {
         double s = 0.0;
-        for (int j = 1; j <= n; ++j) {
+        for (int j = 1 + lane; j <= n; j += 64) {
             const double u = (j - 0.5) / n;
-            const double fx = sqrt(h * cospi(u) + mid);
-            s += fx * cospi(p * u);
+            s += sqrt(h * cospi(u) + mid) * cospi(p * u);
         }
-        scal[8 + p] = 2.0 * s / n;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0) scal[8 + p] = 2.0 * s / n;
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         scal[0] = lo;
         scal[1] = hi;
         scal[2] = 2.0 / (hi - lo);
@@ -500,7 +535,7 @@ __global__ __launch_bounds__(256) void k_cheb_coeffs(int nbeads, int n, int rule
 void launch_cheb_coeffs(const Ctx &c, int n_cheb, int rule, double C, double dmin, double dmax,
                         const double *du, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cheb_coeffs, dim3(1), dim3(256), 0, s, c.N, n_cheb, rule, C, dmin,
+    hipLaunchKernelGGL(k_cheb_coeffs, dim3(1), dim3(1024), 0, s, c.N, n_cheb, rule, C, dmin,
                        dmax, du, c.scal);
 }
 

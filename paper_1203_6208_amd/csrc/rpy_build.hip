@@ -25,6 +25,7 @@ __global__ void k_wrap_tables(int N, double L, int nmax, const double *__restric
         s = s - floor(s);
         rt[3 * nu + i] = L * s;
         sfr[3 * nu + i] = s;
+        sfr[3 * nu + i] = s;
         double2 *tab = etab + (size_t)(3 * nu + i) * (nmax + 1);
         for (int j = 0; j <= nmax; ++j) {
             double sn, cs;

@@ -143,11 +143,13 @@ void launch_cell_list(const Ctx &c, double rcut, hipStream_t s)
 
 // Narrow-Gaussian excluded volume, minimum image (rcut < L/2):
 //   F_nu += (z*/d*^5) d exp(-|d|^2 / (2 d*^2)), d = r_nu - r_mu, |d| <= rcut.
-// One workgroup per home cell: the beads of the 27 surrounding cells are
-// staged in LDS (batches of EV_CAP); each wave takes home beads in turn and
-// its 64 lanes split the candidates; a fixed xor tree combines the lanes.
+// One workgroup per home cell.  The neighbour-cell offsets, the home beads
+// (in batches of 4 EV_HMAX) and the beads of the 27 surrounding cells (in
+// batches of EV_CAP) are staged in LDS by parallel loads; each wave then
+// takes home beads in turn and its 64 lanes split the candidates; a fixed
+// xor tree combines the lanes.
 constexpr int EV_CAP = 1024;
-constexpr int EV_HMAX = 8;   // home beads per wave held in registers per pass
+constexpr int EV_HMAX = 8;   // home beads per wave per batch
 __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double *__restrict__ rt,
                                                   const int *__restrict__ start,
                                                   const int *__restrict__ beads, double pref,
@@ -156,24 +158,25 @@ __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double
 {
     __shared__ double sx[EV_CAP], sy[EV_CAP], sz[EV_CAP];
     __shared__ int sid[EV_CAP];
-    __shared__ int nbr[27];
+    __shared__ double hx[4 * EV_HMAX], hy[4 * EV_HMAX], hz[4 * EV_HMAX];
+    __shared__ int hid[4 * EV_HMAX];
+    __shared__ int nbr_start[27];
     __shared__ int nbr_off[28];
     const int c = blockIdx.x;
     const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+    if (threadIdx.x < 27) {
+        const int q = threadIdx.x;
+        const int ox = q % 3 - 1, oy = (q / 3) % 3 - 1, oz = q / 9 - 1;
+        const int ex = (cx + ox + nc) % nc, ey = (cy + oy + nc) % nc, ez = (cz + oz + nc) % nc;
+        const int cc = (ez * nc + ey) * nc + ex;
+        const int st = start[cc];
+        nbr_start[q] = st;
+        nbr_off[q + 1] = start[cc + 1] - st;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        int q = 0, tot = 0;
-        for (int oz = -1; oz <= 1; ++oz)
-            for (int oy = -1; oy <= 1; ++oy)
-                for (int ox = -1; ox <= 1; ++ox) {
-                    const int ex = (cx + ox + nc) % nc, ey = (cy + oy + nc) % nc,
-                              ez = (cz + oz + nc) % nc;
-                    const int cc = (ez * nc + ey) * nc + ex;
-                    nbr[q] = cc;
-                    nbr_off[q] = tot;
-                    tot += start[cc + 1] - start[cc];
-                    ++q;
-                }
-        nbr_off[27] = tot;
+        nbr_off[0] = 0;
+        for (int q = 0; q < 27; ++q) nbr_off[q + 1] += nbr_off[q];
     }
     __syncthreads();
     const int hlo = start[c], nh = start[c + 1] - hlo;
@@ -181,6 +184,14 @@ __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double invL = 1.0 / L;
     for (int h0 = 0; h0 < nh; h0 += 4 * EV_HMAX) {
+        const int nhb = min(4 * EV_HMAX, nh - h0);
+        if (threadIdx.x < nhb) {
+            const int nu = beads[hlo + h0 + threadIdx.x];
+            hid[threadIdx.x] = nu;
+            hx[threadIdx.x] = rt[3 * nu];
+            hy[threadIdx.x] = rt[3 * nu + 1];
+            hz[threadIdx.x] = rt[3 * nu + 2];
+        }
         double acc[EV_HMAX][3];
 #pragma unroll
         for (int i = 0; i < EV_HMAX; ++i) acc[i][0] = acc[i][1] = acc[i][2] = 0.0;
@@ -191,7 +202,7 @@ __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double
                 const int g = b0 + e;
                 int q = 0;
                 while (nbr_off[q + 1] <= g) ++q;
-                const int mu = beads[start[nbr[q]] + (g - nbr_off[q])];
+                const int mu = beads[nbr_start[q] + (g - nbr_off[q])];
                 sid[e] = mu;
                 sx[e] = rt[3 * mu];
                 sy[e] = rt[3 * mu + 1];
@@ -200,10 +211,10 @@ __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < EV_HMAX; ++i) {
-                const int hi = h0 + 4 * i + w;
-                if (hi < nh) {
-                    const int nu = beads[hlo + hi];
-                    const double x = rt[3 * nu], y = rt[3 * nu + 1], z = rt[3 * nu + 2];
+                const int li = 4 * i + w;
+                if (li < nhb) {
+                    const int nu = hid[li];
+                    const double x = hx[li], y = hy[li], z = hz[li];
                     for (int e = lane; e < nb; e += 64) {
                         if (sid[e] == nu) continue;
                         double dx = x - sx[e], dy = y - sy[e], dz = z - sz[e];
@@ -222,7 +233,7 @@ __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double
         }
 #pragma unroll
         for (int i = 0; i < EV_HMAX; ++i) {
-            const int hi = h0 + 4 * i + w;
+            const int li = 4 * i + w;
             double f0 = acc[i][0], f1 = acc[i][1], f2 = acc[i][2];
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) {
@@ -230,13 +241,14 @@ __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double
                 f1 += __shfl_xor(f1, o);
                 f2 += __shfl_xor(f2, o);
             }
-            if (hi < nh && lane == 0) {
-                const int nu = beads[hlo + hi];
+            if (li < nhb && lane == 0) {
+                const int nu = hid[li];
                 F[3 * nu] += f0;
                 F[3 * nu + 1] += f1;
                 F[3 * nu + 2] += f2;
             }
         }
+        __syncthreads();   // hid/hx are rewritten by the next home batch
     }
 }
 
