@@ -29,6 +29,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes moved by one FP64 tile-product launch at N = 4000, from two
+# rocprofv3 counter runs (FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000, scale
+# factors calibrated on a 512 MiB device copy in the same process).  Valid only
+# for the kernel source it was measured on (sha256 of the product kernel's
+# source files); otherwise reported as null.
+TRAFFIC = {"src_sha256": "fa0af34b46958e20811dc216cc30badc8fb9dbd2f7231e3db8eb9b10312dd8b3",
+           "bytes_per_launch": 607749062}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 
@@ -158,6 +165,15 @@ def cpu_baseline(w, seconds):
                        f"(O(N))")}
 
 
+def measured_traffic():
+    import hashlib
+    src = b"".join(open(os.path.join(ROOT, "paper_1203_6208_amd", "csrc", f), "rb").read()
+                   for f in ("rpy_apply.hip", "rpy_internal.h"))
+    if hashlib.sha256(src).hexdigest() == TRAFFIC["src_sha256"]:
+        return TRAFFIC["bytes_per_launch"]
+    return None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -219,7 +235,7 @@ def main():
                                f"bound rule C={BOUNDS_C:g}, device Philox noise",
                    "n_beads": w.n, "n_cheb": w.nch, "box_l": w.L, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_symv<double,1> (symmetric tile product, FP64, m=1)",
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_us": sym["avg_us"], "launches": sym["launches"]},
