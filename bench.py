@@ -132,6 +132,40 @@ def form_errors(w, torch, rpy):
     return res
 
 
+def time_block(w, prec, reps, torch, rpy):
+    """sqrt(D) dW for a block of 16 dW vectors (N_Ch - 1 = 29 products of D
+    with 16 vectors; FP32/BF16 tiles go through the matrix-core block
+    kernel, FP64 through the vector-unit kernel 4 vectors at a time) on the
+    step's D and bounds."""
+    ctx = rpy.context_for(w, lowp=prec, max_rhs=16)
+    pos = torch.from_numpy(w.positions()).cuda()
+    dw16 = torch.from_numpy(w.noise(m=16)).cuda()
+    ctx.build(pos)
+    lo, hi = ctx.bounds(BOUNDS_C)
+    for _ in range(2):
+        ctx.sqrt_apply(dw16, w.nch, lo, hi, prec=prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.sqrt_apply(dw16, w.nch, lo, hi, prec=prec)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    rpy.rpy_profile_enable(ctx.handle, 64 * w.nch)
+    ctx.sqrt_apply(dw16, w.nch, lo, hi, prec=prec)
+    torch.cuda.synchronize()
+    n, ms = rpy.rpy_profile_read(ctx.handle, rpy.PROF_SYMV)
+    rpy.rpy_profile_enable(ctx.handle, 0)
+    nprod = w.nch - 1
+    n3 = 3 * w.n
+    esize = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+    tile_us = 1e3 * ms / nprod          # all tile-product launches of one product
+    gbs = n3 * (n3 + 1) // 2 * esize / (tile_us * 1e-6) / 1e9
+    del ctx
+    return {"ms_per_block": 1e3 * wall, "us_per_product": 1e6 * wall / nprod,
+            "tile_product_us": tile_us, "tile_product_launches": n // nprod,
+            "tile_product_GBs": gbs, "tile_product_hbm_frac": gbs / HBM_PEAK_GBS}
+
+
 def cpu_baseline(w, seconds):
     """Oracle on a bounded sample of one step: block rows of D (real space,
     self term, reciprocal sum over the full +-k set) for a subset of beads, and
@@ -219,6 +253,9 @@ def main():
                            / (pr2["tile_product"]["avg_us"] * 1e-6) / 1e9}
             del c2
             print(f"# {prec}: {forms[prec]}", file=sys.stderr, flush=True)
+        for prec in ("f64", "f32", "bf16"):
+            forms.setdefault(prec, {})["block_m16"] = time_block(w, prec, 5, torch, rpy)
+            print(f"# block m16 {prec}: {forms[prec]['block_m16']}", file=sys.stderr, flush=True)
         errs = form_errors(w, torch, rpy)
         for k, v in errs.items():
             forms.setdefault(k, {}).update(v)

@@ -194,6 +194,20 @@ def diffusion_rows(pos, rows, L, a, alpha, rc, n2max) -> np.ndarray:
     return D
 
 
+def real_space_rows(pos, rows, L, a, alpha, rc) -> np.ndarray:
+    """Block rows of the self term plus the real-space sum (eq. DFmodified,
+    first, second and last terms) for the listed beads: [3*len(rows), 3N]."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    rt = wrap(pos, L)
+    r = np.ascontiguousarray(np.asarray(rows, dtype=np.intc))
+    rp = r.ctypes.data_as(_ip)
+    D = np.zeros((3 * len(r), 3 * n))
+    _L().orc_real_space_rows(n, _ptr(rt), L, a, alpha, rc, len(r), rp, _ptr(D))
+    _L().orc_self_term_rows(n, a, alpha, len(r), rp, _ptr(D))
+    return D
+
+
 def matvec(D, V) -> np.ndarray:
     """D . V for V of shape [m, 3N] (or [3N])."""
     D = _f64(D)

@@ -19,6 +19,12 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+# Per-file additions.  The block-product kernels keep their MFMA accumulators
+# in ordinary VGPRs: with the default heuristic the loop-carried FP64
+# accumulators are copied to and from AGPRs around every MFMA batch.
+FILE_FLAGS = {
+    "rpy_block.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
 
 
 def _run(cmd):
@@ -36,7 +42,8 @@ def build(jobs: int = 4) -> str:
     for src in srcs:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-c", src, "-o", obj]
+        extra = FILE_FLAGS.get(os.path.basename(src), [])
+        cmd = [hipcc, *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-c", src, "-o", obj]
         print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))
         if len(procs) >= jobs:

@@ -25,7 +25,6 @@ __global__ void k_wrap_tables(int N, double L, int nmax, const double *__restric
         s = s - floor(s);
         rt[3 * nu + i] = L * s;
         sfr[3 * nu + i] = s;
-        sfr[3 * nu + i] = s;
         double2 *tab = etab + (size_t)(3 * nu + i) * (nmax + 1);
         for (int j = 0; j <= nmax; ++j) {
             double sn, cs;
@@ -41,6 +40,32 @@ void launch_wrap_tables(const Ctx &c, const double *pos, hipStream_t s)
     const int bs = 256;
     hipLaunchKernelGGL(k_wrap_tables, dim3((c.N + bs - 1) / bs), dim3(bs), 0, s, c.N, c.L,
                        c.nmax, pos, c.rt, c.sfr, c.etab, c.flags);
+}
+
+// Wrapped positions only; a non-finite coordinate raises flags[0] as above.
+__global__ void k_wrap_positions(int N, double L, const double *__restrict__ pos,
+                                 double *__restrict__ rt, int *__restrict__ flags)
+{
+    const int nu = blockIdx.x * blockDim.x + threadIdx.x;
+    if (nu >= N) return;
+    bool bad = false;
+    for (int i = 0; i < 3; ++i) {
+        double r = pos[3 * nu + i];
+        if (!isfinite(r)) {
+            bad = true;
+            r = 0.0;
+        }
+        const double s = r / L;
+        rt[3 * nu + i] = L * (s - floor(s));
+    }
+    if (bad) atomicOr(flags, 1);
+}
+
+void launch_wrap_positions(const Ctx &c, const double *pos, double *rt, hipStream_t s)
+{
+    const int bs = 256;
+    hipLaunchKernelGGL(k_wrap_positions, dim3((c.N + bs - 1) / bs), dim3(bs), 0, s, c.N, c.L, pos,
+                       rt, c.flags);
 }
 
 __device__ inline uint16_t to_bf16(double d)

@@ -30,6 +30,8 @@ struct rpy_ctx {
     double *Bv[2] = {nullptr, nullptr};  // [max_rhs][3N] Chebyshev vectors
     double *ddw = nullptr;    // [max_rhs][3N] D.dW
     double *acc = nullptr;    // [max_rhs][3N] scratch accumulator
+    // the phase matrix c.eph is valid for wrap generation eph_gen
+    uint64_t wrap_gen = 1, eph_gen = 0;
 };
 
 static thread_local char g_err[256];
@@ -139,6 +141,15 @@ static int validate(const rpy_params *p, int *n2max_out)
     return RPY_OK;
 }
 
+// Structure-factor partials: [nsfc][6 rhs_cap][nk] for the vector-unit
+// product, [nk/16 blocks][nchb][6 x 16][16] for the block product.
+static size_t sfpart_elems(const Ctx &c)
+{
+    const size_t a = (size_t)c.nsfc * 6 * c.rhs_cap * c.nk;
+    const size_t b = c.block ? (size_t)((c.nk + 15) / 16) * c.nchb * 6 * BLOCK_RHS * 16 : 0;
+    return a > b ? a : b;
+}
+
 template <typename T> static int dalloc(T **p, size_t n)
 {
     if (n == 0) n = 1;
@@ -157,7 +168,9 @@ extern "C" void rpy_destroy(rpy_ctx *x)
     if (!x) return;
     (void)hipDeviceSynchronize();
     Ctx &c = x->c;
-    void *bufs[] = {c.rt, c.etab, c.kvec, c.kcoef, c.tile_ij, c.d64, c.d32, c.d16, c.part,
+    void *bufs[] = {c.rt, c.rt_ev, c.eph, c.etab, c.kvec, c.kcoef, c.tile_ij, c.d64, c.d32,
+                    c.d16, c.part, c.xpk,
+                    c.vpk, c.part32, c.tkm,
                     c.sfpart, c.tk, c.sfr, c.work, c.scal, c.red, c.flags, c.cell_start,
                     c.cell_beads};
     for (void *b : bufs)
@@ -195,6 +208,8 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     c.lowp = p->lowp;
     c.max_rhs = p->max_rhs;
     c.rhs_cap = c.max_rhs > 2 ? c.max_rhs : 2;
+    c.block = c.lowp != RPY_PREC_F64 && c.max_rhs >= BLOCK_MIN_RHS;
+    if (c.block) c.rhs_cap = BLOCK_RHS;  // block kernels write all 16 columns
     c.pc = make_pair_const(c.L, c.a, c.alpha, c.rc);
     c.nbt = (c.N + TB - 1) / TB;
     c.ntiles = c.nbt * (c.nbt + 1) / 2;
@@ -222,6 +237,8 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
                 kc.push_back(KCoef{2.0 * mk, kx / k, ky / k, kz / k});
             }
     c.nk = (int)kv.size();
+    c.nk4 = (c.nk + 3) / 4 * 4;
+    c.nchb = c.nsfc < 16 ? c.nsfc : 16;
 
     std::vector<int2> tij;
     for (int I = 0; I < c.nbt; ++I)
@@ -233,13 +250,19 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     c.work_elems = 2 * nv + 2 * nv + nv + nv + 2 * mv + mv + mv;
     const int ncell_cap = 64;
     const size_t ncells_cap = (size_t)ncell_cap * ncell_cap * ncell_cap;
-    if ((rc = dalloc(&c.rt, nv)) || (rc = dalloc(&c.etab, nv * (c.nmax + 1))) ||
+    if ((rc = dalloc(&c.rt, nv)) || (rc = dalloc(&c.rt_ev, nv)) || (rc = dalloc(&c.etab, nv * (c.nmax + 1))) ||
         (rc = dalloc(&c.kvec, kv.size())) || (rc = dalloc(&c.kcoef, kc.size())) ||
         (rc = dalloc(&c.tile_ij, tij.size())) || (rc = dalloc(&c.d64, te)) ||
         (c.lowp == RPY_PREC_F32 && (rc = dalloc(&c.d32, te))) ||
         (c.lowp == RPY_PREC_BF16 && (rc = dalloc(&c.d16, te))) ||
         (rc = dalloc(&c.part, (size_t)c.nbt * c.rhs_cap * c.n3pad)) ||
-        (rc = dalloc(&c.sfpart, (size_t)c.nsfc * 6 * c.rhs_cap * c.nk)) ||
+        (c.block && ((rc = dalloc(reinterpret_cast<uint32_t **>(&c.xpk),
+                                  (size_t)c.n3pad * BLOCK_RHS)) ||
+                     (rc = dalloc(&c.vpk, (size_t)c.n3pad * BLOCK_RHS)) ||
+                     (rc = dalloc(&c.part32, (size_t)c.nbt * BLOCK_RHS * c.n3pad)) ||
+                     (rc = dalloc(&c.tkm, (size_t)c.nk4 * 6 * BLOCK_RHS)) ||
+                     (rc = dalloc(&c.eph, (size_t)(c.N + 3) / 4 * ((c.nk + 15) / 16 * 16) * 4)))) ||
+        (rc = dalloc(&c.sfpart, sfpart_elems(c))) ||
         (rc = dalloc(&c.tk, (size_t)6 * c.rhs_cap * c.nk)) ||
         (rc = dalloc(&c.sfr, nv)) ||
         (rc = dalloc(&c.work, c.work_elems)) || (rc = dalloc(&c.scal, 8 + MAX_NCHEB)) ||
@@ -262,7 +285,8 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
         (e = hipMemcpy(c.kcoef, kc.data(), kc.size() * sizeof(KCoef), hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(c.tile_ij, tij.data(), tij.size() * sizeof(int2), hipMemcpyHostToDevice)) ||
         (e = hipMemset(c.flags, 0, 4 * sizeof(int))) ||
-        (e = hipMemset(c.d64, 0, te * sizeof(double)))) {
+        (e = hipMemset(c.d64, 0, te * sizeof(double))) ||
+        (c.block && (e = hipMemset(c.tkm, 0, (size_t)c.nk4 * 6 * BLOCK_RHS * sizeof(double))))) {
         rc = hip_fail(e, "rpy_create upload");
         rpy_destroy(x);
         return rc;
@@ -303,6 +327,7 @@ extern "C" int rpy_ewald_build(rpy_ctx *x, const double *pos, void *stream)
 {
     if (!x || !pos) return RPY_EINVAL;
     launch_wrap_tables(x->c, pos, S(stream));
+    ++x->wrap_gen;
     {
         ProfScope ps(x, RPY_PROF_BUILD, S(stream));
         launch_build_tiles(x->c, S(stream));
@@ -318,11 +343,30 @@ static bool prec_ok(const Ctx &c, int prec)
 
 // One product of the full periodic D with the m vectors v; `f` selects the
 // epilogue.  Three kernels: tile product (+ structure-factor partials of v),
-// structure-factor reduction, reciprocal back-projection + epilogue.
+// structure-factor reduction, reciprocal back-projection + epilogue.  With
+// FP32 / BF16 tiles and 5..16 vectors the block path runs instead: matrix-core
+// tile product, FP64 matrix-core structure factors and back-projection.
 static void product(rpy_ctx *x, const double *v, int m, int prec, const EpiArgs &f,
                     hipStream_t s)
 {
     const Ctx &c = x->c;
+    if (c.block && prec != RPY_PREC_F64 && m >= BLOCK_MIN_RHS) {
+        {
+            ProfScope ps(x, RPY_PROF_SYMV, s);
+            launch_block_tiles(c, prec, v, m, s);
+        }
+        {
+            ProfScope ps(x, RPY_PROF_KSPACE, s);
+            if (x->eph_gen != x->wrap_gen) {   // positions changed since the last phases
+                launch_block_phases(c, s);
+                x->eph_gen = x->wrap_gen;
+            }
+            launch_block_sf(c, s);
+        }
+        ProfScope ps(x, RPY_PROF_EPI, s);
+        launch_block_epi(c, f, s);
+        return;
+    }
     for (int j0 = 0; j0 < m;) {
         const int mc = (m - j0) >= 4 ? 4 : (m - j0) >= 2 ? 2 : 1;
         ProfScope ps(x, RPY_PROF_SYMV, s);
@@ -412,16 +456,17 @@ extern "C" int rpy_bounds(rpy_ctx *x, double C, double *d_min, double *d_max, vo
     return fl ? RPY_ENONFINITE : RPY_OK;
 }
 
-static int forces(rpy_ctx *x, const double *pos, double zstar, double dstar, double rcut,
-                  double *F, hipStream_t s)
+// Springs plus excluded volume; `rt` holds the wrapped positions of `pos`.
+static int forces(rpy_ctx *x, const double *pos, const double *rt, double zstar, double dstar,
+                  double rcut, double *F, hipStream_t s)
 {
     Ctx &c = x->c;
     launch_spring_forces(c, pos, F, s);
     if (zstar > 0) {
         const int nc = (int)floor(c.L / rcut);
         c.ncell = nc >= 3 ? (nc > 64 ? 64 : nc) : 0;
-        launch_cell_list(c, rcut, s);
-        launch_ev_forces(c, zstar, dstar, rcut, F, s);
+        launch_cell_list(c, rt, rcut, s);
+        launch_ev_forces(c, rt, zstar, dstar, rcut, F, s);
     }
     return RPY_OK;
 }
@@ -443,8 +488,9 @@ extern "C" int rpy_forces(rpy_ctx *x, const double *pos, double zstar, double ds
     int rc = check_ev(x->c, zstar, dstar, rcut);
     if (rc) return rc;
     hipStream_t s = S(stream);
-    if (zstar > 0) launch_wrap_tables(x->c, pos, s);
-    forces(x, pos, zstar, dstar, rcut, out, s);
+    // its own wrapped copy: the tables of the built D stay untouched
+    if (zstar > 0) launch_wrap_positions(x->c, pos, x->c.rt_ev, s);
+    forces(x, pos, x->c.rt_ev, zstar, dstar, rcut, out, s);
     return check_launch("rpy_forces");
 }
 
@@ -472,7 +518,8 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
     {
         ProfScope ps(x, RPY_PROF_OTHER, s);
         launch_wrap_tables(c, pos, s);
-        forces(x, pos, bp->ev_zstar, bp->ev_dstar, bp->ev_rcut, x->F, s);
+        ++x->wrap_gen;
+        forces(x, pos, c.rt, bp->ev_zstar, bp->ev_dstar, bp->ev_rcut, x->F, s);
     }
     {
         ProfScope ps(x, RPY_PROF_BUILD, s);

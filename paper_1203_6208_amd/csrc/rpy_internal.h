@@ -203,7 +203,8 @@ struct Ctx {
     int n3pad;         // nbt * TS
     int nsfc;          // structure-factor bead chunks (SF_BEADS beads each)
     // device buffers
-    double *rt = nullptr;        // wrapped positions [N][3]
+    double *rt = nullptr;        // wrapped positions [N][3] of the built D
+    double *rt_ev = nullptr;     // wrapped positions for stand-alone force calls
     double *sfr = nullptr;       // fractional coordinates s = r/L - floor(r/L) [N][3]
     double2 *etab = nullptr;     // phases [N][3][nmax+1]
     KVec *kvec = nullptr;        // [nk]
@@ -213,7 +214,16 @@ struct Ctx {
     float *d32 = nullptr;
     uint16_t *d16 = nullptr;
     double *part = nullptr;      // [nbt][rhs_cap][n3pad] tile-column partials
-    double *sfpart = nullptr;    // [nsfc][6*rhs_cap][nk] structure-factor partials
+    // block products (FP32 / BF16 tiles, up to 16 vectors on the matrix cores)
+    bool block = false;          // enabled: lowp tiles and max_rhs >= BLOCK_MIN_RHS
+    int nchb;                    // bead chunks of the block structure factors
+    int nk4;                     // nk rounded up to a multiple of 4
+    void *xpk = nullptr;         // packed low-precision right-hand sides (n3pad x 16 x 4 bytes)
+    double *vpk = nullptr;       // the same vectors in FP64, [n3pad][16]
+    float *part32 = nullptr;     // [nbt][n3pad/16][16 vectors][16 rows] FP32 tile partials
+    double *tkm = nullptr;       // [nk4][6][16] 2 m(k) P_k (C_k, S_k), rows >= nk zero
+    double2 *eph = nullptr;      // [ceil(N/4)][nk16][4] e^{i k.r_mu} of the wrapped positions
+    double *sfpart = nullptr;    // structure-factor partials (layouts in rpy_capi.hip)
     double *tk = nullptr;        // [nk][rhs_cap][6] 2 m(k) P_k (C_k, S_k)
     double *work = nullptr;      // vectors, see capi
     double *scal = nullptr;      // scalars: [0]=dmin [1]=dmax [2]=ya [3]=yb [8..]=coeffs
@@ -230,6 +240,8 @@ struct Ctx {
 // ------------------------------------------------------------ launchers
 // build
 void launch_wrap_tables(const Ctx &c, const double *pos, hipStream_t s);
+// wrapped positions only (into `rt`), for forces of positions other than D's
+void launch_wrap_positions(const Ctx &c, const double *pos, double *rt, hipStream_t s);
 void launch_build_tiles(const Ctx &c, hipStream_t s);
 void launch_dense_copy(const Ctx &c, double *out, hipStream_t s);
 // products: the tile-product kernel also computes the structure-factor
@@ -249,6 +261,18 @@ struct EpiArgs {
     const double *scal;    // device scalars (ya, yb, coeffs)
 };
 void launch_symv(const Ctx &c, int prec, const double *v, int j0, int mc, hipStream_t s);
+// FP32 / BF16 tiles, up to 16 vectors at once on the matrix cores; same
+// outputs (part, sfpart) as launch_symv over the vectors j0 .. j0 + mc - 1.
+// Block product D.V for m <= 16 vectors (c.block): the tile product on the
+// matrix cores (FP32 partials), the FP64 matrix-core structure factors and
+// their reduction to tkm, and the FP64 matrix-core back-projection fused with
+// the partial sum and the epilogue `f`.
+void launch_block_tiles(const Ctx &c, int prec, const double *v, int m, hipStream_t s);
+void launch_block_phases(const Ctx &c, hipStream_t s);   // eph from the current tables
+void launch_block_sf(const Ctx &c, hipStream_t s);
+void launch_block_epi(const Ctx &c, const EpiArgs &f, hipStream_t s);
+constexpr int BLOCK_MIN_RHS = 5;   // products with at least this many vectors use it
+constexpr int BLOCK_RHS = 16;
 void launch_sf_reduce(const Ctx &c, int m, hipStream_t s);
 void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s);
 void launch_cheb_coeffs(const Ctx &c, int n_cheb, int rule, double C, double dmin,
@@ -259,9 +283,9 @@ void launch_fill(double *p, double v, size_t n, hipStream_t s);
 void launch_copy(double *dst, const double *src, size_t n, hipStream_t s);
 // step
 void launch_spring_forces(const Ctx &c, const double *pos, double *F, hipStream_t s);
-void launch_cell_list(const Ctx &c, double rcut, hipStream_t s);
-void launch_ev_forces(const Ctx &c, double zstar, double dstar, double rcut, double *F,
-                      hipStream_t s);
+void launch_cell_list(const Ctx &c, const double *rt, double rcut, hipStream_t s);
+void launch_ev_forces(const Ctx &c, const double *rt, double zstar, double dstar, double rcut,
+                      double *F, hipStream_t s);
 void launch_noise(double *out, int64_t count, uint64_t seed, uint64_t step, double dt,
                   hipStream_t s);
 void launch_philox(const uint32_t *ck, uint32_t *out, int64_t n, hipStream_t s);

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start
     }
 }
 
-void launch_cell_list(const Ctx &c, double rcut, hipStream_t s)
+void launch_cell_list(const Ctx &c, const double *rt, double rcut, hipStream_t s)
 {
     (void)rcut;
     const int nc = c.ncell;
@@ -133,10 +133,10 @@ void launch_cell_list(const Ctx &c, double rcut, hipStream_t s)
     const int ncells = nc * nc * nc;
     int *count = reinterpret_cast<int *>(c.cell_start) + ncells + 1;  // cursor area
     hipLaunchKernelGGL(k_cell_zero, dim3((ncells + 255) / 256), dim3(256), 0, s, ncells, count);
-    hipLaunchKernelGGL(k_cell_count, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, c.L, nc, c.rt,
+    hipLaunchKernelGGL(k_cell_count, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, c.L, nc, rt,
                        count);
     hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, ncells, count, c.cell_start);
-    hipLaunchKernelGGL(k_cell_fill, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, c.L, nc, c.rt,
+    hipLaunchKernelGGL(k_cell_fill, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, c.L, nc, rt,
                        c.cell_start, count, c.cell_beads);
     hipLaunchKernelGGL(k_cell_sort, dim3(ncells), dim3(256), 0, s, c.cell_start, c.cell_beads);
 }
@@ -279,17 +279,17 @@ __global__ void k_ev_pairs(int N, double L, const double *__restrict__ rt, doubl
     F[3 * nu + 2] += f2;
 }
 
-void launch_ev_forces(const Ctx &c, double zstar, double dstar, double rcut, double *F,
-                      hipStream_t s)
+void launch_ev_forces(const Ctx &c, const double *rt, double zstar, double dstar, double rcut,
+                      double *F, hipStream_t s)
 {
     const double d2 = dstar * dstar;
     const double pref = zstar / (d2 * d2 * dstar);
     if (c.ncell >= 3) {
         const int ncells = c.ncell * c.ncell * c.ncell;
-        hipLaunchKernelGGL(k_ev_cells, dim3(ncells), dim3(256), 0, s, c.L, c.ncell, c.rt,
+        hipLaunchKernelGGL(k_ev_cells, dim3(ncells), dim3(256), 0, s, c.L, c.ncell, rt,
                            c.cell_start, c.cell_beads, pref, 1.0 / (2.0 * d2), rcut * rcut, F);
     } else {
-        hipLaunchKernelGGL(k_ev_pairs, dim3((c.N + 127) / 128), dim3(128), 0, s, c.N, c.L, c.rt,
+        hipLaunchKernelGGL(k_ev_pairs, dim3((c.N + 127) / 128), dim3(128), 0, s, c.N, c.L, rt,
                            pref, 1.0 / (2.0 * d2), rcut * rcut, F);
     }
 }
