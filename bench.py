@@ -29,13 +29,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes moved by one FP64 tile-product launch at N = 4000, from two
-# rocprofv3 counter runs (FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000, scale
-# factors calibrated on a 512 MiB device copy in the same process).  Valid only
-# for the kernel source it was measured on (sha256 of the product kernel's
-# source files); otherwise reported as null.
-TRAFFIC = {"src_sha256": "fa0af34b46958e20811dc216cc30badc8fb9dbd2f7231e3db8eb9b10312dd8b3",
-           "bytes_per_launch": 607749062}
+# HBM bytes moved by one tile-product launch at N = 4000, from two rocprofv3
+# counter runs (FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000, scale factors
+# calibrated on 1 GiB device copies in the same process).  Valid only for the
+# kernel source they were measured on (sha256 of the kernel's source files);
+# otherwise reported as null.
+TRAFFIC = {"src_sha256": "9bd0f334b875f7a45214a4edc8282700c01cd7333a6a03db0a49431671ac41a2",
+           "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
+           "bytes_per_launch": 607757516}
+TRAFFIC_BLOCK = {"src_sha256": "f0f3bbb8ce13c8c4b7b0d02395885f53e199e4c8260166a65893acf34eef528b",
+                 "files": ("rpy_block.hip", "rpy_internal.h"),
+                 "bytes_per_launch": {"f32": 312432364 + 48771072, "bf16": 159657310 + 48771072}}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 
@@ -134,9 +138,11 @@ def form_errors(w, torch, rpy):
 
 def time_block(w, prec, reps, torch, rpy):
     """sqrt(D) dW for a block of 16 dW vectors (N_Ch - 1 = 29 products of D
-    with 16 vectors; FP32/BF16 tiles go through the matrix-core block
-    kernel, FP64 through the vector-unit kernel 4 vectors at a time) on the
-    step's D and bounds."""
+    with 16 vectors) on the step's D and bounds.  FP32/BF16 tiles go through
+    the matrix-core block product (tile kernel with the vector packing, FP64
+    structure factors and their reduction, FP64 back-projection + epilogue);
+    FP64 through the vector-unit kernels 4 vectors at a time.  Per-stage times
+    come from HIP event pairs on the library's stream."""
     ctx = rpy.context_for(w, lowp=prec, max_rhs=16)
     pos = torch.from_numpy(w.positions()).cuda()
     dw16 = torch.from_numpy(w.noise(m=16)).cuda()
@@ -153,17 +159,22 @@ def time_block(w, prec, reps, torch, rpy):
     rpy.rpy_profile_enable(ctx.handle, 64 * w.nch)
     ctx.sqrt_apply(dw16, w.nch, lo, hi, prec=prec)
     torch.cuda.synchronize()
-    n, ms = rpy.rpy_profile_read(ctx.handle, rpy.PROF_SYMV)
-    rpy.rpy_profile_enable(ctx.handle, 0)
     nprod = w.nch - 1
+    stage = {}
+    for kind, nm in ((rpy.PROF_SYMV, "tile_product"), (rpy.PROF_KSPACE, "structure_factors"),
+                     (rpy.PROF_EPI, "back_projection_epilogue")):
+        n, ms = rpy.rpy_profile_read(ctx.handle, kind)
+        stage[nm + "_us"] = 1e3 * ms / nprod
+    rpy.rpy_profile_enable(ctx.handle, 0)
     n3 = 3 * w.n
     esize = {"f64": 8, "f32": 4, "bf16": 2}[prec]
-    tile_us = 1e3 * ms / nprod          # all tile-product launches of one product
-    gbs = n3 * (n3 + 1) // 2 * esize / (tile_us * 1e-6) / 1e9
+    gbs = n3 * (n3 + 1) // 2 * esize / (stage["tile_product_us"] * 1e-6) / 1e9
     del ctx
     return {"ms_per_block": 1e3 * wall, "us_per_product": 1e6 * wall / nprod,
-            "tile_product_us": tile_us, "tile_product_launches": n // nprod,
-            "tile_product_GBs": gbs, "tile_product_hbm_frac": gbs / HBM_PEAK_GBS}
+            **stage, "tile_product_GBs": gbs, "tile_product_hbm_frac": gbs / HBM_PEAK_GBS,
+            "tile_product_traffic": (measured_traffic(TRAFFIC_BLOCK, prec)
+                                     if prec in ("f32", "bf16") else None),
+            "vector_products_per_s": 16 * nprod / wall}
 
 
 def cpu_baseline(w, seconds):
@@ -199,13 +210,13 @@ def cpu_baseline(w, seconds):
                        f"(O(N))")}
 
 
-def measured_traffic():
+def measured_traffic(t=TRAFFIC, key=None):
     import hashlib
     src = b"".join(open(os.path.join(ROOT, "paper_1203_6208_amd", "csrc", f), "rb").read()
-                   for f in ("rpy_apply.hip", "rpy_internal.h"))
-    if hashlib.sha256(src).hexdigest() == TRAFFIC["src_sha256"]:
-        return TRAFFIC["bytes_per_launch"]
-    return None
+                   for f in t["files"])
+    if hashlib.sha256(src).hexdigest() != t["src_sha256"]:
+        return None
+    return t["bytes_per_launch"] if key is None else t["bytes_per_launch"][key]
 
 
 def main():

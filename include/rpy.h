@@ -65,7 +65,9 @@ typedef struct {
     int32_t lowp;      /* low-precision copy of D kept by rpy_ewald_build:
                           RPY_PREC_F64 (none), RPY_PREC_F32 or RPY_PREC_BF16 */
     int32_t max_rhs;   /* largest m accepted by rpy_apply/chebyshev_sqrt_apply
-                          (1..16) */
+                          (1..16); with lowp FP32/BF16 and max_rhs >= 5 the
+                          context also holds the buffers of the matrix-core
+                          block product (about 100 MB at N = 4000) */
     int32_t reserved;
     double box_l;
     double a;
@@ -103,8 +105,12 @@ int rpy_ewald_build(rpy_ctx *c, const double *pos, void *stream);
  * aliased), D being the full periodic diffusion tensor of the last build:
  * the stored real-space part in arithmetic `prec` (RPY_PREC_*; FP32/BF16 need
  * the matching lowp copy) plus the reciprocal-space sum in FP64 (eq.
- * DFmodified).  Errors: RPY_EINVAL (m outside 1..max_rhs, prec not built,
- * null pointers). */
+ * DFmodified).  With FP32/BF16 and 5 <= m <= 16 the real-space part runs on
+ * the matrix cores with FP32 accumulation inside each 64-bead tile (BF16:
+ * the vectors enter as a hi + lo BF16 pair, so only D is rounded to BF16);
+ * the reciprocal sum and the sums over tiles stay FP64.  Results are
+ * deterministic run to run.  Errors: RPY_EINVAL (m outside 1..max_rhs, prec
+ * not built, null pointers). */
 int rpy_apply(rpy_ctx *c, const double *v, double *out, int m, int prec,
               void *stream);
 
@@ -176,7 +182,9 @@ int rpy_real_space_dense(rpy_ctx *c, double *out, void *stream);
 int rpy_observables(rpy_ctx *c, const double *pos, double *re2, double *rg2,
                     void *stream);
 
-/* Forces used by bd_step for the given positions: out[N][3] (device). */
+/* Forces used by bd_step for the given positions: out[N][3] (device).  The
+ * positions are wrapped into a separate buffer, so the tables of the last
+ * build (and the reciprocal sum of later products) are unaffected. */
 int rpy_forces(rpy_ctx *c, const double *pos, double zstar, double dstar,
                double rcut, double *out, void *stream);
 

@@ -14,8 +14,9 @@
 //      chunk sum and 2 m(k) (I - khat khat) (eq. DF, third term, evaluated
 //      per product).
 //   4. k_block_epi: the back-projection sum_k (cos, sin)(k.r_nu) T_k as an
-//      FP64 matrix-core product, plus the fixed-order sum of the tile
-//      partials, plus the recurrence step.
+//      FP64 matrix-core product, plus the tile partials (summed in a fixed
+//      order by extra workgroups of the k_block_sf launch), plus the
+//      recurrence step.
 // The reciprocal sum and the recurrence are FP64 throughout.
 //
 // Tile product: each wave owns one stored tile A = A_IJ (192 x 192, I <= J):
@@ -373,11 +374,51 @@ struct SfLd {
 // The streamed operands are not declared __restrict__: loads the compiler may
 // treat as invariant get rematerialised at their use, which undoes the
 // prefetch.
-__global__ __launch_bounds__(256) void k_block_sf(int nk, int nk16, int nq, int cq, int rhs_cap,
+// Workgroups past the structure-factor grid (blockIdx.x >= nkb) sum the
+// tile partials instead, 16 beads each (3 row blocks of 16 rows x 16
+// vectors, contiguous per slot K): 16 slots per batch of independent loads,
+// summed pairwise inside a batch and batch after batch in K order, into
+// ypart[j][row].  This HBM stream overlaps the matrix-core work.
+__device__ inline void block_part_sum(int b, int N, int n3, int n3pad, int m, int nslot,
+                                      const float *__restrict__ part, double *__restrict__ ypart)
+{
+    const int nu0 = 16 * b, nb = min(16, N - nu0);
+    const int nrb = n3pad / 16;
+    for (int o = threadIdx.x; o < BLOCK_RHS * 48; o += blockDim.x) {
+        const int rbl = o >> 8, j = (o >> 4) & 15, rr = o & 15;
+        const int r = 16 * rbl + rr;     // row of the 48
+        if (r >= 3 * nb || j >= m) continue;
+        const float *pp = part + (size_t)(3 * b + rbl) * 256 + 16 * j + rr;
+        const size_t ks = (size_t)nrb * 256;
+        double y = 0.0;
+        int K = 0;
+        for (; K + 16 <= nslot; K += 16) {
+            float q[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) q[u] = pp[(K + u) * ks];
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = (double)q[2 * u] + (double)q[2 * u + 1];
+            y += ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+        }
+        for (; K < nslot; ++K) y += (double)pp[K * ks];
+        ypart[(size_t)j * n3 + 3 * nu0 + r] = y;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_block_sf(int nk, int nk16, int nq, int cq, int nkb,
+                                                  int N, int n3, int n3pad, int m, int nslot,
                                                   const double2 *eph, const double *vpk,
-                                                  double *sfpart)
+                                                  double *sfpart,
+                                                  const float *__restrict__ part,
+                                                  double *__restrict__ ypart)
 {
     __shared__ d4v red[SF_WAVES - 1][6][64];
+    if ((int)blockIdx.x >= nkb) {
+        const int b = (blockIdx.x - nkb) + blockIdx.y * (gridDim.x - nkb);
+        if (16 * b < N) block_part_sum(b, N, n3, n3pad, m, nslot, part, ypart);
+        return;
+    }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 15, g = lane >> 4;
     const int k0 = blockIdx.x * 16, ch = blockIdx.y;
@@ -483,13 +524,18 @@ __global__ void k_block_sf_reduce(int nk, int nch, const KCoef *__restrict__ kco
     d[2 * BLOCK_RHS] = kc.w * (t2 - kc.hz * h);
 }
 
-void launch_block_sf(const Ctx &c, hipStream_t s)
+void launch_block_sf(const Ctx &c, int m, hipStream_t s)
 {
     const int nq = (c.N + 3) / 4;
     const int cq = (nq + c.nchb - 1) / c.nchb;
-    hipLaunchKernelGGL(k_block_sf, dim3((c.nk + 15) / 16, c.nchb), dim3(64 * SF_WAVES), 0, s,
-                       c.nk, (c.nk + 15) / 16 * 16, nq, cq, c.rhs_cap, c.eph, c.vpk,
-                       c.sfpart);
+    const int nkb = (c.nk + 15) / 16;
+    // grid x: nkb structure-factor blocks, then ceil(npg / nchb) part-sum
+    // workgroups per grid row (npg = 16-bead groups)
+    const int npg = (c.N + 15) / 16;
+    const int px = (npg + c.nchb - 1) / c.nchb;
+    hipLaunchKernelGGL(k_block_sf, dim3(nkb + px, c.nchb), dim3(64 * SF_WAVES), 0, s, c.nk,
+                       (c.nk + 15) / 16 * 16, nq, cq, nkb, c.N, c.n3, c.n3pad, m, c.nbt, c.eph,
+                       c.vpk, c.sfpart, c.part32, c.ypart);
     const int nt = (c.nk + 15) / 16 * 2 * BLOCK_RHS * 16;
     hipLaunchKernelGGL(k_block_sf_reduce, dim3((nt + 255) / 256), dim3(256), 0, s, c.nk, c.nchb,
                        c.kcoef, c.sfpart, c.tkm);
@@ -498,39 +544,36 @@ void launch_block_sf(const Ctx &c, hipStream_t s)
 // ------------------------------ back-projection + partial sum + epilogue
 // Workgroup: 16 beads nu0 .. nu0 + 15, EPI_W waves; wave w takes the
 // wave-vector steps w, w + EPI_W, ... (4 wave vectors each).  Lane (g, i)
-// holds the phase of bead nu0 + i and k = 4 step + g (A operand: row = bead,
-// inner = k) and T[k][3 half + c][j = i] (B operand; tkm rows >= nk are
+// holds the phase of bead nu0 + i and k = 4 step + g (A operand: row =
+// bead, inner = k) and T[k][3 half + c][j = i] (B operand; tkm rows >= nk are
 // zero), loaded 3 steps ahead; six FP64 MFMAs per step add
 //   sum_k cos(k.r) Tc + sin(k.r) Ts,  c = 0..2.
-// The waves are summed in a fixed order in LDS; the workgroup's threads sum
-// the tile partials over the slots K; thread (j, bead) adds the
-// two and applies the epilogue of f.mode (as in k_kspace_epi).
+// The waves are summed in a fixed order in LDS; thread (j, bead) adds the
+// summed tile partials ypart and applies the epilogue of f.mode (as in
+// k_kspace_epi).
 constexpr int EPI_W = 8;
 struct EpiLd {
     double2 e;
     double t[6];
 };
-__global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int n3pad, int nk4,
-                                                          int nslot, int nk16,
+__global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int nk4, int nk16,
                                                           const double2 *eph, const double *tkm,
-                                                          const float *__restrict__ part,
+                                                          const double *__restrict__ ypart,
                                                           EpiArgs f)
 {
     __shared__ double red[EPI_W][3][16][17];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 15, g = lane >> 4;
     const int nu0 = blockIdx.x * 16;
-    const int nu = nu0 + i;
-    const bool live = nu < N;
     // dead lanes read a zero entry of the last quad (phases of mu >= N are 0)
-    const int nus = min(nu, ((N + 3) / 4) * 4 - 1);
+    const int nus = min(nu0 + i, ((N + 3) / 4) * 4 - 1);
     const double2 *ep = eph + (size_t)(nus >> 2) * nk16 * 4 + (nus & 3);
     d4v acc[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[c] = d4v{0.0, 0.0, 0.0, 0.0};
     const int nst = nk4 / 4;
     // Branch-free (see k_block_sf): a step past the end is loaded from a
-    // valid row and never consumed; phases of k >= nk are stored as zero.
+    // valid row and consumes a zero phase; phases of k >= nk are zero.
     auto fetch = [&](int st, EpiLd &d) {
         const int k = 4 * min(st, nst - 1) + g;
         d.e = ep[(size_t)k * 4];
@@ -538,7 +581,6 @@ __global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int n3p
 #pragma unroll
         for (int q = 0; q < 6; ++q) d.t[q] = tr[q * BLOCK_RHS];
     };
-    // Ring of 4 buffers in fixed registers, as in k_block_sf.
     auto use = [&](const EpiLd &d, int st) {
         const bool on = st < nst;
         const double c = on ? d.e.x : 0.0, sn = on ? d.e.y : 0.0;
@@ -548,6 +590,7 @@ __global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int n3p
             acc[cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(sn, d.t[3 + cc], acc[cc], 0, 0, 0);
         }
     };
+    // ring of 4 buffers in fixed registers, as in k_block_sf
     constexpr int S = EPI_W;
     EpiLd b0, b1, b2, b3;
     fetch(w, b0);
@@ -572,47 +615,19 @@ __global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int n3p
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int e = 0; e < 4; ++e) red[w][c][g + 4 * e][i] = acc[c][e];
-    // Tile partials: the workgroup's 48 rows (3 row blocks of 16) x 16
-    // vectors, contiguous per slot K, over all 512 threads; 16 slots per
-    // batch of independent loads, summed pairwise inside a batch and batch
-    // after batch in K order.
-    __shared__ double psum[BLOCK_RHS][48];
-    const int nb = min(16, N - nu0);
-    const int nrb = n3pad / 16;
-    for (int o = threadIdx.x; o < BLOCK_RHS * 48; o += blockDim.x) {
-        const int rbl = o >> 8, j = (o >> 4) & 15, rr = o & 15;
-        const int r = 16 * rbl + rr;     // row of the workgroup's 48
-        double y = 0.0;
-        if (r < 3 * nb && j < f.m) {
-            const float *pp = part + (size_t)(3 * (nu0 / 16) + rbl) * 256 + 16 * j + rr;
-            const size_t ks = (size_t)nrb * 256;
-            int K = 0;
-            for (; K + 16 <= nslot; K += 16) {
-                float q[16];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) q[u] = pp[(K + u) * ks];
-                double t[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) t[u] = (double)q[2 * u] + (double)q[2 * u + 1];
-                y += ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
-            }
-            for (; K < nslot; ++K) y += (double)pp[K * ks];
-        }
-        psum[j][r] = y;
-    }
     __syncthreads();
     if (threadIdx.x >= 256) return;
     const int j = threadIdx.x >> 4, bl = threadIdx.x & 15;
     const int bead = nu0 + bl;
-    if (bl >= nb || j >= f.m) return;
+    if (bead >= N || j >= f.m) return;
     const double ya = f.scal ? f.scal[2] : 0.0, yb = f.scal ? f.scal[3] : 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         double yk = 0.0;
 #pragma unroll
         for (int ww = 0; ww < EPI_W; ++ww) yk += red[ww][c][bl][j];
-        const double yy = yk + psum[j][3 * bl + c];
         const size_t o = (size_t)j * n3 + 3 * bead + c;
+        const double yy = yk + ypart[o];
         if (f.mode == EPI_APPLY) {
             f.vout[o] = yy;
         } else if (f.mode == EPI_CHEB_FIRST) {
@@ -632,7 +647,7 @@ __global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int n3p
 void launch_block_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
 {
     hipLaunchKernelGGL(k_block_epi, dim3((c.N + 15) / 16), dim3(64 * EPI_W), 0, s, c.N, c.n3,
-                       c.n3pad, c.nk4, c.nbt, (c.nk + 15) / 16 * 16, c.eph, c.tkm, c.part32, f);
+                       c.nk4, (c.nk + 15) / 16 * 16, c.eph, c.tkm, c.ypart, f);
 }
 
 }  // namespace rpy

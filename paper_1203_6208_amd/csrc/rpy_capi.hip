@@ -169,7 +169,7 @@ extern "C" void rpy_destroy(rpy_ctx *x)
     (void)hipDeviceSynchronize();
     Ctx &c = x->c;
     void *bufs[] = {c.rt, c.rt_ev, c.eph, c.etab, c.kvec, c.kcoef, c.tile_ij, c.d64, c.d32,
-                    c.d16, c.part, c.xpk,
+                    c.d16, c.part, c.xpk, c.ypart,
                     c.vpk, c.part32, c.tkm,
                     c.sfpart, c.tk, c.sfr, c.work, c.scal, c.red, c.flags, c.cell_start,
                     c.cell_beads};
@@ -261,6 +261,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
                      (rc = dalloc(&c.vpk, (size_t)c.n3pad * BLOCK_RHS)) ||
                      (rc = dalloc(&c.part32, (size_t)c.nbt * BLOCK_RHS * c.n3pad)) ||
                      (rc = dalloc(&c.tkm, (size_t)c.nk4 * 6 * BLOCK_RHS)) ||
+                     (rc = dalloc(&c.ypart, (size_t)BLOCK_RHS * c.n3)) ||
                      (rc = dalloc(&c.eph, (size_t)(c.N + 3) / 4 * ((c.nk + 15) / 16 * 16) * 4)))) ||
         (rc = dalloc(&c.sfpart, sfpart_elems(c))) ||
         (rc = dalloc(&c.tk, (size_t)6 * c.rhs_cap * c.nk)) ||
@@ -361,7 +362,7 @@ static void product(rpy_ctx *x, const double *v, int m, int prec, const EpiArgs 
                 launch_block_phases(c, s);
                 x->eph_gen = x->wrap_gen;
             }
-            launch_block_sf(c, s);
+            launch_block_sf(c, m, s);
         }
         ProfScope ps(x, RPY_PROF_EPI, s);
         launch_block_epi(c, f, s);

@@ -222,6 +222,7 @@ struct Ctx {
     double *vpk = nullptr;       // the same vectors in FP64, [n3pad][16]
     float *part32 = nullptr;     // [nbt][n3pad/16][16 vectors][16 rows] FP32 tile partials
     double *tkm = nullptr;       // [nk4][6][16] 2 m(k) P_k (C_k, S_k), rows >= nk zero
+    double *ypart = nullptr;     // [16][3N] summed FP64 tile partials of a block product
     double2 *eph = nullptr;      // [ceil(N/4)][nk16][4] e^{i k.r_mu} of the wrapped positions
     double *sfpart = nullptr;    // structure-factor partials (layouts in rpy_capi.hip)
     double *tk = nullptr;        // [nk][rhs_cap][6] 2 m(k) P_k (C_k, S_k)
@@ -269,7 +270,7 @@ void launch_symv(const Ctx &c, int prec, const double *v, int j0, int mc, hipStr
 // the partial sum and the epilogue `f`.
 void launch_block_tiles(const Ctx &c, int prec, const double *v, int m, hipStream_t s);
 void launch_block_phases(const Ctx &c, hipStream_t s);   // eph from the current tables
-void launch_block_sf(const Ctx &c, hipStream_t s);
+void launch_block_sf(const Ctx &c, int m, hipStream_t s);
 void launch_block_epi(const Ctx &c, const EpiArgs &f, hipStream_t s);
 constexpr int BLOCK_MIN_RHS = 5;   // products with at least this many vectors use it
 constexpr int BLOCK_RHS = 16;

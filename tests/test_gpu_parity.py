@@ -260,7 +260,7 @@ def test_nonfinite_position_reported():
 def test_precision_forms_n100(n100, prec, tol):
     """FP32 / BF16 stored real-space part with FP32 accumulation inside each
     tile; error of D.v and of dS against the FP64 oracle within the bound of
-    the element rounding (2^-24, 2^-9 relative per element) times the
+    the element rounding (2^-24, 2^-8 relative per element) times the
     row-norm growth."""
     _say(f"precision {prec}")
     w, pos, D, _ = n100
