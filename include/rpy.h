@@ -68,7 +68,10 @@ typedef struct {
                           (1..16); with lowp FP32/BF16 and max_rhs >= 5 the
                           context also holds the buffers of the matrix-core
                           block product (about 100 MB at N = 4000) */
-    int32_t reserved;
+    int32_t cheb_keep; /* Chebyshev vectors V_p kept for
+                          chebyshev_sqrt_adaptive (0 disables that call;
+                          at most 512): cheb_keep x max(max_rhs, 2) x 3N
+                          doubles */
     double box_l;
     double a;
     double alpha;
@@ -134,6 +137,39 @@ int rpy_bounds(rpy_ctx *c, double C, double *d_min, double *d_max,
 int chebyshev_sqrt_apply(rpy_ctx *c, const double *dw, double *out, int m,
                          int n_cheb, double d_min, double d_max, int prec,
                          double *e_f, void *stream);
+
+/* Eigenvalue bounds of D of the last build by the Lanczos recurrence in FP64
+ * (the interval of eq. cheb3 must satisfy d_max >= lambda_max and
+ * d_min <= lambda_min, section "Decomposition of the diffusion tensor"):
+ *   q_1 = r/|r|,  w = D q_j - beta_{j-1} q_{j-1},  alpha_j = q_j.w,
+ *   w -= alpha_j q_j,  beta_j = |w|,  q_{j+1} = w/beta_j,   j = 1..n_iter
+ * (one FP64 product per step, no reorthogonalisation).  r is `start`
+ * (device [N][3]) or, if NULL, Gaussian noise from (seed, step 0) as in
+ * rpy_gaussian_noise.  From the extreme eigenvalues theta of the tridiagonal
+ * T and their residual bounds res = beta_n |s_n| (s the unit eigenvector):
+ *   d_min = (theta_min - res_min)(1 - margin),
+ *   d_max = (theta_max + res_max)(1 + margin)
+ * (d_min = theta_min/2 if that is not positive).  d_min, d_max: HOST outputs;
+ * alpha, beta: optional HOST [n_iter] outputs.  Synchronises the stream.
+ * Errors: RPY_EINVAL for n_iter outside 2..512, margin < 0 or null outputs. */
+int rpy_lanczos_bounds(rpy_ctx *c, int n_iter, uint64_t seed, const double *start,
+                       double margin, double *d_min, double *d_max, double *alpha,
+                       double *beta, void *stream);
+
+/* Fixman-Chebyshev Brownian term with the paper's adaptive order (eq. nint,
+ * then the E_f criterion): N_Ch starts at n_start (or, if n_start < 2, at
+ * nint(sqrt(d_max/d_min)) + 1, rounding half away from zero), and grows by one
+ * term at a time -- each step one more product and a re-summation of the kept
+ * V_p with the coefficients of the new order -- until
+ * E_f < tol for every right-hand side or N_Ch = n_max.  n_used: HOST output,
+ * the final N_Ch; e_f: optional device [m] output.  Synchronises the stream
+ * once per trial order.  Needs cheb_keep >= n_max.  Returns RPY_ETOL (outputs
+ * written) if E_f >= tol at n_max; RPY_EINVAL as chebyshev_sqrt_apply, for
+ * tol <= 0, or n_max outside 2..cheb_keep. */
+int chebyshev_sqrt_adaptive(rpy_ctx *c, const double *dw, double *out, int m,
+                            int n_start, int n_max, double d_min, double d_max,
+                            double tol, int prec, int *n_used, double *e_f,
+                            void *stream);
 
 /* One Euler-Maruyama step (eq. sde with kappa = 0):
  *   r <- r + (dt/4) D.F + (1/sqrt 2) dS,  dS ~ sqrt(D) dW by Chebyshev,

@@ -68,6 +68,8 @@ def _L():
             "orc_cheb_sqrt": (None, [i, p, i, p, i, d, d, p]),
             "orc_sqrt_error": (d, [i, p, p, p]),
             "orc_bounds_rule": (None, [i, p, d, p, p]),
+            "orc_cheb_adaptive": (i, [i, p, i, p, i, i, d, d, d, p]),
+            "orc_lanczos": (None, [i, p, p, i, p, p]),
             "orc_spring_forces": (None, [i, i, p, p]),
             "orc_ev_forces": (None, [i, p, d, d, d, d, p]),
             "orc_euler": (None, [i, p, d, p, p, p]),
@@ -245,6 +247,45 @@ def cheb_sqrt(D, dw, nch: int, dmin: float, dmax: float) -> np.ndarray:
     _L().orc_cheb_sqrt(D.shape[0], _ptr(D), W.shape[0], _ptr(W), int(nch),
                        dmin, dmax, _ptr(out))
     return out.reshape(shp)
+
+
+def cheb_adaptive(D, dw, dmin: float, dmax: float, tol: float, nmax: int, nch0: int = 0):
+    """The paper's adaptive order (eq. nint, then N_Ch + 1 until every E_f <
+    tol, at most nmax); returns (N_Ch, dS)."""
+    D = _f64(D)
+    dw = _f64(dw)
+    shp = dw.shape
+    W = dw.reshape(-1, D.shape[0])
+    out = np.empty_like(W)
+    n = _L().orc_cheb_adaptive(D.shape[0], _ptr(D), W.shape[0], _ptr(W), int(nch0), int(nmax),
+                               dmin, dmax, tol, _ptr(out))
+    return int(n), out.reshape(shp)
+
+
+def lanczos(D, start, k: int):
+    """alpha[k], beta[k] of the plain Lanczos recurrence from `start`."""
+    D, start = _f64(D), _f64(start).ravel()
+    a, b = np.empty(k), np.empty(k)
+    _L().orc_lanczos(D.shape[0], _ptr(D), _ptr(start), int(k), _ptr(a), _ptr(b))
+    return a, b
+
+
+def lanczos_bounds(alpha, beta, margin: float):
+    """Chebyshev interval from Lanczos coefficients: the extreme Ritz values
+    theta of the tridiagonal T_k widened by their residual bounds
+    beta_k |s_k| (s the unit eigenvector of T_k) and by the relative margin:
+      d_min = (theta_min - r_min)(1 - margin), d_max = (theta_max + r_max)(1 + margin);
+    if that d_min is not positive, d_min = theta_min / 2."""
+    alpha, beta = np.asarray(alpha, float), np.asarray(beta, float)
+    k = len(alpha)
+    T = np.diag(alpha) + np.diag(beta[:k - 1], 1) + np.diag(beta[:k - 1], -1)
+    th, S = np.linalg.eigh(T)
+    r = abs(beta[k - 1]) * np.abs(S[k - 1, :])
+    lo = (th[0] - r[0]) * (1.0 - margin)
+    hi = (th[-1] + r[-1]) * (1.0 + margin)
+    if not lo > 0:
+        lo = th[0] / 2
+    return float(lo), float(hi), th
 
 
 def sqrt_error(D, dw, ds) -> float:

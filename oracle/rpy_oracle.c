@@ -413,6 +413,66 @@ double orc_sqrt_error(int n3, const double *D, const double *dw, const double *d
     return sqrt(fabs(ss - wdw) / wdw);
 }
 
+/* Adaptive order (section "Decomposition of the diffusion tensor",
+ * eq. nint and the E_f criterion): start from
+ *   N_Ch = nint(sqrt(dmax / dmin)) + 1   (nint: round half away from zero)
+ * (or from nch0 when nch0 >= 2) and increase N_Ch by one until E_f < tol
+ * for every right-hand side, or N_Ch = nmax.  Each trial recomputes the
+ * whole recurrence from scratch.  Returns the final N_Ch; out holds its dS. */
+int orc_cheb_adaptive(int n3, const double *D, int m, const double *dw, int nch0, int nmax,
+                      double dmin, double dmax, double tol, double *out)
+{
+    int n = nch0 >= 2 ? nch0 : (int)lround(sqrt(dmax / dmin)) + 1;
+    if (n < 2) n = 2;
+    if (n > nmax) n = nmax;
+    for (;;) {
+        orc_cheb_sqrt(n3, D, m, dw, n, dmin, dmax, out);
+        double worst = 0.0;
+        for (int j = 0; j < m; ++j) {
+            double e = orc_sqrt_error(n3, D, dw + (long)j * n3, out + (long)j * n3);
+            if (e > worst) worst = e;
+        }
+        if (worst < tol || n >= nmax) return n;
+        ++n;
+    }
+}
+
+/* Lanczos tridiagonalisation of the symmetric D from the start vector
+ * (Lanczos 1950): q_1 = start/|start|, and for j = 1..k
+ *   w = D q_j - beta_{j-1} q_{j-1},  alpha_j = q_j . w,
+ *   w = w - alpha_j q_j,  beta_j = |w|,  q_{j+1} = w / beta_j
+ * (no reorthogonalisation).  alpha, beta: [k]. */
+void orc_lanczos(int n3, const double *D, const double *start, int k, double *alpha,
+                 double *beta)
+{
+    double *qp = (double *)calloc(n3, sizeof(double));
+    double *q = (double *)malloc(sizeof(double) * n3);
+    double *w = (double *)malloc(sizeof(double) * n3);
+    double nrm = 0.0;
+    for (int i = 0; i < n3; ++i) nrm += start[i] * start[i];
+    nrm = sqrt(nrm);
+    for (int i = 0; i < n3; ++i) q[i] = start[i] / nrm;
+    double bprev = 0.0;
+    for (int j = 0; j < k; ++j) {
+        orc_matvec(n3, D, 1, q, w);
+        for (int i = 0; i < n3; ++i) w[i] -= bprev * qp[i];
+        double a = 0.0;
+        for (int i = 0; i < n3; ++i) a += q[i] * w[i];
+        for (int i = 0; i < n3; ++i) w[i] -= a * q[i];
+        double b = 0.0;
+        for (int i = 0; i < n3; ++i) b += w[i] * w[i];
+        b = sqrt(b);
+        alpha[j] = a;
+        beta[j] = b;
+        for (int i = 0; i < n3; ++i) {
+            qp[i] = q[i];
+            q[i] = w[i] / b;
+        }
+        bprev = b;
+    }
+    free(qp); free(q); free(w);
+}
+
 /* Paper's semidilute bound rule: lmax_F = U+.D.U+/(3N) (eq. lmax-lmin-dilute),
  * lmax = 0.35 N^0.6 lmax_F (eq. fmax), lmin = lmax/(C N^0.6) (eq. fmin),
  * with d_max = lmax, d_min = lmin. */

@@ -424,7 +424,6 @@ __global__ __launch_bounds__(256) void k_block_sf(int nk, int nk16, int nq, int 
     const int k0 = blockIdx.x * 16, ch = blockIdx.y;
     const int q0 = ch * cq, q1 = min(nq, q0 + cq);
     const int k = k0 + i;
-    const bool kin = k < nk;
     d4v acc[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) acc[q] = d4v{0.0, 0.0, 0.0, 0.0};

@@ -118,6 +118,10 @@ static int validate(const rpy_params *p, int *n2max_out)
         snprintf(g_err, sizeof g_err, "max_rhs must be in 1..%d", MAX_RHS);
         return RPY_EINVAL;
     }
+    if (p->cheb_keep < 0 || p->cheb_keep > MAX_NCHEB) {
+        snprintf(g_err, sizeof g_err, "cheb_keep must be in 0..%d", MAX_NCHEB);
+        return RPY_EINVAL;
+    }
     if (p->lowp != RPY_PREC_F64 && p->lowp != RPY_PREC_F32 && p->lowp != RPY_PREC_BF16) {
         snprintf(g_err, sizeof g_err, "unknown lowp");
         return RPY_EINVAL;
@@ -171,7 +175,8 @@ extern "C" void rpy_destroy(rpy_ctx *x)
     void *bufs[] = {c.rt, c.rt_ev, c.eph, c.etab, c.kvec, c.kcoef, c.tile_ij, c.d64, c.d32,
                     c.d16, c.part, c.xpk, c.ypart,
                     c.vpk, c.part32, c.tkm,
-                    c.sfpart, c.tk, c.sfr, c.work, c.scal, c.red, c.flags, c.cell_start,
+                    c.sfpart, c.tk, c.sfr, c.work, c.scal, c.red, c.flags, c.cell_start, c.lanc,
+                    c.vhist,
                     c.cell_beads};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -207,6 +212,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     while (c.nmax * c.nmax > n2max) --c.nmax;
     c.lowp = p->lowp;
     c.max_rhs = p->max_rhs;
+    c.cheb_keep = p->cheb_keep;
     c.rhs_cap = c.max_rhs > 2 ? c.max_rhs : 2;
     c.block = c.lowp != RPY_PREC_F64 && c.max_rhs >= BLOCK_MIN_RHS;
     if (c.block) c.rhs_cap = BLOCK_RHS;  // block kernels write all 16 columns
@@ -268,6 +274,8 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
         (rc = dalloc(&c.sfr, nv)) ||
         (rc = dalloc(&c.work, c.work_elems)) || (rc = dalloc(&c.scal, 8 + MAX_NCHEB)) ||
         (rc = dalloc(&c.red, 64)) || (rc = dalloc(&c.flags, 4)) ||
+        (rc = dalloc(&c.lanc, 2 * MAX_LANCZOS)) ||
+        (c.cheb_keep > 0 && (rc = dalloc(&c.vhist, (size_t)c.cheb_keep * c.rhs_cap * nv))) ||
         (rc = dalloc(&c.cell_start, 2 * ncells_cap + 1)) || (rc = dalloc(&c.cell_beads, nv))) {
         rpy_destroy(x);
         return rc;
@@ -432,6 +440,202 @@ extern "C" int chebyshev_sqrt_apply(rpy_ctx *x, const double *dw, double *out, i
     cheb_run(x, dw, out, m, n_cheb, prec, s);
     if (e_f) launch_sqrt_error(x->c, m, dw, x->ddw, out, e_f, s);
     return check_launch("chebyshev_sqrt_apply");
+}
+
+// Number of eigenvalues of the symmetric tridiagonal (a, b) below x
+// (Sturm sequence of the LDL^T pivots).
+static int sturm_below(const double *a, const double *b, int k, double x)
+{
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < k; ++i) {
+        const double off = i > 0 ? b[i - 1] * b[i - 1] / q : 0.0;
+        q = a[i] - x - off;
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// Eigenvalue number idx (0 = smallest) of the tridiagonal by bisection on
+// the Gershgorin interval.
+static double tridiag_eig(const double *a, const double *b, int k, int idx)
+{
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < k ? fabs(b[i]) : 0.0);
+        lo = fmin(lo, a[i] - r);
+        hi = fmax(hi, a[i] + r);
+    }
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (sturm_below(a, b, k, mid) > idx) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Solve (T - x I) y = r for the symmetric tridiagonal T = (a, b) by
+// Gaussian elimination with partial pivoting (LAPACK's gtsv scheme).
+static void tridiag_solve(const double *a, const double *b, int k, double x,
+                          std::vector<double> &r)
+{
+    std::vector<double> dl(k), d(k), du(k), du2(k, 0.0);
+    for (int i = 0; i < k; ++i) {
+        d[i] = a[i] - x;
+        du[i] = i + 1 < k ? b[i] : 0.0;
+        dl[i] = i + 1 < k ? b[i] : 0.0;   // sub-diagonal entry below row i
+    }
+    for (int i = 0; i + 1 < k; ++i) {
+        if (fabs(d[i]) >= fabs(dl[i])) {   // no row interchange
+            const double f = d[i] != 0.0 ? dl[i] / d[i] : 0.0;
+            d[i + 1] -= f * du[i];
+            r[i + 1] -= f * r[i];
+            dl[i] = 0.0;
+        } else {                           // interchange rows i and i + 1
+            const double f = d[i] / dl[i];
+            d[i] = dl[i];
+            const double t = d[i + 1];
+            d[i + 1] = du[i] - f * t;
+            if (i + 2 < k) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -f * du2[i];
+            }
+            du[i] = t;
+            const double rt = r[i];
+            r[i] = r[i + 1];
+            r[i + 1] = rt - f * r[i + 1];
+        }
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        double v = r[i];
+        if (i + 1 < k) v -= du[i] * r[i + 1];
+        if (i + 2 < k) v -= du2[i] * r[i + 2];
+        const double piv = d[i] != 0.0 ? d[i] : 1e-300;
+        r[i] = v / piv;
+    }
+}
+
+// |last component| of the unit eigenvector of the tridiagonal for the
+// eigenvalue theta, by three steps of inverse iteration from a constant
+// vector (the shift is moved off theta by a few ulps).
+static double tridiag_last(const double *a, const double *b, int k, double th)
+{
+    const double x = th + 8.0 * 2.22e-16 * fmax(fabs(th), 1e-300);
+    std::vector<double> r(k, 1.0);
+    for (int it = 0; it < 3; ++it) {
+        tridiag_solve(a, b, k, x, r);
+        double n = 0.0;
+        for (double v : r) n += v * v;
+        n = sqrt(n);
+        if (!(n > 0) || !isfinite(n)) return 1.0;   // no information: widest residual
+        for (double &v : r) v /= n;
+    }
+    return fabs(r[k - 1]);
+}
+
+extern "C" int rpy_lanczos_bounds(rpy_ctx *x, int n_iter, uint64_t seed, const double *start,
+                                  double margin, double *d_min, double *d_max, double *alpha,
+                                  double *beta, void *stream)
+{
+    if (!x || !d_min || !d_max || n_iter < 2 || n_iter > MAX_LANCZOS || !(margin >= 0))
+        return RPY_EINVAL;
+    hipStream_t s = S(stream);
+    const Ctx &c = x->c;
+    const int n3 = c.n3;
+    double *qa = x->Bv[0], *qb = x->Bv[1], *w = x->acc;
+    if (!start) {
+        launch_noise(x->dW, n3, seed, 0, 1.0, s);
+        start = x->dW;
+    }
+    launch_lanczos_init(n3, start, qb, s);
+    double *q = qb, *qp = qa;
+    for (int j = 0; j < n_iter; ++j) {
+        EpiArgs f{};
+        f.mode = EPI_APPLY;
+        f.m = 1;
+        f.vout = w;
+        product(x, q, 1, RPY_PREC_F64, f, s);
+        launch_lanczos_step(n3, j, q, w, qp, c.lanc, s);
+        double *t = q; q = qp; qp = t;   // qp now holds the old q, q the new one
+    }
+    int rc = check_launch("rpy_lanczos_bounds");
+    if (rc) return rc;
+    std::vector<double> ab(2 * n_iter), a(n_iter), b(n_iter);
+    HIP_TRY(hipMemcpyAsync(ab.data(), c.lanc, sizeof(double) * 2 * n_iter,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int j = 0; j < n_iter; ++j) {
+        a[j] = ab[2 * j];
+        b[j] = ab[2 * j + 1];
+        if (alpha) alpha[j] = a[j];
+        if (beta) beta[j] = b[j];
+    }
+    const double tmin = tridiag_eig(a.data(), b.data(), n_iter, 0);
+    const double tmax = tridiag_eig(a.data(), b.data(), n_iter, n_iter - 1);
+    const double rmin = fabs(b[n_iter - 1]) * tridiag_last(a.data(), b.data(), n_iter, tmin);
+    const double rmax = fabs(b[n_iter - 1]) * tridiag_last(a.data(), b.data(), n_iter, tmax);
+    double lo = (tmin - rmin) * (1.0 - margin);
+    if (!(lo > 0)) lo = 0.5 * tmin;
+    *d_min = lo;
+    *d_max = (tmax + rmax) * (1.0 + margin);
+    if (!isfinite(*d_min) || !isfinite(*d_max) || !(*d_max > *d_min)) return RPY_ENONFINITE;
+    return RPY_OK;
+}
+
+extern "C" int chebyshev_sqrt_adaptive(rpy_ctx *x, const double *dw, double *out, int m,
+                                       int n_start, int n_max, double d_min, double d_max,
+                                       double tol, int prec, int *n_used, double *e_f,
+                                       void *stream)
+{
+    if (!x || !dw || !out || !n_used || m < 1 || m > x->c.max_rhs || n_max < 2 ||
+        n_max > x->c.cheb_keep || !(tol > 0) || !(d_min > 0) || !(d_max > d_min) ||
+        !isfinite(d_max) || !prec_ok(x->c, prec))
+        return RPY_EINVAL;
+    hipStream_t s = S(stream);
+    const Ctx &c = x->c;
+    const size_t ps = (size_t)c.rhs_cap * c.n3;   // stride between kept V_p
+    double *vh = c.vhist;
+    double *ef = e_f ? e_f : c.red;
+    int n = n_start >= 2 ? n_start : (int)lround(sqrt(d_max / d_min)) + 1;
+    n = n < 2 ? 2 : (n > n_max ? n_max : n);
+    launch_copy(vh, dw, (size_t)m * c.n3, s);   // V_0 = dW
+    int have = 1;                                // V_0 .. V_{have-1} computed
+    std::vector<double> eh(m);
+    double worst = 0.0;
+    for (;;) {
+        launch_cheb_coeffs(c, n, RPY_BOUNDS_EXPLICIT, 0.0, d_min, d_max, nullptr, s);
+        for (int p = have; p < n; ++p) {
+            EpiArgs f{};
+            f.m = m;
+            f.p = p;
+            f.scal = c.scal;
+            f.acc = out;   // running sum of this order; re-summed below
+            f.vout = vh + p * ps;
+            f.vprev = vh + (p - 1) * ps;
+            if (p == 1) {
+                f.mode = EPI_CHEB_FIRST;
+                f.dv = x->ddw;
+            } else {
+                f.mode = EPI_CHEB_NEXT;
+                f.vprev2 = vh + (p - 2) * ps;
+            }
+            product(x, f.vprev, m, prec, f, s);
+        }
+        have = n;
+        launch_cheb_resum(c.n3, m, n, ps, c.scal, vh, out, s);
+        launch_sqrt_error(c, m, dw, x->ddw, out, ef, s);
+        int rc = check_launch("chebyshev_sqrt_adaptive");
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(eh.data(), ef, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        worst = 0.0;
+        for (int j = 0; j < m; ++j) worst = eh[j] > worst ? eh[j] : worst;
+        if (worst < tol || n >= n_max) break;
+        ++n;
+    }
+    *n_used = n;
+    return worst < tol ? RPY_OK : RPY_ETOL;
 }
 
 extern "C" int rpy_bounds(rpy_ctx *x, double C, double *d_min, double *d_max, void *stream)

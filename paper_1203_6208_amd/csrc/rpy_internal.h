@@ -26,6 +26,7 @@ constexpr int NSER = 20;        // terms of the small-r series of S(r)
 constexpr double XSER = 0.75;   // use the series for alpha*r below this
 constexpr int MAX_RHS = 16;
 constexpr int MAX_NCHEB = 512;
+constexpr int MAX_LANCZOS = 512;
 constexpr int KSLICE = 16;      // wave-vector / tile-column slices of the back-projection
 constexpr int SF_BEADS = 64;    // beads per structure-factor partial
 
@@ -229,6 +230,9 @@ struct Ctx {
     double *work = nullptr;      // vectors, see capi
     double *scal = nullptr;      // scalars: [0]=dmin [1]=dmax [2]=ya [3]=yb [8..]=coeffs
     double *red = nullptr;       // reduction outputs
+    double *lanc = nullptr;      // [2 MAX_LANCZOS] Lanczos alpha, beta
+    int cheb_keep = 0;           // Chebyshev vectors kept for the adaptive order
+    double *vhist = nullptr;     // [cheb_keep][rhs_cap][3N]
     int *flags = nullptr;        // [0] nonfinite
     // cell list for excluded volume
     int ncell;                   // cells per side (0: no cell list)
@@ -281,6 +285,12 @@ void launch_cheb_coeffs(const Ctx &c, int n_cheb, int rule, double C, double dmi
 void launch_sqrt_error(const Ctx &c, int m, const double *dw, const double *ddw,
                        const double *ds, double *e_f, hipStream_t s);
 void launch_fill(double *p, double v, size_t n, hipStream_t s);
+// Lanczos and the adaptive Chebyshev order
+void launch_lanczos_init(int n, const double *r, double *q, hipStream_t s);
+void launch_lanczos_step(int n, int j, const double *q, double *w, double *qprev, double *ab,
+                         hipStream_t s);
+void launch_cheb_resum(int n3, int m, int n_cheb, size_t pstride, const double *scal,
+                       const double *vh, double *out, hipStream_t s);
 void launch_copy(double *dst, const double *src, size_t n, hipStream_t s);
 // step
 void launch_spring_forces(const Ctx &c, const double *pos, double *F, hipStream_t s);

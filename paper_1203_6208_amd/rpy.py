@@ -29,7 +29,7 @@ class RpyError(RuntimeError):
 class RpyParams(ctypes.Structure):
     _fields_ = [("n_beads", ctypes.c_int32), ("n_chains", ctypes.c_int32),
                 ("beads_per_chain", ctypes.c_int32), ("lowp", ctypes.c_int32),
-                ("max_rhs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_rhs", ctypes.c_int32), ("cheb_keep", ctypes.c_int32),
                 ("box_l", ctypes.c_double), ("a", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("r_c", ctypes.c_double),
                 ("k_c", ctypes.c_double)]
@@ -71,6 +71,8 @@ _SIG = {
     "rpy_profile_enable": (_i, [_v, _i]),
     "rpy_profile_read": (_i, [_v, _i, _P(ctypes.c_int64), _P(_d)]),
     "rpy_strerror": (ctypes.c_char_p, [_i]),
+    "rpy_lanczos_bounds": (_i, [_v, _i, ctypes.c_uint64, _v, _d, _P(_d), _P(_d), _P(_d), _P(_d), _v]),
+    "chebyshev_sqrt_adaptive": (_i, [_v, _v, _v, _i, _i, _i, _d, _d, _d, _i, _P(_i), _v, _v]),
 }
 for _name, (_res, _args) in _SIG.items():
     _f = getattr(_lib, _name)
@@ -102,10 +104,10 @@ def rpy_strerror(code: int) -> str:
 
 
 def make_params(*, n_beads, n_chains, beads_per_chain, box_l, a, alpha, r_c, k_c,
-                lowp="f64", max_rhs=1) -> RpyParams:
+                lowp="f64", max_rhs=1, cheb_keep=0) -> RpyParams:
     return RpyParams(int(n_beads), int(n_chains), int(beads_per_chain), PREC[lowp],
-                     int(max_rhs), 0, float(box_l), float(a), float(alpha), float(r_c),
-                     float(k_c))
+                     int(max_rhs), int(cheb_keep), float(box_l), float(a), float(alpha),
+                     float(r_c), float(k_c))
 
 
 def rpy_create(params: RpyParams) -> ctypes.c_void_p:
@@ -142,6 +144,34 @@ def chebyshev_sqrt_apply(ctx, dw: torch.Tensor, out: torch.Tensor, m: int, n_che
                                      float(d_min), float(d_max), PREC[prec], _dev(e_f, "e_f"),
                                      _stream(stream)), "chebyshev_sqrt_apply")
     return out
+
+
+def rpy_lanczos_bounds(ctx, n_iter: int, seed: int = 0, start: torch.Tensor = None,
+                       margin: float = 0.05, stream=None):
+    """(d_min, d_max, alpha[n_iter], beta[n_iter]) from the FP64 Lanczos
+    recurrence on D of the last build."""
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    a = (ctypes.c_double * int(n_iter))()
+    b = (ctypes.c_double * int(n_iter))()
+    _check(_lib.rpy_lanczos_bounds(ctx, int(n_iter), int(seed), _dev(start, "start"), float(margin),
+                                   ctypes.byref(lo), ctypes.byref(hi), a, b, _stream(stream)),
+           "rpy_lanczos_bounds")
+    return lo.value, hi.value, list(a), list(b)
+
+
+def chebyshev_sqrt_adaptive(ctx, dw: torch.Tensor, out: torch.Tensor, m: int, n_start: int,
+                            n_max: int, d_min: float, d_max: float, tol: float, prec="f64",
+                            e_f: torch.Tensor = None, stream=None, allow_etol=False):
+    """Adaptive-order square root; returns the order used.  RPY_ETOL raises
+    unless allow_etol (then the order n_max is returned)."""
+    n = ctypes.c_int()
+    code = _lib.chebyshev_sqrt_adaptive(ctx, _dev(dw, "dw"), _dev(out, "out"), int(m),
+                                        int(n_start), int(n_max), float(d_min), float(d_max),
+                                        float(tol), PREC[prec], ctypes.byref(n), _dev(e_f, "e_f"),
+                                        _stream(stream))
+    if not (code == RPY_OK or (allow_etol and code == RPY_ETOL)):
+        _check(code, "chebyshev_sqrt_adaptive")
+    return n.value
 
 
 def make_bd_params(*, dt, n_cheb, bounds_rule=BOUNDS_EXPLICIT, d_min=0.0, d_max=0.0,
@@ -260,6 +290,21 @@ class Context:
     def bounds(self, C, stream=None):
         return rpy_bounds(self.handle, C, stream)
 
+    def lanczos_bounds(self, n_iter, seed=0, start=None, margin=0.05, stream=None):
+        if start is not None:
+            start = start.reshape(self.n, 3).contiguous()
+        return rpy_lanczos_bounds(self.handle, n_iter, seed, start, margin, stream)
+
+    def sqrt_adaptive(self, dw, d_min, d_max, tol, n_max, n_start=0, prec="f64", stream=None,
+                      allow_etol=False):
+        """(dS, E_f, N_Ch used)."""
+        dw = dw.reshape(-1, self.n, 3).contiguous()
+        out = torch.empty_like(dw)
+        ef = torch.empty(dw.shape[0], dtype=torch.float64, device=dw.device)
+        n = chebyshev_sqrt_adaptive(self.handle, dw, out, dw.shape[0], n_start, n_max, d_min,
+                                    d_max, tol, prec, ef, stream, allow_etol)
+        return out, ef, n
+
     def real_space_dense(self, stream=None):
         out = torch.empty((3 * self.n, 3 * self.n), dtype=torch.float64, device="cuda")
         return rpy_real_space_dense(self.handle, out, stream)
@@ -280,9 +325,9 @@ class Context:
         return rpy_num_kvectors(self.handle)
 
 
-def context_for(workload, lowp="f64", max_rhs=1) -> Context:
+def context_for(workload, lowp="f64", max_rhs=1, cheb_keep=0) -> Context:
     """Context for an ``inputs.Workload``."""
     return Context(n_beads=workload.n, n_chains=workload.nchains,
                    beads_per_chain=workload.bpc, box_l=workload.L, a=workload.a,
                    alpha=workload.alpha, r_c=workload.rc, k_c=workload.kc, lowp=lowp,
-                   max_rhs=max_rhs)
+                   max_rhs=max_rhs, cheb_keep=cheb_keep)
