@@ -105,8 +105,9 @@ NG_EV = {"zstar": 1.0, "dstar": 0.5, "rcut": 4.0}
 
 
 def workload(name: str) -> Workload:
-    """The five workloads: plain FP64 N=100 and N=1000, the precision form at
-    N=4000, the differentiation form at N=2000 (batching boxes: batch_boxes)."""
+    """The workloads: plain FP64 N=100 and N=1000, the precision form at
+    N=4000, the differentiation form at N=2000, the theta-statics check
+    (batching boxes: batch_boxes)."""
     base = POSITION_SEED_BASE
     if name == "n100":
         return Workload("n100", 10, 10, 1.0, nch=20, seed=base + 0)
@@ -116,6 +117,12 @@ def workload(name: str) -> Workload:
         return Workload("n4000", 80, 50, 2.0, nch=30, ev=dict(NG_EV), seed=base + 2)
     if name == "n2000":
         return Workload("n2000", 40, 50, 1.0, nch=30, ev=dict(NG_EV), seed=base + 4)
+    if name == "theta20":
+        # theta-statics check: N_c = 20 chains of N_b = 20 beads, a = 0.5,
+        # dt = 0.01, c/c* = 1, no excluded volume (section "Testing and
+        # verification")
+        return Workload("theta20", 20, 20, 1.0, hstar=0.5 / math.sqrt(math.pi), nch=0,
+                        dt=0.01, seed=base + 5)
     raise KeyError(name)
 
 

@@ -309,14 +309,26 @@ class Context:
         out = torch.empty((3 * self.n, 3 * self.n), dtype=torch.float64, device="cuda")
         return rpy_real_space_dense(self.handle, out, stream)
 
-    def step(self, pos, bp, dw=None, seed=0, step=0, want=False, stream=None):
-        drift = noise = ef = None
+    def step(self, pos, bp, dw=None, seed=0, step=0, want=False, e_f=None, stream=None):
+        drift = noise = None
+        ef = e_f
         if want:
             drift = torch.empty_like(pos)
             noise = torch.empty_like(pos)
-            ef = torch.empty(1, dtype=torch.float64, device=pos.device)
+            if ef is None:
+                ef = torch.empty(1, dtype=torch.float64, device=pos.device)
         bd_step(self.handle, pos, bp, dw, seed, step, drift, noise, ef, stream)
         return (drift, noise, ef) if want else None
+
+    def observables(self, pos, re2=None, rg2=None, stream=None):
+        """Per-chain R_e^2, R_g^2 (device [n_chains] each)."""
+        nc = self.params.n_chains
+        if re2 is None:
+            re2 = torch.empty(nc, dtype=torch.float64, device=pos.device)
+        if rg2 is None:
+            rg2 = torch.empty(nc, dtype=torch.float64, device=pos.device)
+        rpy_observables(self.handle, pos, re2, rg2, stream)
+        return re2, rg2
 
     def status(self, stream=None):
         return rpy_status(self.handle, stream)
