@@ -262,6 +262,92 @@ int rpy_profile_read(rpy_ctx *c, int kind, int64_t *count, double *total_ms);
 /* Number of wave vectors in the half-space set used per product. */
 int rpy_num_kvectors(const rpy_ctx *c);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent boxes (the ensembles over which section "Testing
+ * and verification" averages R_e, R_g and diffusion).  Every box is its own
+ * periodic system with its own N, chains, L, a, alpha and r_c; all boxes
+ * must give the same integer wave-vector set (equal floor((k_c L/2 pi)^2),
+ * e.g. a common alpha L and k_c/alpha).  Excluded volume is not supported
+ * (theta conditions with the overlap-corrected tensor, eq. cor5).
+ *
+ * Layout: the beads of box b occupy the padded index range
+ * [bead0[b], bead0[b] + N_b) of one global array of rpy_batch_padded_beads()
+ * beads; bead0[b] is a multiple of tile_beads and the beads between boxes
+ * are padding.  Every vector argument is a device FP64 array [G][3] in that
+ * layout (G = padded beads), m vectors stacked with stride 3G.  Entries of
+ * padding beads must be finite on input; they are zero (or untouched
+ * positions) on output.
+ *
+ * Each stage of a call is one kernel launch over all boxes: the wrap and the
+ * phase tables, the real-space tiles of every box (tile_beads beads per tile
+ * side, 32 or 64; symmetric storage per box as in rpy_create), one product
+ * kernel for all stored tiles plus the structure-factor partials, one
+ * reduction over all boxes' wave vectors and one back-projection + epilogue.
+ * ----------------------------------------------------------------------- */
+typedef struct rpy_batch rpy_batch;
+
+/* Validate every entry of p[0..nbox-1] as rpy_create does (their lowp,
+ * max_rhs and cheb_keep fields are ignored) and allocate everything once.
+ * lowp: RPY_PREC_F64, or RPY_PREC_F32 to also keep FP32 tiles for
+ * Chebyshev products in FP32.  Errors: RPY_EINVAL (bad entry, unequal
+ * wave-vector sets, tile_beads not 32/64, more than 65535 boxes, 3G beyond
+ * int32), RPY_EGEOM, RPY_ENOMEM, RPY_EHIP. */
+int rpy_batch_create(rpy_batch **out, const rpy_params *p, int nbox, int lowp,
+                     int tile_beads);
+void rpy_batch_destroy(rpy_batch *b);
+
+/* G, the padded number of beads (-1 for NULL). */
+int64_t rpy_batch_padded_beads(const rpy_batch *b);
+
+/* bead0: host int64 [nbox + 1]; bead0[nbox] = G. */
+int rpy_batch_offsets(const rpy_batch *b, int64_t *bead0);
+
+/* Wrap pos (device [G][3]) and build the real-space tiles of every box
+ * (eq. DF with the overlap form, as rpy_ewald_build per box). */
+int rpy_batch_build(rpy_batch *b, const double *pos, void *stream);
+
+/* out = D_b . v on every box for m = 1 or 2 vectors (eq. DF, full periodic
+ * sum).  prec: RPY_PREC_F64, or RPY_PREC_F32 if created with FP32 tiles (the
+ * reciprocal sum stays FP64). */
+int rpy_batch_apply(rpy_batch *b, const double *v, double *out, int m,
+                    int prec, void *stream);
+
+/* Chebyshev approximation of sqrt(D_b) dw on every box (eq. cheb1-cheb3),
+ * n_cheb terms; interval per box from the paper's rule with constant C
+ * (RPY_BOUNDS_PAPER, one extra FP64 product with U+) or the explicit
+ * [d_min, d_max] for all boxes.  e_f: optional device [nbox] E_f per box;
+ * bounds: optional device [nbox][2] (d_min, d_max) used per box. */
+int rpy_batch_chebyshev(rpy_batch *b, const double *dw, double *out,
+                        int n_cheb, int bounds_rule, double C, double d_min,
+                        double d_max, int prec, double *e_f, double *bounds,
+                        void *stream);
+
+/* One step of every box, as bd_step with dw = NULL: springs, D.F in FP64,
+ * interval + coefficients per box, noise from Philox4x32-10 with the mapping
+ * of rpy_gaussian_noise over all 3G padded entries (padding entries zero),
+ * Chebyshev products in bp->prec, Euler update of the real beads.
+ * bp->ev_zstar must be 0.  drift, noise: optional device [G][3]; e_f:
+ * optional device [nbox]. */
+int rpy_batch_step(rpy_batch *b, double *pos, const bd_params *bp,
+                   uint64_t seed, uint64_t step, double *drift, double *noise,
+                   double *e_f, void *stream);
+
+/* n_steps steps with noise steps step0, step0 + 1, ...: identical to that
+ * many rpy_batch_step calls, but every step is one launch of a HIP graph
+ * captured from the step's kernels (captured on the first call and again
+ * when pos, *bp or seed change; capture uses an internal stream).  The
+ * graph holds kernel nodes only. */
+int rpy_batch_run(rpy_batch *b, double *pos, const bd_params *bp,
+                  uint64_t seed, uint64_t step0, int n_steps, void *stream);
+
+/* Per-chain R_e^2 and R_g^2 of all boxes, chains in box order: device
+ * outputs [sum of n_chains]. */
+int rpy_batch_observables(rpy_batch *b, const double *pos, double *re2,
+                          double *rg2, void *stream);
+
+/* As rpy_status, for the batch's non-finite flag. */
+int rpy_batch_status(rpy_batch *b, void *stream);
+
 /* Human-readable text for an error code (static storage). */
 const char *rpy_strerror(int code);
 

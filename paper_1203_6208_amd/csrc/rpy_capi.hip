@@ -145,6 +145,12 @@ static int validate(const rpy_params *p, int *n2max_out)
     return RPY_OK;
 }
 
+namespace rpy {
+int validate_params(const rpy_params *p, int *n2max) { return validate(p, n2max); }
+void set_error(const char *msg) { snprintf(g_err, sizeof g_err, "%s", msg); }
+int hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+}  // namespace rpy
+
 // Structure-factor partials: [nsfc][6 rhs_cap][nk] for the vector-unit
 // product, [nk/16 blocks][nchb][6 x 16][16] for the block product.
 static size_t sfpart_elems(const Ctx &c)

@@ -188,6 +188,23 @@ struct KCoef {
     double hx, hy, hz; // khat
 };
 
+// ------------------------------------------------------------------ noise
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): round function
+// (c0,c1,c2,c3) -> (hi(B c2) ^ c1 ^ k0, lo(B c2), hi(A c0) ^ c3 ^ k1, lo(A c0))
+// with A = 0xD2511F53, B = 0xCD9E8D57, key bumped by (0x9E3779B9, 0xBB67AE85).
+__device__ inline uint4 philox10(uint4 c, uint2 k)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
 // -------------------------------------------------------------- context
 struct Ctx {
     // problem
@@ -241,6 +258,14 @@ struct Ctx {
     size_t work_elems = 0;
     double ev_rcut_built = 0.0;
 };
+
+// ------------------------------------------------------------ errors
+// Parameter checks of rpy_create (RPY_OK or an error code; *n2max = the
+// integer |n|^2 cutoff of the wave vectors), and the message rpy_strerror
+// reports for the last RPY_EINVAL / RPY_ENOMEM / RPY_EHIP of this thread.
+int validate_params(const rpy_params *p, int *n2max);
+void set_error(const char *msg);
+int hip_error(hipError_t e, const char *what);   // records and returns RPY_EHIP
 
 // ------------------------------------------------------------ launchers
 // build

@@ -295,22 +295,7 @@ void launch_ev_forces(const Ctx &c, const double *rt, double zstar, double dstar
 }
 
 // ------------------------------------------------------------------ Philox
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): round function
-// (c0,c1,c2,c3) -> (hi(B c2) ^ c1 ^ k0, lo(B c2), hi(A c0) ^ c3 ^ k1, lo(A c0))
-// with A = 0xD2511F53, B = 0xCD9E8D57, key bumped by (0x9E3779B9, 0xBB67AE85).
-__device__ inline uint4 philox10(uint4 c, uint2 k)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
-        k.x += 0x9E3779B9u;
-        k.y += 0xBB67AE85u;
-    }
-    return c;
-}
-
+// Raw Philox4x32-10 blocks (philox10 in rpy_internal.h).
 __global__ void k_philox(const uint32_t *__restrict__ ck, uint32_t *__restrict__ out, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

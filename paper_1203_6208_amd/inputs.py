@@ -126,15 +126,17 @@ def workload(name: str) -> Workload:
     raise KeyError(name)
 
 
-def batch_boxes(count: int = 256, seed: int = POSITION_SEED_BASE + 3):
-    """Ragged ensemble: N_b ~ U{10..50}, N in whole chains with 100 <= N <= 2000,
-    c/c* ~ U[0.5, 3], no excluded volume."""
+def batch_boxes(count: int = 256, seed: int = POSITION_SEED_BASE + 3, n_lo: int = 100,
+                n_hi: int = 2000):
+    """Ragged ensemble: N_b ~ U{10..50}, N in whole chains with n_lo <= N <= n_hi
+    (100..2000 for the batching workload), c/c* ~ U[0.5, 3], no excluded
+    volume."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for b in range(count):
         bpc = int(rng.integers(10, 51))
-        lo = math.ceil(100 / bpc)
-        hi = max(lo, 2000 // bpc)
+        lo = math.ceil(n_lo / bpc)
+        hi = max(lo, n_hi // bpc)
         nchains = int(rng.integers(lo, hi + 1))
         cc = float(rng.uniform(0.5, 3.0))
         out.append(Workload(f"box{b}", nchains, bpc, cc, nch=30, seed=seed + 7919 * (b + 1)))

@@ -73,6 +73,18 @@ _SIG = {
     "rpy_strerror": (ctypes.c_char_p, [_i]),
     "rpy_lanczos_bounds": (_i, [_v, _i, ctypes.c_uint64, _v, _d, _P(_d), _P(_d), _P(_d), _P(_d), _v]),
     "chebyshev_sqrt_adaptive": (_i, [_v, _v, _v, _i, _i, _i, _d, _d, _d, _i, _P(_i), _v, _v]),
+    "rpy_batch_create": (_i, [_P(_v), _P(RpyParams), _i, _i, _i]),
+    "rpy_batch_destroy": (None, [_v]),
+    "rpy_batch_padded_beads": (ctypes.c_int64, [_v]),
+    "rpy_batch_offsets": (_i, [_v, _P(ctypes.c_int64)]),
+    "rpy_batch_build": (_i, [_v, _v, _v]),
+    "rpy_batch_apply": (_i, [_v, _v, _v, _i, _i, _v]),
+    "rpy_batch_chebyshev": (_i, [_v, _v, _v, _i, _i, _d, _d, _d, _i, _v, _v, _v]),
+    "rpy_batch_step": (_i, [_v, _v, _P(BdParams), ctypes.c_uint64, ctypes.c_uint64, _v, _v, _v,
+                            _v]),
+    "rpy_batch_run": (_i, [_v, _v, _P(BdParams), ctypes.c_uint64, ctypes.c_uint64, _i, _v]),
+    "rpy_batch_observables": (_i, [_v, _v, _v, _v, _v]),
+    "rpy_batch_status": (_i, [_v, _v]),
 }
 for _name, (_res, _args) in _SIG.items():
     _f = getattr(_lib, _name)
@@ -343,3 +355,148 @@ def context_for(workload, lowp="f64", max_rhs=1, cheb_keep=0) -> Context:
                    beads_per_chain=workload.bpc, box_l=workload.L, a=workload.a,
                    alpha=workload.alpha, r_c=workload.rc, k_c=workload.kc, lowp=lowp,
                    max_rhs=max_rhs, cheb_keep=cheb_keep)
+
+
+# ------------------------------------------------------------------ batches
+def rpy_batch_create(params, lowp="f64", tile_beads=64) -> ctypes.c_void_p:
+    arr = (RpyParams * len(params))(*params)
+    h = ctypes.c_void_p()
+    _check(_lib.rpy_batch_create(ctypes.byref(h), arr, len(params), PREC[lowp], int(tile_beads)),
+           "rpy_batch_create")
+    return h
+
+
+def rpy_batch_destroy(b) -> None:
+    _lib.rpy_batch_destroy(b)
+
+
+def rpy_batch_padded_beads(b) -> int:
+    return int(_lib.rpy_batch_padded_beads(b))
+
+
+def rpy_batch_offsets(b, nbox: int):
+    out = (ctypes.c_int64 * (nbox + 1))()
+    _check(_lib.rpy_batch_offsets(b, out), "rpy_batch_offsets")
+    return [int(x) for x in out]
+
+
+def rpy_batch_build(b, pos, stream=None):
+    _check(_lib.rpy_batch_build(b, _dev(pos, "pos"), _stream(stream)), "rpy_batch_build")
+
+
+def rpy_batch_apply(b, v, out, m, prec="f64", stream=None):
+    _check(_lib.rpy_batch_apply(b, _dev(v, "v"), _dev(out, "out"), int(m), PREC[prec],
+                                _stream(stream)), "rpy_batch_apply")
+    return out
+
+
+def rpy_batch_chebyshev(b, dw, out, n_cheb, bounds_rule=BOUNDS_PAPER, C=8.0, d_min=0.0,
+                        d_max=0.0, prec="f64", e_f=None, bounds=None, stream=None):
+    _check(_lib.rpy_batch_chebyshev(b, _dev(dw, "dw"), _dev(out, "out"), int(n_cheb),
+                                    int(bounds_rule), float(C), float(d_min), float(d_max),
+                                    PREC[prec], _dev(e_f, "e_f"), _dev(bounds, "bounds"),
+                                    _stream(stream)), "rpy_batch_chebyshev")
+    return out
+
+
+def rpy_batch_step(b, pos, bp: BdParams, seed=0, step=0, drift=None, noise=None, e_f=None,
+                   stream=None):
+    _check(_lib.rpy_batch_step(b, _dev(pos, "pos"), ctypes.byref(bp), ctypes.c_uint64(seed),
+                               ctypes.c_uint64(step), _dev(drift, "drift"), _dev(noise, "noise"),
+                               _dev(e_f, "e_f"), _stream(stream)), "rpy_batch_step")
+
+
+def rpy_batch_run(b, pos, bp: BdParams, seed=0, step0=0, n_steps=1, stream=None):
+    _check(_lib.rpy_batch_run(b, _dev(pos, "pos"), ctypes.byref(bp), ctypes.c_uint64(seed),
+                              ctypes.c_uint64(step0), int(n_steps), _stream(stream)),
+           "rpy_batch_run")
+
+
+def rpy_batch_observables(b, pos, re2, rg2, stream=None):
+    _check(_lib.rpy_batch_observables(b, _dev(pos, "pos"), _dev(re2, "re2"), _dev(rg2, "rg2"),
+                                      _stream(stream)), "rpy_batch_observables")
+
+
+def rpy_batch_status(b, stream=None) -> int:
+    return _lib.rpy_batch_status(b, _stream(stream))
+
+
+class Batch:
+    """Owns one rpy_batch over ``inputs.Workload`` boxes; converts between the
+    per-box ``[N_b, 3]`` arrays and the padded global layout."""
+
+    def __init__(self, workloads, lowp="f64", tile_beads=64):
+        self.workloads = list(workloads)
+        ps = [make_params(n_beads=w.n, n_chains=w.nchains, beads_per_chain=w.bpc, box_l=w.L,
+                          a=w.a, alpha=w.alpha, r_c=w.rc, k_c=w.kc) for w in self.workloads]
+        self.tile_beads = int(tile_beads)
+        self.handle = rpy_batch_create(ps, lowp, tile_beads)
+        self.nbox = len(ps)
+        self.G = rpy_batch_padded_beads(self.handle)
+        self.bead0 = rpy_batch_offsets(self.handle, self.nbox)
+        self.nchain = sum(w.nchains for w in self.workloads)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            rpy_batch_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, per_box, m=None, device="cuda"):
+        """Per-box arrays [N_b, 3] (or [m, N_b, 3]) -> padded [G, 3] ([m, G, 3])."""
+        lead = () if m is None else (m,)
+        out = torch.zeros(lead + (self.G, 3), dtype=torch.float64)
+        for b, x in enumerate(per_box):
+            t = torch.as_tensor(x, dtype=torch.float64)
+            out[..., self.bead0[b]:self.bead0[b] + self.workloads[b].n, :] = t
+        return out.to(device).contiguous()
+
+    def unpack(self, x):
+        """Padded [..., G, 3] -> list of per-box [..., N_b, 3] (same device)."""
+        return [x[..., self.bead0[b]:self.bead0[b] + w.n, :] for b, w in enumerate(self.workloads)]
+
+    def build(self, pos, stream=None):
+        rpy_batch_build(self.handle, pos, stream)
+
+    def apply(self, v, prec="f64", stream=None):
+        v = v.reshape(-1, self.G, 3).contiguous()
+        out = torch.empty_like(v)
+        rpy_batch_apply(self.handle, v, out, v.shape[0], prec, stream)
+        return out
+
+    def chebyshev(self, dw, n_cheb, bounds_rule=BOUNDS_PAPER, C=8.0, d_min=0.0, d_max=0.0,
+                  prec="f64", stream=None):
+        """(dS [G, 3], E_f [nbox], bounds [nbox, 2])."""
+        dw = dw.reshape(self.G, 3).contiguous()
+        out = torch.empty_like(dw)
+        ef = torch.empty(self.nbox, dtype=torch.float64, device=dw.device)
+        bnd = torch.empty((self.nbox, 2), dtype=torch.float64, device=dw.device)
+        rpy_batch_chebyshev(self.handle, dw, out, n_cheb, bounds_rule, C, d_min, d_max, prec, ef,
+                            bnd, stream)
+        return out, ef, bnd
+
+    def step(self, pos, bp, seed=0, step=0, want=False, stream=None):
+        drift = noise = ef = None
+        if want:
+            drift = torch.empty_like(pos)
+            noise = torch.empty_like(pos)
+            ef = torch.empty(self.nbox, dtype=torch.float64, device=pos.device)
+        rpy_batch_step(self.handle, pos, bp, seed, step, drift, noise, ef, stream)
+        return (drift, noise, ef) if want else None
+
+    def run(self, pos, bp, seed=0, step0=0, n_steps=1, stream=None):
+        rpy_batch_run(self.handle, pos, bp, seed, step0, n_steps, stream)
+
+    def observables(self, pos, stream=None):
+        re2 = torch.empty(self.nchain, dtype=torch.float64, device=pos.device)
+        rg2 = torch.empty(self.nchain, dtype=torch.float64, device=pos.device)
+        rpy_batch_observables(self.handle, pos, re2, rg2, stream)
+        return re2, rg2
+
+    def status(self, stream=None):
+        return rpy_batch_status(self.handle, stream)

@@ -103,3 +103,38 @@ def test_host_pair_block_matches_oracle(rpy, orc, case, wl):
         assert np.max(np.abs(got - off)) < 1e-13, (case, r)
         gd = np.array(rpy.rpy_host_pair_block(p, [0.0, 0.0, 0.0], True)).reshape(3, 3)
         assert np.max(np.abs(gd - diag)) < 1e-13
+
+
+def _batch_create(rpy, ps, lowp=0, tb=64):
+    arr = (rpy.RpyParams * max(len(ps), 1))(*ps)
+    h = ctypes.c_void_p()
+    rc = rpy._lib.rpy_batch_create(ctypes.byref(h), arr, len(ps), lowp, tb)
+    return rc, h
+
+
+@pytest.mark.parametrize("case", ["empty", "tile48", "bf16", "kset", "badbox", "geom"])
+def test_batch_create_rejects_invalid(rpy, case):
+    """Batch parameter validation happens before any device call: every box
+    is checked as rpy_create checks it, all boxes must share one integer
+    wave-vector set, tiles are 32 or 64 beads, FP64 or FP32 tiles only."""
+    ok = [_params(rpy), _params(rpy, box_l=_params(rpy).box_l * 1.3,
+                                alpha=_params(rpy).alpha / 1.3, r_c=_params(rpy).r_c * 1.3,
+                                k_c=_params(rpy).k_c / 1.3)]
+    ps, lowp, tb, code = ok, 0, 64, -1
+    if case == "empty":
+        ps = []
+    elif case == "tile48":
+        tb = 48
+    elif case == "bf16":
+        lowp = 2
+    elif case == "kset":
+        ps = ok + [_params(rpy, k_c=_params(rpy).k_c * 1.5)]
+    elif case == "badbox":
+        ps = ok + [_params(rpy, n_chains=7)]
+    elif case == "geom":
+        ps = ok + [_params(rpy, a=2.0)]
+        code = -2
+    rc, h = _batch_create(rpy, ps, lowp, tb)
+    assert rc == code
+    assert not h.value
+    assert rpy.rpy_strerror(rc)
