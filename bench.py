@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batching form (for profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -177,6 +179,135 @@ def time_block(w, prec, reps, torch, rpy):
             "vector_products_per_s": 16 * nprod / wall}
 
 
+def eigen_study(w, torch, rpy):
+    """Chebyshev interval and order at the bench state (section
+    "Decomposition of the diffusion tensor"): FP64 Lanczos bounds (60 steps)
+    against the paper's rule at C = 8 and at the bench's C, the order of
+    eq. nint for each, and the order the adaptive procedure needs for
+    E_f < 1e-3 on one dW with the Lanczos interval."""
+    ctx = rpy.context_for(w, max_rhs=1, cheb_keep=256)
+    pos = torch.from_numpy(w.positions()).cuda()
+    ctx.build(pos)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lo, hi, _, _ = ctx.lanczos_bounds(60, seed=1, margin=0.05)
+    t_lz = time.perf_counter() - t0
+    out = {"lanczos_60": {"d_min": lo, "d_max": hi, "seconds": t_lz,
+                          "n_cheb_rule": math.floor(math.sqrt(hi / lo) + 0.5) + 1}}
+    for C in (8.0, BOUNDS_C):
+        a, b = ctx.bounds(C)
+        out[f"paper_rule_C{C:g}"] = {"d_min": a, "d_max": b,
+                                     "n_cheb_rule": math.floor(math.sqrt(b / a) + 0.5) + 1}
+    dw = torch.from_numpy(w.noise()[0]).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, ef, n = ctx.sqrt_adaptive(dw, lo, hi, 1e-3, 256, allow_etol=True)
+    t_ad = time.perf_counter() - t0
+    out["adaptive_tol_1e-3"] = {"n_cheb": n, "E_f": float(ef[0]), "seconds": t_ad}
+    del ctx
+    return out
+
+
+def batch_study(torch, rpy, inputs, steps=5, per_box=True):
+    """Batching form: the 256-box ragged ensemble (N 125..1989 in whole chains
+    of 10..50 beads, c/c* 0.5..3, no excluded volume), FP64 core with FP32
+    Chebyshev products (N_Ch = 30, paper rule), every step one HIP graph
+    replay.  Tile size from the autotuner, compared with both fixed sizes;
+    the same ensemble with FP64 products, and box by box through the
+    single-box library (FP64, one bd_step per box) as the plain baseline.
+    Throughput is aggregate box-steps/s (boxes x steps / s)."""
+    from paper_1203_6208_amd import autotune
+    ws = inputs.batch_boxes()
+    nbox = len(ws)
+    beads = sum(w.n for w in ws)
+    bp32 = rpy.make_bd_params(dt=1e-3, n_cheb=30, bounds_rule=rpy.BOUNDS_PAPER,
+                              bounds_C=BOUNDS_C, prec="f32")
+    bp64 = rpy.make_bd_params(dt=1e-3, n_cheb=30, bounds_rule=rpy.BOUNDS_PAPER,
+                              bounds_C=BOUNDS_C, prec="f64")
+    pos_np = [w.positions() for w in ws]
+    t0 = time.perf_counter()
+    best, times = autotune.tune_batch(ws, bp32, lowp="f32", steps=3, positions=pos_np)
+    t_tune = time.perf_counter() - t0
+    out = {"boxes": nbox, "beads": beads, "n_cheb": 30,
+           "autotune": {"tile_beads": best, "seconds_tuning": t_tune,
+                        "candidates_ms_per_step": {str(k): 1e3 * v for k, v in times.items()}}}
+
+    def graph_rate(lowp, bp, tb):
+        B = rpy.Batch(ws, lowp=lowp, tile_beads=tb)
+        pos = B.pack(pos_np)
+        B.run(pos, bp, seed=1, step0=0, n_steps=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.run(pos, bp, seed=1, step0=1, n_steps=steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = B.status()
+        return B, pos, wall / steps, st
+
+    B, pos, sec, st = graph_rate("f32", bp32, best)
+    out["f32_autotuned"] = {"box_steps_per_s": nbox / sec, "ensemble_steps_per_s": 1.0 / sec,
+                            "ms_per_step": 1e3 * sec, "status": st, "tile_beads": best}
+    # one FP32 product (tile kernel + reduction + back-projection) timed with events
+    v = B.pack([np.ones((w.n, 3)) for w in ws], m=1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    B.apply(v, prec="f32")
+    e0.record()
+    for _ in range(5):
+        B.apply(v, prec="f32")
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / 5
+    alg = sum(3 * w.n * (3 * w.n + 1) // 2 for w in ws) * 4
+    out["f32_product"] = {"us": us, "algorithmic_bytes": alg,
+                          "GBs": alg / (us * 1e-6) / 1e9,
+                          "hbm_frac": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    # accuracy of the FP32 form on one step against FP64 products (same state)
+    B64 = rpy.Batch(ws, lowp="f64", tile_beads=best)
+    p64 = B64.pack(pos_np)
+    p32 = B.pack(pos_np)
+    d64, n64, _ = B64.step(p64, bp64, seed=5, step=0, want=True)
+    d32, n32, _ = B.step(p32, bp32, seed=5, step=0, want=True)
+    torch.cuda.synchronize()
+    e_n = max(float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+              for a, b in zip(B.unpack(n32), B64.unpack(n64)))
+    e_d = max(float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+              for a, b in zip(B.unpack(d32), B64.unpack(d64)))
+    out["f32_vs_f64_max_box_rel_err"] = {"dS": e_n, "drift": e_d}
+    del B, B64, pos, p64, p32
+    for tb in (32, 64):
+        if tb == best:
+            continue
+        Bx, px, sx, stx = graph_rate("f32", bp32, tb)
+        out[f"f32_fixed_tile{tb}"] = {"box_steps_per_s": nbox / sx, "ms_per_step": 1e3 * sx}
+        del Bx, px
+    out[f"f32_fixed_tile{best}"] = dict(out["f32_autotuned"])
+    Bd, pd, sd, std = graph_rate("f64", bp64, best)
+    out["f64_batched"] = {"box_steps_per_s": nbox / sd, "ms_per_step": 1e3 * sd, "status": std}
+    del Bd, pd
+    torch.cuda.empty_cache()
+    if per_box:
+        ctxs = [rpy.context_for(w) for w in ws]
+        tp = [torch.from_numpy(p).cuda() for p in pos_np]
+        bps = [rpy.make_bd_params(dt=1e-3, n_cheb=30, bounds_rule=rpy.BOUNDS_PAPER,
+                                  bounds_C=BOUNDS_C, prec="f64") for _ in ws]
+        for c, p, b in zip(ctxs, tp, bps):
+            c.step(p, b, seed=1, step=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c, p, b in zip(ctxs, tp, bps):
+            c.step(p, b, seed=1, step=1)
+        torch.cuda.synchronize()
+        sp = time.perf_counter() - t0
+        out["f64_box_by_box"] = {"box_steps_per_s": nbox / sp, "ms_per_ensemble_step": 1e3 * sp}
+        for c in ctxs:
+            c.close()
+        del ctxs, tp
+    out["speedup_autotuned_f32_vs_box_by_box_f64"] = (
+        out["f32_autotuned"]["box_steps_per_s"] / out["f64_box_by_box"]["box_steps_per_s"]
+        if per_box else None)
+    return out
+
+
 def cpu_baseline(w, seconds):
     """Oracle on a bounded sample of one step: block rows of D (real space,
     self term, reciprocal sum over the full +-k set) for a subset of beads, and
@@ -238,6 +369,10 @@ def main():
         torch.cuda.synchronize()
         print(f"# calibration copy: {nb * 8} bytes read and written per launch", file=sys.stderr)
         del a, b
+    if args.batch_only:
+        print(json.dumps({"batch": batch_study(torch, rpy, inputs, steps=args.steps,
+                                               per_box=False)}))
+        return
     w = inputs.workload("n4000")
     print(f"# workload n4000 N={w.n} L={w.L:.4f} alpha={w.alpha:.5f} rc={w.rc:.4f} "
           f"n2max={w.n2max}", file=sys.stderr, flush=True)
@@ -271,6 +406,16 @@ def main():
         for k, v in errs.items():
             forms.setdefault(k, {}).update(v)
         forms["f64"].update({"steps_per_s": value, "ms_per_step": ms_step})
+    eigen = None if args.no_forms else eigen_study(w, torch, rpy)
+    if eigen:
+        print(f"# eigen {eigen}", file=sys.stderr, flush=True)
+    batch = None
+    if not args.no_forms:
+        del ctx, tpos
+        torch.cuda.empty_cache()
+        batch = batch_study(torch, rpy, inputs)
+        print(f"# batch {batch}", file=sys.stderr, flush=True)
+        forms["batched_256_boxes"] = batch
     cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_seconds)
     line = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,
@@ -289,6 +434,7 @@ def main():
                      "avg_launch_us": sym["avg_us"], "launches": sym["launches"]},
         "kernels": prof,
         "forms": forms,
+        "eigen": eigen,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

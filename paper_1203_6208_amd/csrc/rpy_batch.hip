@@ -190,14 +190,66 @@ __global__ __launch_bounds__(256) void k_bbuild(const int4 *__restrict__ stor,
 }
 
 // ------------------------------------------------------------------ product
-// Workgroups [0, nsf): structure-factor partials of one bead tile (chunk) for
-// a block of wave vectors, one thread per k:
+// Columns of a tile row owned by lane q (0..15) of a 16-lane row group and
+// their loads: FP64 tiles in 16-byte pairs at 32 s + 2 q; FP32 tiles in
+// 16-byte quads at 64 s + 4 q (64-bead tiles) or a quad at 4 q plus a pair
+// at 64 + 2 q (32-bead tiles).  Every row is read once, contiguously across
+// the row group.
+template <typename T, int TBB> struct BLd;
+template <int TBB> struct BLd<double, TBB> {
+    static constexpr int NE = 3 * TBB / 16;
+    __device__ static int col(int q, int e) { return 32 * (e >> 1) + 2 * q + (e & 1); }
+    __device__ static void load(const double *row, int q, double a[NE])
+    {
+#pragma unroll
+        for (int s = 0; s < NE / 2; ++s) {
+            const double2 v = *reinterpret_cast<const double2 *>(row + 32 * s + 2 * q);
+            a[2 * s] = v.x;
+            a[2 * s + 1] = v.y;
+        }
+    }
+};
+template <> struct BLd<float, 64> {
+    static constexpr int NE = 12;
+    __device__ static int col(int q, int e) { return 64 * (e >> 2) + 4 * q + (e & 3); }
+    __device__ static void load(const float *row, int q, double a[NE])
+    {
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const float4 v = *reinterpret_cast<const float4 *>(row + 64 * s + 4 * q);
+            a[4 * s] = v.x;
+            a[4 * s + 1] = v.y;
+            a[4 * s + 2] = v.z;
+            a[4 * s + 3] = v.w;
+        }
+    }
+};
+template <> struct BLd<float, 32> {
+    static constexpr int NE = 6;
+    __device__ static int col(int q, int e) { return e < 4 ? 4 * q + e : 64 + 2 * q + (e - 4); }
+    __device__ static void load(const float *row, int q, double a[NE])
+    {
+        const float4 v = *reinterpret_cast<const float4 *>(row + 4 * q);
+        const float2 u = *reinterpret_cast<const float2 *>(row + 64 + 2 * q);
+        a[0] = v.x;
+        a[1] = v.y;
+        a[2] = v.z;
+        a[3] = v.w;
+        a[4] = u.x;
+        a[5] = u.y;
+    }
+};
+
+// nsf structure-factor workgroups (spread over the launch, see below): the
+// partials of one bead tile (chunk) for a block of wave vectors, one thread
+// per k:
 //   sfpart[chunk][6 j + c][k] = sum over the chunk's real beads of
 //   {cos, sin}(k.r) v_c.
-// Further workgroups: one stored tile each, as k_symv (4 waves; row group of
-// 16 lanes per tile row; each lane owns TSB/16 columns loaded in pairs).
+// The other workgroups: one stored tile each, as k_symv (4 waves; row group of
+// 16 lanes per tile row; each lane owns the TSB/16 columns of BLd; FP64
+// accumulation for both tile types).
 template <int TBB, typename T, int M>
-__global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int nkb, int nk, int nm1,
+__global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb, int nk, int nm1,
                                                const int *__restrict__ tile_box,
                                                const BoxDev *__restrict__ boxes,
                                                const int4 *__restrict__ stor,
@@ -209,10 +261,17 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int nkb, int nk,
                                                double *__restrict__ part)
 {
     constexpr int TSB = 3 * TBB;
-    constexpr int NE = TSB / 16;        // columns per lane
+    constexpr int NE = BLd<T, TBB>::NE;   // columns per lane
     extern __shared__ double smem[];
-    if ((int)blockIdx.x < nsf) {
-        const int chunk = blockIdx.x / nkb, kb = blockIdx.x % nkb;
+    // workgroup i is structure-factor workgroup i / sfr when i is a multiple
+    // of sfr below nsf * sfr, else tile i - (structure-factor workgroups
+    // before it): the structure factors are spread over the launch so that
+    // their arithmetic overlaps the streaming of the tiles
+    const int bid = blockIdx.x;
+    const int nsf_before = min(nsf, bid / sfr + 1);
+    if (bid % sfr == 0 && bid / sfr < nsf) {
+        const int sfb = bid / sfr;
+        const int chunk = sfb / nkb, kb = sfb % nkb;
         const BoxDev &d = boxes[tile_box[chunk]];
         const int loc0 = (chunk - d.tile0) * TBB;
         const int nb = max(0, min(TBB, d.N - loc0));
@@ -261,7 +320,7 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int nkb, int nk,
     typedef double A;
     A(*sx)[TSB] = reinterpret_cast<A(*)[TSB]>(smem);                          // [M][TSB]
     double(*scol)[M][TSB] = reinterpret_cast<double(*)[M][TSB]>(smem + M * TSB);  // [4][M][TSB]
-    const int t = blockIdx.x - nsf;
+    const int t = bid - nsf_before;
     const int4 e = stor[t];
     const BoxDev &d = boxes[e.x];
     const int I = e.y, J = e.z;
@@ -277,7 +336,7 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int nkb, int nk,
     for (int j = 0; j < M; ++j)
 #pragma unroll
         for (int c = 0; c < NE; ++c)
-            xj[j][c] = v[(size_t)j * G3 + rowJ + 32 * (c >> 1) + 2 * q + (c & 1)];
+            xj[j][c] = v[(size_t)j * G3 + rowJ + BLd<T, TBB>::col(q, c)];
     A cacc[M][NE];
 #pragma unroll
     for (int j = 0; j < M; ++j)
@@ -286,15 +345,11 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int nkb, int nk,
     __syncthreads();
     const T *tile = tiles + (size_t)t * TSB * TSB;
     const bool offd = I != J;
+#pragma unroll 4
     for (int it = 0; it < TSB / 16; ++it) {
         const int r = 16 * it + 4 * w + g;
-        const T *row = tile + (size_t)r * TSB + 2 * q;
         A a[NE];
-#pragma unroll
-        for (int s = 0; s < NE / 2; ++s) {
-            a[2 * s] = (A)row[32 * s];
-            a[2 * s + 1] = (A)row[32 * s + 1];
-        }
+        BLd<T, TBB>::load(tile + (size_t)r * TSB, q, a);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             A rs = 0.0;
@@ -318,7 +373,7 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int nkb, int nk,
             double s = cacc[j][c];
             s += __shfl_xor(s, 16);
             s += __shfl_xor(s, 32);
-            if (g == 0) scol[w][j][32 * (c >> 1) + 2 * q + (c & 1)] = s;
+            if (g == 0) scol[w][j][BLd<T, TBB>::col(q, c)] = s;
         }
     __syncthreads();
     for (int z = threadIdx.x; z < M * TSB; z += blockDim.x) {
@@ -328,160 +383,218 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int nkb, int nk,
     }
 }
 
-// Chunk sum (box order) and T_k = 2 m(k) (I - khat khat) (C_k or S_k):
-// workgroup (16 wave vectors x 64 chunk groups), grid (k blocks, 2 M, box).
-__global__ __launch_bounds__(1024) void k_bsf_reduce(int nk, const BoxDev *__restrict__ boxes,
-                                                     const KCoef *__restrict__ kcoef,
-                                                     const double *__restrict__ sfpart,
-                                                     double *__restrict__ tk)
+// Chunk sum and T_k = 2 m(k) (I - khat khat) (C_k or S_k) of every box: one
+// thread per (k, vector j, half), grid (k blocks of 64, 2 M, box).  The
+// chunks of the box are summed in ascending order (loads coalesced over k).
+// Output tk[box][j][k][6] = (T^C_k, T^S_k).
+__global__ __launch_bounds__(64) void k_bsf_reduce(int nk, const BoxDev *__restrict__ boxes,
+                                                   const KCoef *__restrict__ kcoef,
+                                                   const double *__restrict__ sfpart,
+                                                   double *__restrict__ tk)
 {
-    __shared__ double red[16][3][16];
     const BoxDev &d = boxes[blockIdx.z];
-    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int kk = lane & 15, sub = lane >> 4;
-    const int k = blockIdx.x * 16 + kk;
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= nk) return;
     const int j = blockIdx.y >> 1, half = blockIdx.y & 1;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    if (k < nk) {
-        const size_t cst = (size_t)6 * BRC * nk;
-        const double *o = sfpart + (size_t)d.tile0 * cst + (size_t)(6 * j + 3 * half) * nk + k;
-        for (int ch = 4 * g + sub; ch < d.nbt; ch += 64) {
-            s0 += o[ch * cst];
-            s1 += o[ch * cst + nk];
-            s2 += o[ch * cst + 2 * (size_t)nk];
+    const size_t cst = (size_t)6 * BRC * nk;
+    const double *o = sfpart + (size_t)d.tile0 * cst + (size_t)(6 * j + 3 * half) * nk + k;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    const int nb = d.nbt;
+    int ch = 0;
+    for (; ch + 4 <= nb; ch += 4) {
+        double a[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double *p = o + (size_t)(ch + q) * cst;
+            a[q][0] = p[0];
+            a[q][1] = p[nk];
+            a[q][2] = p[2 * (size_t)nk];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            t0 += a[q][0];
+            t1 += a[q][1];
+            t2 += a[q][2];
         }
     }
-    s0 += __shfl_xor(s0, 16);
-    s0 += __shfl_xor(s0, 32);
-    s1 += __shfl_xor(s1, 16);
-    s1 += __shfl_xor(s1, 32);
-    s2 += __shfl_xor(s2, 16);
-    s2 += __shfl_xor(s2, 32);
-    if (sub == 0) {
-        red[g][0][kk] = s0;
-        red[g][1][kk] = s1;
-        red[g][2][kk] = s2;
-    }
-    __syncthreads();
-    if (threadIdx.x >= 16 || k >= nk) return;
-    double t[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        double a = 0.0;
-#pragma unroll
-        for (int w = 0; w < 16; ++w) a += red[w][c][kk];
-        t[c] = a;
+    for (; ch < nb; ++ch) {
+        const double *p = o + (size_t)ch * cst;
+        t0 += p[0];
+        t1 += p[nk];
+        t2 += p[2 * (size_t)nk];
     }
     const KCoef kc = kcoef[(size_t)blockIdx.z * nk + k];
-    const double h = kc.hx * t[0] + kc.hy * t[1] + kc.hz * t[2];
-    double *o = tk + (((size_t)blockIdx.z * nk + k) * BRC + j) * 6 + 3 * half;
-    o[0] = kc.w * (t[0] - kc.hx * h);
-    o[1] = kc.w * (t[1] - kc.hy * h);
-    o[2] = kc.w * (t[2] - kc.hz * h);
+    const double h = kc.hx * t0 + kc.hy * t1 + kc.hz * t2;
+    double *out = tk + (((size_t)blockIdx.z * BRC + j) * nk + k) * 6 + 3 * half;
+    out[0] = kc.w * (t0 - kc.hx * h);
+    out[1] = kc.w * (t1 - kc.hy * h);
+    out[2] = kc.w * (t2 - kc.hz * h);
 }
 
-// Back-projection + partial sum + epilogue for 16 beads (one box), as
-// k_kspace_epi: 64 slices; slice u sums the box's tile-column slots K = u,
-// u + 64, ... and the wave vectors [u nk/64, (u+1) nk/64) with the n_z phase
-// recursion; fixed-order combination; per-box recurrence scalars.
-template <int TBB, int M>
-__global__ __launch_bounds__(1024) void k_bepi(int G3, int nk, const int *__restrict__ tile_box,
-                                               const BoxDev *__restrict__ boxes,
-                                               const KVec *__restrict__ kvec,
-                                               const double *__restrict__ sfr,
-                                               const double *__restrict__ part,
-                                               const double *__restrict__ tk, EpiArgs f,
-                                               const double *__restrict__ scal_all)
+// Back-projection + partial sum + epilogue of one bead tile (TBB beads of
+// one box), 256 threads: S = 256 / TBB slices per bead.  Slice u sums the
+// box's tile-column slots K = u, u + S, ... and the wave vectors
+// [u nk / S, (u + 1) nk / S).  The wave vectors are walked as runs of
+// consecutive n_z at fixed (n_x, n_y) (runs[r] = (n_x, n_y, first n_z, first
+// k), runs[nruns].w = nk; krun[k] = run of k); the phase of bead l is
+// e^{i 2 pi n.s} = ex[n_x] ey[n_y] ez[n_z] from its wrap tables (negative
+// components conjugate), ex ey once per run.  Slices are combined in
+// ascending order.  STAGE: the box's T_k are copied to LDS (else read from
+// global memory).  Every global load of the prologue (partial slots, tables,
+// T_k) is issued before the first wait.  Padding beads get zero outputs;
+// recurrence scalars are per box.
+constexpr int EPI_SLOTS = 8;    // partial slots per slice held in registers
+constexpr int EPI_TAB = 6;      // table entries (double2) per thread and round
+constexpr int EPI_TK = 8;       // T_k entries (double2) per thread and round
+
+template <int TBB, int M, bool STAGE>
+__global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns,
+                                              const int *__restrict__ tile_box,
+                                              const BoxDev *__restrict__ boxes,
+                                              const int4 *__restrict__ runs,
+                                              const int *__restrict__ krun,
+                                              const double2 *__restrict__ etab,
+                                              const double *__restrict__ part,
+                                              const double *__restrict__ tk, EpiArgs f,
+                                              const double *__restrict__ scal_all)
 {
-    __shared__ double red[16][3][16];
-    const int g0 = blockIdx.x * 16;
-    const int b = tile_box[g0 / TBB];
+    constexpr int S = 256 / TBB;
+    extern __shared__ double sm[];
+    const int tile = blockIdx.x;
+    const int b = tile_box[tile];
     const BoxDev &d = boxes[b];
     const double *scal = scal_all ? scal_all + (size_t)b * BSCAL : nullptr;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int bl = lane & 15, sub = lane >> 4;
-    const int u = 4 * w + sub;
-    const int gb = g0 + bl;
-    const bool live = gb - d.tile0 * TBB < d.N;
-    const double sx = live ? sfr[3 * gb] : 0.0, sy = live ? sfr[3 * gb + 1] : 0.0,
-                 sz = live ? sfr[3 * gb + 2] : 0.0;
+    const double *tkb = tk + (size_t)b * BRC * nk * 6;   // [j][k][6] of this box
+    // LDS: phase tables [3 nm1][TBB] (double2), runs [nruns + 1] (int4), then
+    // the staged T_k [M][nk][6]
+    double2 *tab = reinterpret_cast<double2 *>(sm);
+    int4 *srun = reinterpret_cast<int4 *>(sm + 2 * 3 * nm1 * TBB);
+    double *stk = sm + 2 * 3 * nm1 * TBB + 2 * (nruns + 1);
+    const int l = threadIdx.x % TBB, u = threadIdx.x / TBB;
+    const int g = tile * TBB + l;
+    const bool live = (tile - d.tile0) * TBB + l < d.N;
+    const int nbt = d.nbt;
+    // partial slots K = u + S i (i < EPI_SLOTS per round), clamped addresses
     double y[M][3];
 #pragma unroll
     for (int j = 0; j < M; ++j) y[j][0] = y[j][1] = y[j][2] = 0.0;
-    if (live) {
-        for (int K = u; K < d.nbt; K += 64) {
+    for (int K0 = u; K0 < nbt; K0 += S * EPI_SLOTS) {
+        double pv[EPI_SLOTS][M][3];
+#pragma unroll
+        for (int i = 0; i < EPI_SLOTS; ++i) {
+            const int K = min(K0 + S * i, nbt - 1);
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                const double *pp = part + ((size_t)K * BRC + j) * G3 + 3 * gb;
-                y[j][0] += pp[0];
-                y[j][1] += pp[1];
-                y[j][2] += pp[2];
+                const double *pp = part + ((size_t)K * BRC + j) * G3 + 3 * (size_t)g;
+                pv[i][j][0] = pp[0];
+                pv[i][j][1] = pp[1];
+                pv[i][j][2] = pp[2];
             }
         }
-        const int klo = (int)((long)u * nk / 64), khi = (int)((long)(u + 1) * nk / 64);
-        double ezr, ezi;
-        sincospi(2.0 * sz, &ezi, &ezr);
-        double cs = 1.0, sn = 0.0;
-        int px = -(1 << 30), py = 0, pz = 0;
-        const double *tb = tk + (size_t)b * nk * BRC * 6;
-        for (int k = klo; k < khi; ++k) {
-            const KVec kv = kvec[k];
-            if (kv.nx == px && kv.ny == py && kv.nz == pz + 1) {
-                const double c2 = cs * ezr - sn * ezi;
-                sn = cs * ezi + sn * ezr;
-                cs = c2;
-            } else {
-                sincospi(2.0 * (kv.nx * sx + kv.ny * sy + kv.nz * sz), &sn, &cs);
-            }
-            px = kv.nx;
-            py = kv.ny;
-            pz = kv.nz;
-            const double *tt = tb + (size_t)k * BRC * 6;
+#pragma unroll
+        for (int i = 0; i < EPI_SLOTS; ++i)
 #pragma unroll
             for (int j = 0; j < M; ++j)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) y[j][c] += cs * tt[6 * j + c] + sn * tt[6 * j + 3 + c];
+                for (int c = 0; c < 3; ++c)
+                    y[j][c] += K0 + S * i < nbt ? pv[i][j][c] : 0.0;
+    }
+    // phase tables of the tile's beads
+    const int ntab = 3 * nm1 * TBB;
+    for (int q0 = 0; q0 < ntab; q0 += 256 * EPI_TAB) {
+        double2 tv[EPI_TAB];
+#pragma unroll
+        for (int i = 0; i < EPI_TAB; ++i) {
+            const int q = min(q0 + 256 * i + (int)threadIdx.x, ntab - 1);
+            const int ql = q % TBB, rj = q / TBB;   // rj = axis * nm1 + j
+            tv[i] = etab[(size_t)(tile * TBB + ql) * 3 * nm1 + rj];
+        }
+#pragma unroll
+        for (int i = 0; i < EPI_TAB; ++i) {
+            const int q = q0 + 256 * i + (int)threadIdx.x;
+            if (q < ntab) tab[q] = tv[i];
         }
     }
-    const double ya = scal ? scal[2] : 0.0, yb = scal ? scal[3] : 0.0;
+    for (int q = threadIdx.x; q <= nruns; q += 256) srun[q] = runs[q];
+    if (STAGE) {
+        const int ntk = nk * 3 * M;   // double2 entries of T_k for j < M
+        const double2 *src = reinterpret_cast<const double2 *>(tkb);
+        double2 *dst = reinterpret_cast<double2 *>(stk);
+        for (int q0 = 0; q0 < ntk; q0 += 256 * EPI_TK) {
+            double2 tv[EPI_TK];
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
+            for (int i = 0; i < EPI_TK; ++i)
+                tv[i] = src[min(q0 + 256 * i + (int)threadIdx.x, ntk - 1)];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double vv = y[j][c];
-            vv += __shfl_xor(vv, 16);
-            vv += __shfl_xor(vv, 32);
-            if (sub == 0) red[w][c][bl] = vv;
+            for (int i = 0; i < EPI_TK; ++i) {
+                const int q = q0 + 256 * i + (int)threadIdx.x;
+                if (q < ntk) dst[q] = tv[i];
+            }
         }
-        __syncthreads();
-        if (threadIdx.x < 48) {
-            const int bb = threadIdx.x / 3, c = threadIdx.x % 3;
-            const int gg = g0 + bb;
-            const size_t o = (size_t)j * G3 + 3 * gg + c;
-            if (gg - d.tile0 * TBB >= d.N) {   // padding bead: zero outputs
-                f.vout[o] = 0.0;
-                if (f.mode != EPI_APPLY) f.acc[o] = 0.0;
-                if (f.mode == EPI_CHEB_FIRST && f.dv) f.dv[o] = 0.0;
-            } else {
-                double yy = 0.0;
+    }
+    const int klo = (int)((long)u * nk / S), khi = (int)((long)(u + 1) * nk / S);
+    const int r0 = klo < khi ? krun[klo] : 0;
+    __syncthreads();
+    const double *tks = STAGE ? stk : tkb;
+    if (live) {
+        const double2 *tx = tab + l, *ty = tab + nm1 * TBB + l, *tz = tab + 2 * nm1 * TBB + l;
+        int k = klo;
+        for (int r = r0; k < khi; ++r) {
+            const int4 R = srun[r];
+            const int kend = min(khi, srun[r + 1].w);
+            const double2 ex = tx[R.x * TBB];
+            double2 ey = ty[(R.y < 0 ? -R.y : R.y) * TBB];
+            if (R.y < 0) ey.y = -ey.y;
+            const double xr = ex.x * ey.x - ex.y * ey.y, xi = ex.x * ey.y + ex.y * ey.x;
+            for (; k < kend; ++k) {
+                const int nz = R.z + (k - R.w);
+                double2 ez = tz[(nz < 0 ? -nz : nz) * TBB];
+                if (nz < 0) ez.y = -ez.y;
+                const double cs = xr * ez.x - xi * ez.y, sn = xr * ez.y + xi * ez.x;
 #pragma unroll
-                for (int ww = 0; ww < 16; ++ww) yy += red[ww][c][bb];
-                if (f.mode == EPI_APPLY) {
-                    f.vout[o] = yy;
-                } else if (f.mode == EPI_CHEB_FIRST) {
-                    const double v0 = f.vprev[o];
-                    const double v1 = ya * yy - yb * v0;
-                    f.vout[o] = v1;
-                    f.acc[o] = 0.5 * scal[8] * v0 + scal[9] * v1;
-                    if (f.dv) f.dv[o] = yy;
-                } else {
-                    const double vp = 2.0 * (ya * yy - yb * f.vprev[o]) - f.vprev2[o];
-                    f.vout[o] = vp;
-                    f.acc[o] += scal[8 + f.p] * vp;
+                for (int j = 0; j < M; ++j) {
+                    const double *tt = tks + ((size_t)j * nk + k) * 6;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) y[j][c] += cs * tt[c] + sn * tt[3 + c];
                 }
             }
         }
-        __syncthreads();
+    }
+    __syncthreads();   // tables and staged T_k are reused below
+    double *red = sm;  // [S][3 M][TBB]
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) red[(u * 3 * M + 3 * j + c) * TBB + l] = y[j][c];
+    __syncthreads();
+    const double ya = scal ? scal[2] : 0.0, yb = scal ? scal[3] : 0.0;
+    const int nreal = d.N - (tile - d.tile0) * TBB;   // real beads of this tile (may exceed TBB)
+    for (int q = threadIdx.x; q < 3 * TBB * M; q += 256) {
+        const int j = q / (3 * TBB), qq = q % (3 * TBB);
+        const int bl = qq / 3, c = qq % 3;
+        const size_t o = (size_t)j * G3 + 3 * (size_t)tile * TBB + qq;
+        if (bl >= nreal) {   // padding bead: zero outputs
+            f.vout[o] = 0.0;
+            if (f.mode != EPI_APPLY) f.acc[o] = 0.0;
+            if (f.mode == EPI_CHEB_FIRST && f.dv) f.dv[o] = 0.0;
+            continue;
+        }
+        double yy = 0.0;
+#pragma unroll
+        for (int w = 0; w < S; ++w) yy += red[(w * 3 * M + 3 * j + c) * TBB + bl];
+        if (f.mode == EPI_APPLY) {
+            f.vout[o] = yy;
+        } else if (f.mode == EPI_CHEB_FIRST) {
+            const double v0 = f.vprev[o];
+            const double v1 = ya * yy - yb * v0;
+            f.vout[o] = v1;
+            f.acc[o] = 0.5 * scal[8] * v0 + scal[9] * v1;
+            if (f.dv) f.dv[o] = yy;
+        } else {
+            const double vp = 2.0 * (ya * yy - yb * f.vprev[o]) - f.vprev2[o];
+            f.vout[o] = vp;
+            f.acc[o] += scal[8 + f.p] * vp;
+        }
     }
 }
 
@@ -630,6 +743,9 @@ struct rpy_batch {
     int4 *stor = nullptr;         // [nstor] (box, I, J, 0)
     int2 *chains = nullptr;       // [nchain] (box, chain)
     KVec *kvec = nullptr;         // [nk], shared by all boxes
+    int nruns = 0;
+    int4 *runs = nullptr;         // [nruns + 1] runs of consecutive n_z (n_x, n_y, n_z0, k0)
+    int *krun = nullptr;          // [nk] run of each wave vector
     KCoef *kcoef = nullptr;       // [nbox][nk]
     double *rt = nullptr, *sfr = nullptr;   // [G][3]
     double2 *etab = nullptr;      // [G][3][nmax + 1]
@@ -637,7 +753,7 @@ struct rpy_batch {
     float *d32 = nullptr;
     double *part = nullptr;       // [maxnbt][BRC][3G]
     double *sfpart = nullptr;     // [ntb][6 BRC][nk]
-    double *tk = nullptr;         // [nbox][nk][BRC][6]
+    double *tk = nullptr;         // [nbox][BRC][nk][6]
     double *scal = nullptr;       // [nbox][BSCAL]
     double *work = nullptr;
     double *FU = nullptr;         // [2][3G]: forces, U+
@@ -686,7 +802,8 @@ extern "C" void rpy_batch_destroy(rpy_batch *b)
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cs) (void)hipStreamDestroy(b->cs);
-    void *bufs[] = {b->boxes, b->tile_box, b->stor, b->chains, b->kvec, b->kcoef, b->rt,
+    void *bufs[] = {b->boxes, b->tile_box, b->stor, b->chains, b->kvec, b->runs, b->krun,
+                    b->kcoef, b->rt,
                     b->sfr, b->etab, b->d64, b->d32, b->part, b->sfpart, b->tk, b->scal,
                     b->work, b->flags, b->stepc};
     for (void *p : bufs)
@@ -779,6 +896,16 @@ extern "C" int rpy_batch_create(rpy_batch **out, const rpy_params *bp, int nbox,
                 kv.push_back(KVec{nx, ny, nz, 0});
             }
     b->nk = (int)kv.size();
+    std::vector<int4> runs;
+    std::vector<int> krun(b->nk);
+    for (int k = 0; k < b->nk; ++k) {
+        if (k == 0 || kv[k].nx != kv[k - 1].nx || kv[k].ny != kv[k - 1].ny ||
+            kv[k].nz != kv[k - 1].nz + 1)
+            runs.push_back(make_int4(kv[k].nx, kv[k].ny, kv[k].nz, k));
+        krun[k] = (int)runs.size() - 1;
+    }
+    b->nruns = (int)runs.size();
+    runs.push_back(make_int4(0, 0, 0, b->nk));   // sentinel: end of the last run
     std::vector<KCoef> kc((size_t)nbox * b->nk);
     for (int i = 0; i < nbox; ++i) {
         const double L = bp[i].box_l, a = bp[i].a, al2 = bp[i].alpha * bp[i].alpha;
@@ -799,7 +926,8 @@ extern "C" int rpy_batch_create(rpy_batch **out, const rpy_params *bp, int nbox,
     int rc;
     if ((rc = balloc(&b->boxes, nbox)) || (rc = balloc(&b->tile_box, b->ntb)) ||
         (rc = balloc(&b->stor, b->nstor)) || (rc = balloc(&b->chains, b->nchain)) ||
-        (rc = balloc(&b->kvec, b->nk)) || (rc = balloc(&b->kcoef, kc.size())) ||
+        (rc = balloc(&b->kvec, b->nk)) || (rc = balloc(&b->runs, runs.size())) ||
+        (rc = balloc(&b->krun, b->nk)) || (rc = balloc(&b->kcoef, kc.size())) ||
         (rc = balloc(&b->rt, G3)) || (rc = balloc(&b->sfr, G3)) ||
         (rc = balloc(&b->etab, G3 * (nmax + 1))) || (rc = balloc(&b->d64, te)) ||
         (lowp == RPY_PREC_F32 && (rc = balloc(&b->d32, te))) ||
@@ -827,6 +955,8 @@ extern "C" int rpy_batch_create(rpy_batch **out, const rpy_params *bp, int nbox,
         (e = hipMemcpy(b->chains, chains.data(), chains.size() * sizeof(int2),
                        hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(b->kvec, kv.data(), kv.size() * sizeof(KVec), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(b->runs, runs.data(), runs.size() * sizeof(int4), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(b->krun, krun.data(), krun.size() * sizeof(int), hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(b->kcoef, kc.data(), kc.size() * sizeof(KCoef), hipMemcpyHostToDevice)) ||
         (e = hipMemset(b->flags, 0, 4 * sizeof(int))) ||
         (e = hipMemset(b->work, 0, 9 * G3 * sizeof(double))) ||
@@ -884,8 +1014,10 @@ static void bsymv(rpy_batch *b, const T *tiles, const double *v, hipStream_t s)
     const int nsf = b->ntb * nkb;
     const size_t sm_sf = (size_t)(2 * TBB * 3 * nm1 + TBB * 3 * M) * sizeof(double);
     const size_t sm_t = (size_t)5 * M * 3 * TBB * sizeof(double);
-    hipLaunchKernelGGL((k_bsymv<TBB, T, M>), dim3(nsf + b->nstor), dim3(256),
-                       sm_sf > sm_t ? sm_sf : sm_t, s, 3 * b->G, nsf, nkb, b->nk, nm1,
+    const int total = nsf + b->nstor;
+    const int sfr = total / nsf > 1 ? total / nsf : 1;   // one structure-factor workgroup per sfr
+    hipLaunchKernelGGL((k_bsymv<TBB, T, M>), dim3(total), dim3(256),
+                       sm_sf > sm_t ? sm_sf : sm_t, s, 3 * b->G, nsf, sfr, nkb, b->nk, nm1,
                        b->tile_box, b->boxes, b->stor, b->kvec, b->etab, b->sfpart, tiles, v,
                        b->part);
 }
@@ -902,15 +1034,31 @@ static void bproduct(rpy_batch *b, const double *v, int m, int prec, const EpiAr
         if (m == 2) bsymv<TBB, double, 2>(b, b->d64, v, s);
         else bsymv<TBB, double, 1>(b, b->d64, v, s);
     }
-    hipLaunchKernelGGL(k_bsf_reduce, dim3((b->nk + 15) / 16, 2 * m, b->nbox), dim3(1024), 0, s,
+    hipLaunchKernelGGL(k_bsf_reduce, dim3((b->nk + 63) / 64, 2 * m, b->nbox), dim3(64), 0, s,
                        b->nk, b->boxes, b->kcoef, b->sfpart, b->tk);
-    const dim3 ge((unsigned)(b->G / 16));
-    if (m == 2)
-        hipLaunchKernelGGL((k_bepi<TBB, 2>), ge, dim3(1024), 0, s, 3 * b->G, b->nk, b->tile_box,
-                           b->boxes, b->kvec, b->sfr, b->part, b->tk, f, scal);
-    else
-        hipLaunchKernelGGL((k_bepi<TBB, 1>), ge, dim3(1024), 0, s, 3 * b->G, b->nk, b->tile_box,
-                           b->boxes, b->kvec, b->sfr, b->part, b->tk, f, scal);
+    // LDS: phase tables and runs, plus the box's T_k when they fit in 64 KiB
+    // together; the region is reused for the slice sums
+    const int nm1 = b->nmax + 1;
+    const size_t tabb = (size_t)2 * 3 * nm1 * TBB * sizeof(double) +
+                        (size_t)(b->nruns + 1) * sizeof(int4);
+    const size_t red = (size_t)3 * m * 256 * sizeof(double);
+    const size_t stk = (size_t)b->nk * 6 * m * sizeof(double);
+    const bool stage = tabb + stk <= 65536;
+    size_t lds = tabb + (stage ? stk : 0);
+    lds = lds > red ? lds : red;
+    const dim3 ge((unsigned)b->ntb);
+#define RPY_BEPI(MM, ST)                                                                      \
+    hipLaunchKernelGGL((k_bepi<TBB, MM, ST>), ge, dim3(256), lds, s, 3 * b->G, b->nk, nm1,    \
+                       b->nruns, b->tile_box, b->boxes, b->runs, b->krun, b->etab, b->part,  \
+                       b->tk, f, scal)
+    if (m == 2) {
+        if (stage) RPY_BEPI(2, true);
+        else RPY_BEPI(2, false);
+    } else {
+        if (stage) RPY_BEPI(1, true);
+        else RPY_BEPI(1, false);
+    }
+#undef RPY_BEPI
 }
 
 // Chebyshev interval + coefficients of every box and the recurrence on dw.
