@@ -195,6 +195,10 @@ __global__ __launch_bounds__(256) void k_bbuild(const int4 *__restrict__ stor,
 // 16-byte quads at 64 s + 4 q (64-bead tiles) or a quad at 4 q plus a pair
 // at 64 + 2 q (32-bead tiles).  Every row is read once, contiguously across
 // the row group.
+// Tiles are read once per product: non-temporal loads.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 template <typename T, int TBB> struct BLd;
 template <int TBB> struct BLd<double, TBB> {
     static constexpr int NE = 3 * TBB / 16;
@@ -203,7 +207,8 @@ template <int TBB> struct BLd<double, TBB> {
     {
 #pragma unroll
         for (int s = 0; s < NE / 2; ++s) {
-            const double2 v = *reinterpret_cast<const double2 *>(row + 32 * s + 2 * q);
+            const d2v v =
+                __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 32 * s + 2 * q));
             a[2 * s] = v.x;
             a[2 * s + 1] = v.y;
         }
@@ -216,7 +221,8 @@ template <> struct BLd<float, 64> {
     {
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const float4 v = *reinterpret_cast<const float4 *>(row + 64 * s + 4 * q);
+            const f4v v =
+                __builtin_nontemporal_load(reinterpret_cast<const f4v *>(row + 64 * s + 4 * q));
             a[4 * s] = v.x;
             a[4 * s + 1] = v.y;
             a[4 * s + 2] = v.z;
@@ -229,8 +235,8 @@ template <> struct BLd<float, 32> {
     __device__ static int col(int q, int e) { return e < 4 ? 4 * q + e : 64 + 2 * q + (e - 4); }
     __device__ static void load(const float *row, int q, double a[NE])
     {
-        const float4 v = *reinterpret_cast<const float4 *>(row + 4 * q);
-        const float2 u = *reinterpret_cast<const float2 *>(row + 64 + 2 * q);
+        const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(row + 4 * q));
+        const f2v u = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(row + 64 + 2 * q));
         a[0] = v.x;
         a[1] = v.y;
         a[2] = v.z;
@@ -441,7 +447,8 @@ __global__ __launch_bounds__(64) void k_bsf_reduce(int nk, const BoxDev *__restr
 // components conjugate), ex ey once per run.  Slices are combined in
 // ascending order.  STAGE: the box's T_k are copied to LDS (else read from
 // global memory).  Every global load of the prologue (partial slots, tables,
-// T_k) is issued before the first wait.  Padding beads get zero outputs;
+// T_k) is issued before the first wait (the table pointers are not
+// __restrict__ so that the compiler keeps the loads where they are written).  Padding beads get zero outputs;
 // recurrence scalars are per box.
 constexpr int EPI_SLOTS = 8;    // partial slots per slice held in registers
 constexpr int EPI_TAB = 6;      // table entries (double2) per thread and round
@@ -453,9 +460,9 @@ __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns
                                               const BoxDev *__restrict__ boxes,
                                               const int4 *__restrict__ runs,
                                               const int *__restrict__ krun,
-                                              const double2 *__restrict__ etab,
+                                              const double2 *etab,
                                               const double *__restrict__ part,
-                                              const double *__restrict__ tk, EpiArgs f,
+                                              const double *tk, EpiArgs f,
                                               const double *__restrict__ scal_all)
 {
     constexpr int S = 256 / TBB;
@@ -465,11 +472,14 @@ __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns
     const BoxDev &d = boxes[b];
     const double *scal = scal_all ? scal_all + (size_t)b * BSCAL : nullptr;
     const double *tkb = tk + (size_t)b * BRC * nk * 6;   // [j][k][6] of this box
-    // LDS: phase tables [3 nm1][TBB] (double2), runs [nruns + 1] (int4), then
-    // the staged T_k [M][nk][6]
+    // LDS: phase tables [3 nm1][TBB] (double2) + 1 slack entry, runs
+    // [nruns + 1] (int4), then the staged T_k [M][nk][6] + 1 slack double2.
+    // Loads past the end are clamped and their copies land in the slack
+    // entries, so that loads and LDS writes stay unconditional (and batched).
+    const int ntab = 3 * nm1 * TBB;
     double2 *tab = reinterpret_cast<double2 *>(sm);
-    int4 *srun = reinterpret_cast<int4 *>(sm + 2 * 3 * nm1 * TBB);
-    double *stk = sm + 2 * 3 * nm1 * TBB + 2 * (nruns + 1);
+    int4 *srun = reinterpret_cast<int4 *>(sm + 2 * (ntab + 1));
+    double *stk = sm + 2 * (ntab + 1) + 2 * (nruns + 1);
     const int l = threadIdx.x % TBB, u = threadIdx.x / TBB;
     const int g = tile * TBB + l;
     const bool live = (tile - d.tile0) * TBB + l < d.N;
@@ -500,7 +510,6 @@ __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns
                     y[j][c] += K0 + S * i < nbt ? pv[i][j][c] : 0.0;
     }
     // phase tables of the tile's beads
-    const int ntab = 3 * nm1 * TBB;
     for (int q0 = 0; q0 < ntab; q0 += 256 * EPI_TAB) {
         double2 tv[EPI_TAB];
 #pragma unroll
@@ -510,10 +519,7 @@ __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns
             tv[i] = etab[(size_t)(tile * TBB + ql) * 3 * nm1 + rj];
         }
 #pragma unroll
-        for (int i = 0; i < EPI_TAB; ++i) {
-            const int q = q0 + 256 * i + (int)threadIdx.x;
-            if (q < ntab) tab[q] = tv[i];
-        }
+        for (int i = 0; i < EPI_TAB; ++i) tab[min(q0 + 256 * i + (int)threadIdx.x, ntab)] = tv[i];
     }
     for (int q = threadIdx.x; q <= nruns; q += 256) srun[q] = runs[q];
     if (STAGE) {
@@ -526,10 +532,7 @@ __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns
             for (int i = 0; i < EPI_TK; ++i)
                 tv[i] = src[min(q0 + 256 * i + (int)threadIdx.x, ntk - 1)];
 #pragma unroll
-            for (int i = 0; i < EPI_TK; ++i) {
-                const int q = q0 + 256 * i + (int)threadIdx.x;
-                if (q < ntk) dst[q] = tv[i];
-            }
+            for (int i = 0; i < EPI_TK; ++i) dst[min(q0 + 256 * i + (int)threadIdx.x, ntk)] = tv[i];
         }
     }
     const int klo = (int)((long)u * nk / S), khi = (int)((long)(u + 1) * nk / S);
@@ -1039,10 +1042,10 @@ static void bproduct(rpy_batch *b, const double *v, int m, int prec, const EpiAr
     // LDS: phase tables and runs, plus the box's T_k when they fit in 64 KiB
     // together; the region is reused for the slice sums
     const int nm1 = b->nmax + 1;
-    const size_t tabb = (size_t)2 * 3 * nm1 * TBB * sizeof(double) +
+    const size_t tabb = (size_t)(3 * nm1 * TBB + 1) * sizeof(double2) +
                         (size_t)(b->nruns + 1) * sizeof(int4);
     const size_t red = (size_t)3 * m * 256 * sizeof(double);
-    const size_t stk = (size_t)b->nk * 6 * m * sizeof(double);
+    const size_t stk = (size_t)b->nk * 6 * m * sizeof(double) + sizeof(double2);
     const bool stage = tabb + stk <= 65536;
     size_t lds = tabb + (stage ? stk : 0);
     lds = lds > red ? lds : red;
