@@ -58,6 +58,7 @@ def _L():
             "orc_real_space": (None, [i, p, d, d, d, d, p]),
             "orc_real_space_rows": (None, [i, p, d, d, d, d, i, _ip, p]),
             "orc_recip_space_rows": (None, [i, p, d, d, d, i, i, _ip, p]),
+            "orc_u_vjp_rows": (None, [i, p, d, d, d, d, i, p, p, p, i, d, d, i, _ip, p, p]),
             "orc_self_term_rows": (None, [i, d, d, i, _ip, p]),
             "orc_self_term": (None, [i, d, d, p]),
             "orc_recip_space": (None, [i, p, d, d, d, i, p]),
@@ -377,3 +378,32 @@ def bd_step(pos, *, nchains, bpc, L, a, alpha, rc, n2max, dt, nch, dmin=None,
     new = euler(pos, dt, ud, ds)
     return {"pos": new, "drift": ud, "ds": ds, "dw": dw, "dmin": dmin,
             "dmax": dmax, "ef": ef, "F": F}
+
+
+# ---------------------------------------------------------- differentiation
+def u_forward(pos, L, a, alpha, rc, n2max, F, dw, nch, dmin, dmax) -> np.ndarray:
+    """u = D(R) F + p(D(R)) dW: the drift product plus the Chebyshev sum of
+    eq. cheb1-cheb3 on a fixed interval (the quantity whose reverse mode
+    u_vjp computes)."""
+    D = diffusion_matrix(pos, L, a, alpha, rc, n2max)
+    n3 = D.shape[0]
+    return (matvec(D, _f64(F).reshape(1, n3)) +
+            cheb_sqrt(D, _f64(dw).reshape(1, n3), nch, dmin, dmax)).reshape(-1, 3)
+
+
+def u_vjp(pos, L, a, alpha, rc, n2max, F, dw, g, nch, dmin, dmax, rows=None):
+    """Reverse mode of u_forward for L = g.u: (dL/dR for the listed beads
+    [len(rows), 3] (all beads when rows is None), dL/dF = D g [N, 3]).
+    Pair-term derivatives of eq. M1, b1/b2, cor5 and M2 written out in
+    rpy_oracle.c; the interval is held fixed."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    r = np.arange(n, dtype=np.intc) if rows is None else np.asarray(rows, dtype=np.intc)
+    r = np.ascontiguousarray(r)
+    gpos = np.zeros((len(r), 3))
+    gF = np.zeros((n, 3))
+    _L().orc_u_vjp_rows(n, _ptr(pos), L, a, alpha, rc, int(n2max), _ptr(_f64(F)),
+                        _ptr(_f64(dw)), _ptr(_f64(g)), int(nch), dmin, dmax, len(r),
+                        r.ctypes.data_as(_ip), _ptr(gpos), _ptr(gF))
+    return gpos, gF
+

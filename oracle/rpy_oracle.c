@@ -621,3 +621,214 @@ void orc_gaussian_noise(long count, uint64_t seed, uint64_t step, double dt,
         for (int j = 0; j < 4 && 4 * g + j < count; ++j) out[4 * g + j] = z[j] * sdt;
     }
 }
+
+/* ========================================================================
+ * Reverse mode of u = D(R) F + p(D(R)) dW, where p(D) dW is the Chebyshev
+ * sum dS of orc_cheb_sqrt with a fixed interval [dmin, dmax] (no
+ * dependence of the interval on R).  The derivatives of the pair terms are
+ * not printed in the paper; they are the r-derivatives of the coefficients
+ * of eq. M1, eq. b1/b2 and eq. cor5 as printed (with reading R2), and of
+ * the cosine of eq. M2, written out below.
+ *
+ * Given g = dL/du, dL/dF = D g (D symmetric) and, with the adjoint
+ * vectors of the recurrence
+ *   mu_p = c_p g + 2 Y mu_{p+1} - mu_{p+2}   (p = N_Ch-1 .. 1, mu_{N_Ch} = mu_{N_Ch+1} = 0),
+ * dL = sum_q x_q^T dD y_q over the pairs (x_q, y_q) = (g, F),
+ * (s mu_1, V_0), (2 s mu_p, V_{p-1}) for p >= 2, s = 2/(dmax - dmin).
+ * The pair block D_lm depends on d = r_l - r_m only and is even in d, so
+ *   dL/dr_l = sum_{m != l} grad_d [ W_lm : D(d) ] at d = r_l - r_m,
+ *   W_lm = sum_q (x_q,l y_q,m^T + x_q,m y_q,l^T)   (3 x 3).
+ * For D(d) = c1(r) I + c2(r) dhat dhat and symmetric Ws = (W + W^T)/2:
+ *   grad_k = c1' dhat_k tr(Ws) + c2' dhat_k (dhat.Ws.dhat)
+ *          + (c2 / r) (2 (Ws dhat)_k - 2 dhat_k (dhat.Ws.dhat)),
+ * and for the reciprocal part m(k) (I - khat khat) cos(k.d):
+ *   grad = - sum_{+-k} m(k) ((I - khat khat) : Ws) sin(k.d) k.
+ * The self term and the images of a bead with itself do not move with r_l.
+ * At r = 0 (coincident distinct beads) the pair term is not differentiable;
+ * it contributes nothing.
+ * ====================================================================== */
+
+/* d/dr of the M1 coefficients (eq. M1), binary128:
+ * c1 = e A + g B, c2 = e A2 + g B2 with e = erfc(al r), g = exp(-al^2 r^2)/sqrt(pi),
+ * de/dr = -2 al g, dg/dr = -2 al^2 r g. */
+static void m1_dcoeffs_q(__float128 r, __float128 a, __float128 al,
+                         __float128 *d1, __float128 *d2)
+{
+    __float128 a3 = a * a * a;
+    __float128 e = erfcq(al * r);
+    __float128 g = expq(-al * al * r * r) / sqrtq(M_PIq);
+    __float128 r2 = r * r, r3 = r2 * r, r4 = r2 * r2, r5 = r4 * r;
+    __float128 al3 = al * al * al, al5 = al3 * al * al, al7 = al5 * al * al;
+    __float128 A = 3 * a / (4 * r) + a3 / (2 * r3);
+    __float128 Ap = -3 * a / (4 * r2) - 3 * a3 / (2 * r4);
+    __float128 B = 3 * a * al3 * r2 - 9 * a * al / 2 + 4 * a3 * al7 * r4
+                 - 20 * a3 * al5 * r2 + 14 * a3 * al3 + a3 * al / r2;
+    __float128 Bp = 6 * a * al3 * r + 16 * a3 * al7 * r3 - 40 * a3 * al5 * r - 2 * a3 * al / r3;
+    __float128 A2 = 3 * a / (4 * r) - 3 * a3 / (2 * r3);
+    __float128 A2p = -3 * a / (4 * r2) + 9 * a3 / (2 * r4);
+    __float128 B2 = 3 * a * al / 2 - 3 * a * al3 * r2 - 4 * a3 * al7 * r4
+                  + 16 * a3 * al5 * r2 - 2 * a3 * al3 - 3 * a3 * al / r2;
+    __float128 B2p = -6 * a * al3 * r - 16 * a3 * al7 * r3 + 32 * a3 * al5 * r + 6 * a3 * al / r3;
+    (void)r5;
+    *d1 = -2 * al * g * A + e * Ap - 2 * al * al * r * g * B + g * Bp;
+    *d2 = -2 * al * g * A2 + e * A2p - 2 * al * al * r * g * B2 + g * B2p;
+}
+
+/* d/dx of the M* coefficients (eq. cor5 with reading R2), x = r/a:
+ * c1 = 1 - t1^2/(2x^3), t1 = 3x^2/4 + 1;  c2 = 3 t2^2/(2x^3), t2 = x^2/4 - 1. */
+static void mstar_dcoeffs_q(__float128 x, __float128 *d1, __float128 *d2)
+{
+    __float128 x2 = x * x, x3 = x2 * x, x4 = x2 * x2;
+    __float128 t1 = 3 * x2 / 4 + 1, t2 = x2 / 4 - 1;
+    *d1 = -t1 * (3 * x / 2) / x3 + 3 * t1 * t1 / (2 * x4);
+    *d2 = 3 * t2 / (2 * x2) - 9 * t2 * t2 / (2 * x4);
+}
+
+/* Gradient with respect to the image separation d of Ws : (c1 I + c2 dhat dhat)
+ * for one image (same branches as pair_image); added into gk. */
+static void pair_image_grad(const double d[3], double r2, int in_rc, int overlap,
+                            double a, double al, const double Ws[9], double gk[3])
+{
+    if (r2 == 0.0) return;
+    double r = sqrt(r2);
+    double c2 = 0.0, d1 = 0.0, d2 = 0.0;
+    if (overlap) {
+        if (in_rc && r / a < 1e-6) {
+            /* Omega_B - S with S even and smooth: S' = O(r) */
+            c2 = 3.0 * r / (32.0 * a);
+            d1 = -9.0 / (32.0 * a);
+            d2 = 3.0 / (32.0 * a);
+        } else {
+            __float128 rq = sqrtq((__float128)d[0] * d[0] + (__float128)d[1] * d[1]
+                                  + (__float128)d[2] * d[2]);
+            __float128 q1 = 0, q2 = 0, p1 = 0, p2 = 0, s1, s2, t1, t2;
+            if (in_rc) {
+                m1_coeffs_q(rq, a, al, &q1, &q2);
+                m1_dcoeffs_q(rq, a, al, &p1, &p2);
+            }
+            mstar_coeffs_q(rq / a, &s1, &s2);
+            mstar_dcoeffs_q(rq / a, &t1, &t2);
+            c2 = (double)(q2 + s2);
+            d1 = (double)(p1 + t1 / a);
+            d2 = (double)(p2 + t2 / a);
+        }
+    } else {
+        double c1v;
+        orc_m1_coeffs(r, a, al, &c1v, &c2);
+        __float128 p1, p2;
+        m1_dcoeffs_q(r, a, al, &p1, &p2);
+        d1 = (double)p1;
+        d2 = (double)p2;
+    }
+    double h[3] = {d[0] / r, d[1] / r, d[2] / r};
+    double tr = Ws[0] + Ws[4] + Ws[8];
+    double Wh[3], hWh = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        Wh[i] = Ws[3 * i] * h[0] + Ws[3 * i + 1] * h[1] + Ws[3 * i + 2] * h[2];
+        hWh += h[i] * Wh[i];
+    }
+    for (int k = 0; k < 3; ++k)
+        gk[k] += d1 * h[k] * tr + d2 * h[k] * hWh + (c2 / r) * (2.0 * Wh[k] - 2.0 * h[k] * hWh);
+}
+
+/* Reverse mode of u = D F + p(D) dW (see above) for the listed beads:
+ * gpos[ir][3] = dL/dr of bead rows[ir]; gF[3N] = D g (NULL: skipped).
+ * pos are unwrapped positions (the derivative of the wrap is 1). */
+void orc_u_vjp_rows(int n, const double *pos, double L, double a, double al, double rc,
+                    int n2max, const double *F, const double *dw, const double *g, int nch,
+                    double dmin, double dmax, int nrows, const int *rows, double *gpos,
+                    double *gF)
+{
+    long n3 = 3L * n;
+    double *rt = (double *)malloc(sizeof(double) * n3);
+    double *D = (double *)calloc((size_t)n3 * n3, sizeof(double));
+    orc_wrap(n, pos, L, rt);
+    orc_real_space(n, rt, L, a, al, rc, D);
+    orc_self_term(n, a, al, D);
+    orc_recip_space(n, rt, L, a, al, n2max, D);
+    if (gF) orc_matvec((int)n3, D, 1, g, gF);
+    /* forward recurrence, all V_p kept */
+    double *V = (double *)malloc(sizeof(double) * n3 * nch);
+    double *c = (double *)malloc(sizeof(double) * nch);
+    orc_cheb_coeffs(nch, dmin, dmax, c);
+    for (long i = 0; i < n3; ++i) V[i] = dw[i];
+    if (nch > 1) apply_Y((int)n3, D, dmin, dmax, V, V + n3);
+    for (int p = 2; p < nch; ++p) {
+        apply_Y((int)n3, D, dmin, dmax, V + (p - 1) * n3, V + p * n3);
+        for (long i = 0; i < n3; ++i) V[p * n3 + i] = 2.0 * V[p * n3 + i] - V[(p - 2) * n3 + i];
+    }
+    /* adjoint recurrence: mu[p], p = 1 .. nch-1 (mu[nch], mu[nch+1] = 0) */
+    double *mu = (double *)calloc((size_t)n3 * (nch + 2), sizeof(double));
+    double *t = (double *)malloc(sizeof(double) * n3);
+    for (int p = nch - 1; p >= 1; --p) {
+        double *m = mu + p * n3;
+        apply_Y((int)n3, D, dmin, dmax, mu + (p + 1) * n3, t);
+        for (long i = 0; i < n3; ++i)
+            m[i] = c[p] * g[i] + 2.0 * t[i] - mu[(p + 2) * n3 + i];
+    }
+    /* pairs (x_q, y_q), q = 0 .. nch-1 */
+    double s = 2.0 / (dmax - dmin);
+    int nq = nch;
+    double *X = (double *)malloc(sizeof(double) * n3 * nq);
+    double *Yv = (double *)malloc(sizeof(double) * n3 * nq);
+    for (long i = 0; i < n3; ++i) { X[i] = g[i]; Yv[i] = F[i]; }
+    for (int q = 1; q < nq; ++q) {
+        double f = q == 1 ? s : 2.0 * s;
+        for (long i = 0; i < n3; ++i) {
+            X[q * n3 + i] = f * mu[q * n3 + i];
+            Yv[q * n3 + i] = V[(q - 1) * n3 + i];
+        }
+    }
+    double vol = L * L * L;
+    int nm = (int)floor(sqrt((double)n2max)) + 1;
+    int ni = (int)ceil(rc / L) + 1;
+    double rc2 = rc * rc, a2x4 = 4.0 * a * a;
+#pragma omp parallel for schedule(dynamic)
+    for (int ir = 0; ir < nrows; ++ir) {
+        int l = rows[ir];
+        double acc[3] = {0, 0, 0};
+        for (int m = 0; m < n; ++m) {
+            if (m == l) continue;
+            double W[9] = {0};
+            for (int q = 0; q < nq; ++q)
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j)
+                        W[3 * i + j] += X[q * n3 + 3 * l + i] * Yv[q * n3 + 3 * m + j]
+                                      + X[q * n3 + 3 * m + i] * Yv[q * n3 + 3 * l + j];
+            double Ws[9];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) Ws[3 * i + j] = 0.5 * (W[3 * i + j] + W[3 * j + i]);
+            double d0[3] = {rt[3 * l] - rt[3 * m], rt[3 * l + 1] - rt[3 * m + 1],
+                            rt[3 * l + 2] - rt[3 * m + 2]};
+            /* real space: every image within rc or closer than 2a */
+            for (int nx = -ni; nx <= ni; ++nx)
+                for (int ny = -ni; ny <= ni; ++ny)
+                    for (int nz = -ni; nz <= ni; ++nz) {
+                        double d[3] = {d0[0] + nx * L, d0[1] + ny * L, d0[2] + nz * L};
+                        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                        int in_rc = r2 <= rc2, overlap = r2 < a2x4;
+                        if (!in_rc && !overlap) continue;
+                        pair_image_grad(d, r2, in_rc, overlap, a, al, Ws, acc);
+                    }
+            /* reciprocal space: full +-k set */
+            for (int kx = -nm; kx <= nm; ++kx)
+                for (int ky = -nm; ky <= nm; ++ky)
+                    for (int kz = -nm; kz <= nm; ++kz) {
+                        int n2 = kx * kx + ky * ky + kz * kz;
+                        if (n2 == 0 || n2 > n2max) continue;
+                        double k[3] = {2.0 * ORC_PI * kx / L, 2.0 * ORC_PI * ky / L,
+                                       2.0 * ORC_PI * kz / L};
+                        double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+                        double mk = orc_m2_scalar(sqrt(k2), a, al, vol);
+                        double PW = 0.0;
+                        for (int i = 0; i < 3; ++i)
+                            for (int j = 0; j < 3; ++j)
+                                PW += ((i == j ? 1.0 : 0.0) - k[i] * k[j] / k2) * Ws[3 * i + j];
+                        double sn = sin(k[0] * d0[0] + k[1] * d0[1] + k[2] * d0[2]);
+                        for (int i = 0; i < 3; ++i) acc[i] -= mk * PW * sn * k[i];
+                    }
+        }
+        for (int i = 0; i < 3; ++i) gpos[3 * ir + i] = acc[i];
+    }
+    free(rt); free(D); free(V); free(c); free(mu); free(t); free(X); free(Yv);
+}
