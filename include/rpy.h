@@ -69,9 +69,13 @@ typedef struct {
                           context also holds the buffers of the matrix-core
                           block product (about 100 MB at N = 4000) */
     int32_t cheb_keep; /* Chebyshev vectors V_p kept for
-                          chebyshev_sqrt_adaptive (0 disables that call;
-                          at most 512): cheb_keep x max(max_rhs, 2) x 3N
-                          doubles */
+                          chebyshev_sqrt_adaptive and rpy_u_vjp (0 disables
+                          that call; at most 512): cheb_keep x max(max_rhs, 2)
+                          x 3N doubles */
+    int32_t grad;      /* 1: also hold the buffers of rpy_u_vjp (a second
+                          stored-tile matrix and 2 cheb_keep + 4 vectors of
+                          3N); needs cheb_keep >= 2.  0: none */
+    int32_t reserved;  /* must be 0 */
     double box_l;
     double a;
     double alpha;
@@ -202,6 +206,43 @@ typedef struct {
 int bd_step(rpy_ctx *c, double *pos, const bd_params *bp, const double *dw,
             uint64_t seed, uint64_t step, double *drift, double *noise,
             double *e_f, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Differentiation.  u(R, F) = D(R) F + p(D(R)) dW, where p(D) dW is the
+ * n_cheb-term Chebyshev sum of chebyshev_sqrt_apply on the fixed interval
+ * [d_min, d_max] (eq. DF and eq. cheb1-cheb3; the interval is an input, so
+ * no derivative flows through it).  The derivatives of D's pair terms are
+ * those of eq. M1, b1/b2 and cor5 (with the readings of rpy_ewald_build) and
+ * of the cosine of eq. M2; at r = 0 between distinct beads the pair term is
+ * not differentiable and contributes nothing.
+ *
+ * rpy_u_forward: builds D at pos and writes u (device [N][3]).  vh:
+ * optional device [n_cheb][N][3] that receives V_0 .. V_{n_cheb-1} of the
+ * recurrence for a later rpy_u_vjp (NULL: not kept).
+ *
+ * rpy_u_vjp: for L = g . u (g device [N][3]) writes g_pos = dL/dR and, if
+ * g_F is not NULL, g_F = dL/dF = D g (device [N][3] each).  vh: the V_p
+ * written by rpy_u_forward for the same pos and dw, or NULL to recompute
+ * them (then n_cheb <= cheb_keep).  Rebuilds D at pos.  The context must be
+ * created with grad = 1 and n_cheb <= cheb_keep; otherwise RPY_EINVAL.
+ * Cost: one build, n_cheb - 1 products (n_cheb - 1 more with vh = NULL),
+ * one tile pass over a W matrix of the stored size, the real-space image
+ * derivatives of every pair, and the structure factors of 2 n_cheb vectors. */
+int rpy_u_forward(rpy_ctx *c, const double *pos, const double *F,
+                  const double *dw, int n_cheb, double d_min, double d_max,
+                  double *u, double *vh, void *stream);
+int rpy_u_vjp(rpy_ctx *c, const double *pos, const double *F,
+              const double *dw, const double *vh, const double *g, int n_cheb,
+              double d_min, double d_max, double *g_pos, double *g_F,
+              void *stream);
+
+/* Transpose of the force Jacobian (forces as rpy_forces): g_pos = (dF/dR)^T
+ * gF.  The spring part is the (symmetric) spring operator applied to gF; the
+ * excluded-volume part adds sum_mu J(d) (gF_nu - gF_mu) with
+ * J(d) = (zstar / dstar^5) exp(-|d|^2 / (2 dstar^2)) (I - d d^T / dstar^2),
+ * minimum image, |d| <= rcut.  pos, gF, g_pos: device [N][3]. */
+int rpy_forces_vjp(rpy_ctx *c, const double *pos, double zstar, double dstar,
+                   double rcut, const double *gF, double *g_pos, void *stream);
 
 /* Synchronise the stream and report a non-finite position seen by an
  * earlier build (RPY_ENONFINITE, flag then cleared) or RPY_OK. */

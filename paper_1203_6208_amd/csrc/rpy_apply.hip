@@ -281,6 +281,9 @@ void launch_sf_reduce(const Ctx &c, int m, hipStream_t s)
 //   EPI_APPLY      out = y
 //   EPI_CHEB_FIRST V_1 = ya y - yb V_0, acc = (c_0/2) V_0 + c_1 V_1, dv = y
 //   EPI_CHEB_NEXT  V_p = 2 (ya y - yb V_{p-1}) - V_{p-2}, acc += c_p V_p
+//   EPI_ADJ        adjoint step mu_p = c_p g + 2 (ya y - yb mu_{p+1}) - mu_{p+2}
+//                  (g = acc, read only; mu_{p+2} = 0 when vprev2 is null),
+//                  dv = xs ya mu_p
 constexpr int EPI_BEADS = 16;
 constexpr int EPI_SLICES = 64;
 template <int M>
@@ -379,10 +382,16 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
                     f.vout[o] = v1;
                     f.acc[o] = 0.5 * f.scal[8] * v0 + f.scal[9] * v1;
                     if (f.dv) f.dv[o] = yy;
-                } else {
+                } else if (f.mode == EPI_CHEB_NEXT) {
                     const double vp = 2.0 * (ya * yy - yb * f.vprev[o]) - f.vprev2[o];
                     f.vout[o] = vp;
                     f.acc[o] += f.scal[8 + f.p] * vp;
+                } else {
+                    const double mp = f.scal[8 + f.p] * f.acc[o] +
+                                      2.0 * (ya * yy - yb * f.vprev[o]) -
+                                      (f.vprev2 ? f.vprev2[o] : 0.0);
+                    f.vout[o] = mp;
+                    f.dv[o] = f.xs * ya * mp;
                 }
             }
         }

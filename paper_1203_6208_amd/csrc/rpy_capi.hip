@@ -118,6 +118,18 @@ static int validate(const rpy_params *p, int *n2max_out)
         snprintf(g_err, sizeof g_err, "max_rhs must be in 1..%d", MAX_RHS);
         return RPY_EINVAL;
     }
+    if (p->reserved != 0) {
+        snprintf(g_err, sizeof g_err, "reserved must be 0");
+        return RPY_EINVAL;
+    }
+    if (p->grad != 0 && p->grad != 1) {
+        snprintf(g_err, sizeof g_err, "grad must be 0 or 1");
+        return RPY_EINVAL;
+    }
+    if (p->grad && p->cheb_keep < 2) {
+        snprintf(g_err, sizeof g_err, "grad needs cheb_keep >= 2 (the Chebyshev terms kept)");
+        return RPY_EINVAL;
+    }
     if (p->cheb_keep < 0 || p->cheb_keep > MAX_NCHEB) {
         snprintf(g_err, sizeof g_err, "cheb_keep must be in 0..%d", MAX_NCHEB);
         return RPY_EINVAL;
@@ -182,7 +194,7 @@ extern "C" void rpy_destroy(rpy_ctx *x)
                     c.d16, c.part, c.xpk, c.ypart,
                     c.vpk, c.part32, c.tkm,
                     c.sfpart, c.tk, c.sfr, c.work, c.scal, c.red, c.flags, c.cell_start, c.lanc,
-                    c.vhist,
+                    c.vhist, c.wgrad, c.xy, c.gpart, c.gk, c.mur,
                     c.cell_beads};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -219,6 +231,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     c.lowp = p->lowp;
     c.max_rhs = p->max_rhs;
     c.cheb_keep = p->cheb_keep;
+    c.grad = p->grad != 0;
     c.rhs_cap = c.max_rhs > 2 ? c.max_rhs : 2;
     c.block = c.lowp != RPY_PREC_F64 && c.max_rhs >= BLOCK_MIN_RHS;
     if (c.block) c.rhs_cap = BLOCK_RHS;  // block kernels write all 16 columns
@@ -282,6 +295,10 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
         (rc = dalloc(&c.red, 64)) || (rc = dalloc(&c.flags, 4)) ||
         (rc = dalloc(&c.lanc, 2 * MAX_LANCZOS)) ||
         (c.cheb_keep > 0 && (rc = dalloc(&c.vhist, (size_t)c.cheb_keep * c.rhs_cap * nv))) ||
+        (c.grad && ((rc = dalloc(&c.wgrad, te)) ||
+                    (rc = dalloc(&c.xy, (size_t)c.cheb_keep * 2 * nv)) ||
+                    (rc = dalloc(&c.gpart, (size_t)c.nbt * c.n3pad)) ||
+                    (rc = dalloc(&c.gk, nv)) || (rc = dalloc(&c.mur, 3 * nv)))) ||
         (rc = dalloc(&c.cell_start, 2 * ncells_cap + 1)) || (rc = dalloc(&c.cell_beads, nv))) {
         rpy_destroy(x);
         return rc;
@@ -644,6 +661,133 @@ extern "C" int chebyshev_sqrt_adaptive(rpy_ctx *x, const double *dw, double *out
     return worst < tol ? RPY_OK : RPY_ETOL;
 }
 
+// Chebyshev recurrence on dw keeping every V_p (V_p at vh + p * ps), out =
+// the sum with the coefficients in c.scal.
+static void cheb_keep_run(rpy_ctx *x, const double *dw, double *vh, size_t ps, double *out,
+                          int n_cheb, hipStream_t s)
+{
+    const Ctx &c = x->c;
+    launch_copy(vh, dw, (size_t)c.n3, s);
+    for (int p = 1; p < n_cheb; ++p) {
+        EpiArgs f{};
+        f.m = 1;
+        f.p = p;
+        f.scal = c.scal;
+        f.acc = out;
+        f.vout = vh + p * ps;
+        f.vprev = vh + (p - 1) * ps;
+        if (p == 1) {
+            f.mode = EPI_CHEB_FIRST;
+            f.dv = x->ddw;
+        } else {
+            f.mode = EPI_CHEB_NEXT;
+            f.vprev2 = vh + (p - 2) * ps;
+        }
+        product(x, f.vprev, 1, RPY_PREC_F64, f, s);
+    }
+}
+
+static int check_u_args(const rpy_ctx *x, int n_cheb, double d_min, double d_max)
+{
+    if (n_cheb < 2 || n_cheb > MAX_NCHEB || !(d_min > 0) || !(d_max > d_min) || !isfinite(d_max))
+        return RPY_EINVAL;
+    (void)x;
+    return RPY_OK;
+}
+
+extern "C" int rpy_u_forward(rpy_ctx *x, const double *pos, const double *F, const double *dw,
+                             int n_cheb, double d_min, double d_max, double *u, double *vh,
+                             void *stream)
+{
+    if (!x || !pos || !F || !dw || !u) return RPY_EINVAL;
+    int rc = check_u_args(x, n_cheb, d_min, d_max);
+    if (rc) return rc;
+    hipStream_t s = S(stream);
+    Ctx &c = x->c;
+    const size_t nv = (size_t)c.n3;
+    launch_wrap_tables(c, pos, s);
+    ++x->wrap_gen;
+    launch_build_tiles(c, s);
+    EpiArgs f{};
+    f.mode = EPI_APPLY;
+    f.m = 1;
+    f.vout = x->Y;
+    product(x, F, 1, RPY_PREC_F64, f, s);
+    launch_cheb_coeffs(c, n_cheb, RPY_BOUNDS_EXPLICIT, 0.0, d_min, d_max, nullptr, s);
+    if (vh) cheb_keep_run(x, dw, vh, nv, x->acc, n_cheb, s);
+    else cheb_run(x, dw, x->acc, 1, n_cheb, RPY_PREC_F64, s);
+    launch_add(u, x->Y, x->acc, nv, s);
+    return check_launch("rpy_u_forward");
+}
+
+extern "C" int rpy_u_vjp(rpy_ctx *x, const double *pos, const double *F, const double *dw,
+                         const double *vh, const double *g, int n_cheb, double d_min,
+                         double d_max, double *g_pos, double *g_F, void *stream)
+{
+    if (!x || !pos || !F || !dw || !g || !g_pos) return RPY_EINVAL;
+    Ctx &c = x->c;
+    if (!c.grad) {
+        snprintf(g_err, sizeof g_err, "context was created without grad");
+        return RPY_EINVAL;
+    }
+    int rc = check_u_args(x, n_cheb, d_min, d_max);
+    if (rc) return rc;
+    if (n_cheb > c.cheb_keep) {
+        snprintf(g_err, sizeof g_err, "n_cheb exceeds cheb_keep");
+        return RPY_EINVAL;
+    }
+    hipStream_t s = S(stream);
+    const size_t nv = (size_t)c.n3;
+    launch_wrap_tables(c, pos, s);
+    ++x->wrap_gen;
+    launch_build_tiles(c, s);
+    launch_cheb_coeffs(c, n_cheb, RPY_BOUNDS_EXPLICIT, 0.0, d_min, d_max, nullptr, s);
+    size_t ps = nv;
+    if (!vh) {   // recompute V_0 .. V_{n_cheb-1}
+        ps = (size_t)c.rhs_cap * nv;
+        cheb_keep_run(x, dw, c.vhist, ps, x->acc, n_cheb, s);
+        vh = c.vhist;
+    }
+    EpiArgs f{};
+    f.mode = EPI_APPLY;
+    f.m = 1;
+    f.vout = g_F ? g_F : x->Y;
+    product(x, g, 1, RPY_PREC_F64, f, s);   // dL/dF = D g
+    // pairs: x_0 = g, y_0 = F, y_q = V_{q-1}; x_q from the adjoint recurrence
+    double *xy = c.xy;
+    const int P = n_cheb;
+    launch_copy(xy, g, nv, s);
+    launch_copy(xy + nv, F, nv, s);
+    for (int q = 1; q < P; ++q) launch_copy(xy + (2 * q + 1) * nv, vh + (q - 1) * ps, nv, s);
+    double *mu[3] = {c.mur, c.mur + nv, c.mur + 2 * nv};
+    launch_adj_init(c, P - 1, P - 1 == 1 ? 1.0 : 2.0, g, mu[(P - 1) % 3], xy + 2 * (P - 1) * nv, s);
+    for (int p = P - 2; p >= 1; --p) {
+        EpiArgs a{};
+        a.mode = EPI_ADJ;
+        a.m = 1;
+        a.p = p;
+        a.scal = c.scal;
+        a.vprev = mu[(p + 1) % 3];
+        a.vprev2 = p + 2 <= P - 1 ? mu[(p + 2) % 3] : nullptr;
+        a.vout = mu[p % 3];
+        a.acc = const_cast<double *>(g);
+        a.dv = xy + 2 * p * nv;
+        a.xs = p == 1 ? 1.0 : 2.0;
+        product(x, a.vprev, 1, RPY_PREC_F64, a, s);
+    }
+    launch_grad_wtiles(c, P, s);
+    launch_grad_real(c, s);
+    const int qg = c.rhs_cap / 2;
+    for (int q0 = 0; q0 < P; q0 += qg) {
+        const int nq = P - q0 < qg ? P - q0 : qg;
+        launch_grad_sf(c, xy + 2 * q0 * nv, 2 * nq, s);
+        launch_sf_reduce(c, 2 * nq, s);
+        launch_grad_kspace(c, xy + 2 * q0 * nv, nq, q0 > 0, s);
+    }
+    launch_grad_sum(c, g_pos, s);
+    return check_launch("rpy_u_vjp");
+}
+
 extern "C" int rpy_bounds(rpy_ctx *x, double C, double *d_min, double *d_max, void *stream)
 {
     if (!x || !d_min || !d_max || !(C > 0)) return RPY_EINVAL;
@@ -703,6 +847,25 @@ extern "C" int rpy_forces(rpy_ctx *x, const double *pos, double zstar, double ds
     if (zstar > 0) launch_wrap_positions(x->c, pos, x->c.rt_ev, s);
     forces(x, pos, x->c.rt_ev, zstar, dstar, rcut, out, s);
     return check_launch("rpy_forces");
+}
+
+extern "C" int rpy_forces_vjp(rpy_ctx *x, const double *pos, double zstar, double dstar,
+                              double rcut, const double *gF, double *g_pos, void *stream)
+{
+    if (!x || !pos || !gF || !g_pos) return RPY_EINVAL;
+    int rc = check_ev(x->c, zstar, dstar, rcut);
+    if (rc) return rc;
+    hipStream_t s = S(stream);
+    Ctx &c = x->c;
+    launch_spring_forces(c, gF, g_pos, s);   // the spring operator is linear and symmetric
+    if (zstar > 0) {
+        launch_wrap_positions(c, pos, c.rt_ev, s);
+        const int nc = (int)floor(c.L / rcut);
+        c.ncell = nc >= 3 ? (nc > 64 ? 64 : nc) : 0;
+        launch_cell_list(c, c.rt_ev, rcut, s);
+        launch_ev_vjp(c, c.rt_ev, zstar, dstar, rcut, gF, g_pos, s);
+    }
+    return check_launch("rpy_forces_vjp");
 }
 
 extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const double *dw,

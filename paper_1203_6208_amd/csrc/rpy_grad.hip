@@ -1,0 +1,330 @@
+// rpy_grad.hip -- reverse mode of u = D(R) F + p(D(R)) dW, the drift product
+// plus the Chebyshev sum of arXiv:1203.6208 (eq. DF, eq. cheb1-cheb3) on a
+// fixed interval.
+//
+// With g = dL/du the adjoint vectors of the recurrence are
+//   mu_p = c_p g + 2 Y mu_{p+1} - mu_{p+2}   (p = N_Ch - 1 .. 1, mu_{N_Ch} = mu_{N_Ch+1} = 0)
+// and dL = sum_q x_q^T dD y_q over the pairs (x_q, y_q) = (g, F),
+// (ya mu_1, V_0), (2 ya mu_p, V_{p-1}) for p >= 2, ya = 2/(d_max - d_min).
+// D's pair block depends on d = r_l - r_m only and is even in d, so
+//   dL/dr_l = sum_{m != l} grad_d [ W_lm : D(d) ],  W = sum_q x_q y_q^T + y_q x_q^T,
+// split into the real-space images (pair_grad, per stored tile of W) and the
+// reciprocal sum
+//   -sum_k k sum_q [ x_q,l . (sin T^C_k(y_q) - cos T^S_k(y_q))
+//                  + y_q,l . (sin T^C_k(x_q) - cos T^S_k(x_q)) ]
+// with T^C_k(v) = 2 m(k) (I - khat khat) sum_m cos(k.r_m) v_m (and T^S with
+// sin), i.e. the T_k of a forward product of v.  Self terms and the images of
+// a bead with itself do not move with r_l.
+#include "rpy_internal.h"
+#include "rpy_sf.h"
+
+namespace rpy {
+
+// mu_p = c_p g and x_p = xs ya mu_p (the first adjoint vector needs no product).
+__global__ void k_adj_init(int n3, int p, double xs, const double *__restrict__ scal,
+                           const double *__restrict__ g, double *__restrict__ mu,
+                           double *__restrict__ xq)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    const double m = scal[8 + p] * g[i];
+    mu[i] = m;
+    xq[i] = xs * scal[2] * m;
+}
+
+void launch_adj_init(const Ctx &c, int p, double xs, const double *g, double *mu, double *xq,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_init, dim3((c.n3 + 255) / 256), dim3(256), 0, s, c.n3, p, xs,
+                       c.scal, g, mu, xq);
+}
+
+__global__ void k_add(double *out, const double *a, const double *b, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] + b[i];
+}
+
+void launch_add(double *out, const double *a, const double *b, size_t n, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, a, b, n);
+}
+
+// ------------------------------------------------------------------ W tiles
+// W = sum_q x_q y_q^T + y_q x_q^T on the stored tiles (I <= J), same layout
+// as the stored D.  One workgroup per tile; the four vectors' tile segments
+// are staged in LDS WQC at a time; thread (tr, tc) owns rows tr + 16 i and
+// columns tc + 16 j of the tile, six rows per pass.  Rows and columns past 3N
+// are zero.
+constexpr int WQC = 8;
+__global__ __launch_bounds__(256) void k_grad_wtiles(int n3, int nq, const int2 *__restrict__ tile_ij,
+                                                     const double *__restrict__ xy,
+                                                     double *__restrict__ wt)
+{
+    __shared__ double sxi[WQC][TS], syi[WQC][TS], sxj[WQC][TS], syj[WQC][TS];
+    const int t = blockIdx.x;
+    const int2 ij = tile_ij[t];
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+    double *tile = wt + (size_t)t * TILE_ELEMS;
+    for (int pass = 0; pass < 2; ++pass) {
+        double acc[6][12];
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = 0; j < 12; ++j) acc[i][j] = 0.0;
+        for (int q0 = 0; q0 < nq; q0 += WQC) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < WQC * TS; e += blockDim.x) {
+                const int qq = e / TS, r = e % TS, q = q0 + qq;
+                const int ri = ij.x * TS + r, rj = ij.y * TS + r;
+                const bool qok = q < nq;
+                const double *X = xy + (size_t)(2 * q) * n3, *Y = X + n3;
+                sxi[qq][r] = qok && ri < n3 ? X[ri] : 0.0;
+                syi[qq][r] = qok && ri < n3 ? Y[ri] : 0.0;
+                sxj[qq][r] = qok && rj < n3 ? X[rj] : 0.0;
+                syj[qq][r] = qok && rj < n3 ? Y[rj] : 0.0;
+            }
+            __syncthreads();
+            for (int qq = 0; qq < WQC; ++qq) {
+                double xi[6], yi[6], xj[12], yj[12];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    xi[i] = sxi[qq][tr + 16 * (6 * pass + i)];
+                    yi[i] = syi[qq][tr + 16 * (6 * pass + i)];
+                }
+#pragma unroll
+                for (int j = 0; j < 12; ++j) {
+                    xj[j] = sxj[qq][tc + 16 * j];
+                    yj[j] = syj[qq][tc + 16 * j];
+                }
+#pragma unroll
+                for (int i = 0; i < 6; ++i)
+#pragma unroll
+                    for (int j = 0; j < 12; ++j) acc[i][j] += xi[i] * yj[j] + yi[i] * xj[j];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = 0; j < 12; ++j)
+                tile[(size_t)(tr + 16 * (6 * pass + i)) * TS + tc + 16 * j] = acc[i][j];
+    }
+}
+
+void launch_grad_wtiles(const Ctx &c, int nq, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grad_wtiles, dim3(c.ntiles), dim3(256), 0, s, c.n3, nq, c.tile_ij, c.xy,
+                       c.wgrad);
+}
+
+// ------------------------------------------------------- real-space gradient
+// One workgroup per stored tile (I, J): lane = bead m of J, wave w takes the
+// beads l = w, w + 4, ... of I.  Each (l, m) with l != m reads its 3 x 3
+// block of W (coalesced across the lanes), symmetrises it and sums the image
+// gradients.  Row sums (over the lanes, fixed xor tree) give the
+// contribution to bead l -> gpart[J][3 l + c]; on off-diagonal tiles the
+// negated pair terms summed over l (per lane, then the 4 waves in order) give
+// bead m's -> gpart[I][3 m + c].  Every (slot, row) is written exactly once.
+__global__ __launch_bounds__(256) void k_grad_real(int N, int n3pad, const int2 *__restrict__ tile_ij,
+                                                   const double *__restrict__ rt, PairConst p,
+                                                   const double *__restrict__ wt,
+                                                   double *__restrict__ gpart)
+{
+    __shared__ double sI[TS], sJ[TS];
+    __shared__ double scol[4][TS];
+    const int t = blockIdx.x;
+    const int2 ij = tile_ij[t];
+    const int I = ij.x, J = ij.y;
+    for (int e = threadIdx.x; e < TS; e += blockDim.x) {
+        const int bI = I * TB + e / 3, bJ = J * TB + e / 3;
+        sI[e] = bI < N ? rt[3 * (size_t)I * TB + e] : 0.0;
+        sJ[e] = bJ < N ? rt[3 * (size_t)J * TB + e] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int mu = J * TB + lane;
+    const bool muok = mu < N;
+    const double *W = wt + (size_t)t * TILE_ELEMS;
+    const bool offd = I != J;
+    double cacc[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < TB / 4; ++s) {
+        const int lp = w + 4 * s;
+        const int lam = I * TB + lp;
+        double gr[3] = {0.0, 0.0, 0.0};
+        if (lam < N && muok && (offd || lp != lane)) {
+            const double *wr = W + (size_t)(3 * lp) * TS + 3 * lane;
+            double w9[9];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) w9[3 * i + j] = wr[(size_t)i * TS + j];
+            const double Ws[6] = {w9[0], 0.5 * (w9[1] + w9[3]), 0.5 * (w9[2] + w9[6]),
+                                  w9[4], 0.5 * (w9[5] + w9[7]), w9[8]};
+            pair_grad(sI[3 * lp] - sJ[3 * lane], sI[3 * lp + 1] - sJ[3 * lane + 1],
+                      sI[3 * lp + 2] - sJ[3 * lane + 2], p, Ws, gr);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double v = gr[c];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0 && lam < N) gpart[(size_t)J * n3pad + 3 * lam + c] = v;
+            cacc[c] -= gr[c];
+        }
+    }
+    if (!offd) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) scol[w][3 * lane + c] = cacc[c];
+    __syncthreads();
+    for (int e = threadIdx.x; e < TS; e += blockDim.x)
+        gpart[(size_t)I * n3pad + (size_t)J * TS + e] =
+            ((scol[0][e] + scol[1][e]) + scol[2][e]) + scol[3][e];
+}
+
+void launch_grad_real(const Ctx &c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grad_real, dim3(c.ntiles), dim3(256), 0, s, c.N, c.n3pad, c.tile_ij,
+                       c.rt, c.pc, c.wgrad, c.gpart);
+}
+
+// ------------------------------------------------ reciprocal-space gradient
+// Structure-factor partials of nv vectors v[0 .. nv-1] (stride 3N), two at a
+// time (the phase tables stay in LDS): sfpart as in a forward product, for
+// the reduction of launch_sf_reduce.
+__global__ __launch_bounds__(256) void k_grad_sf(int N, int n3, int nk, int nmax, int rhs_cap,
+                                                 int nkb, int nv, const KVec *__restrict__ kvec,
+                                                 const double2 *__restrict__ etab,
+                                                 const double *__restrict__ v,
+                                                 double *__restrict__ sfpart)
+{
+    extern __shared__ double smem[];
+    for (int j0 = 0; j0 < nv; j0 += 2) {
+        if (j0 > 0) __syncthreads();   // the vector slots are rewritten
+        sf_partial_block<2>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v, sfpart,
+                            smem, j0 == 0);
+    }
+}
+
+void launch_grad_sf(const Ctx &c, const double *v, int nv, hipStream_t s)
+{
+    const int nkb = (c.nk + 255) / 256;
+    const size_t lds = sizeof(double) * (size_t)(2 * SF_BEADS * 3 * (c.nmax + 1) + SF_BEADS * 2 * 3);
+    hipLaunchKernelGGL(k_grad_sf, dim3(c.nsfc * nkb), dim3(256), lds, s, c.N, c.n3, c.nk, c.nmax,
+                       c.rhs_cap, nkb, nv, c.kvec, c.etab, v, c.sfpart);
+}
+
+// Per bead l: the reciprocal term above for the nq pairs whose T_k are in
+// tk[k][2 qq + (0: x, 1: y)][6].  Workgroup: 16 beads x 16 wave-vector slices
+// (phases by the n_z recursion as in the product's back-projection); slices
+// are combined in a fixed order; gk = (or +=, accumulate) the result.
+constexpr int GK_BEADS = 16;
+constexpr int GK_SLICES = 16;
+constexpr int GK_QMAX = 8;
+__global__ __launch_bounds__(256) void k_grad_kspace(int N, int n3, int nk, int rhs_cap, int nq,
+                                                      double twopi_L, int accumulate,
+                                                      const KVec *__restrict__ kvec,
+                                                      const double *__restrict__ sfr,
+                                                      const double *__restrict__ xy,
+                                                      const double *__restrict__ tk,
+                                                      double *__restrict__ gk)
+{
+    __shared__ double red[4][3][GK_BEADS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int bl = lane & 15, sub = lane >> 4;
+    const int u = 4 * w + sub;   // slice 0 .. 15
+    const int nu = blockIdx.x * GK_BEADS + bl;
+    const bool live = nu < N;
+    double xv[GK_QMAX][3], yv[GK_QMAX][3];
+#pragma unroll
+    for (int q = 0; q < GK_QMAX; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const bool ok = live && q < nq;
+            xv[q][c] = ok ? xy[(size_t)(2 * q) * n3 + 3 * nu + c] : 0.0;
+            yv[q][c] = ok ? xy[(size_t)(2 * q + 1) * n3 + 3 * nu + c] : 0.0;
+        }
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (live) {
+        const double sx = sfr[3 * nu], sy = sfr[3 * nu + 1], sz = sfr[3 * nu + 2];
+        const int klo = (int)((long)u * nk / GK_SLICES),
+                  khi = (int)((long)(u + 1) * nk / GK_SLICES);
+        double ezr, ezi;
+        sincospi(2.0 * sz, &ezi, &ezr);
+        double cs = 1.0, sn = 0.0;
+        int px = -(1 << 30), py = 0, pz = 0;
+        for (int k = klo; k < khi; ++k) {
+            const KVec kv = kvec[k];
+            if (kv.nx == px && kv.ny == py && kv.nz == pz + 1) {
+                const double c2 = cs * ezr - sn * ezi;
+                sn = cs * ezi + sn * ezr;
+                cs = c2;
+            } else {
+                sincospi(2.0 * (kv.nx * sx + kv.ny * sy + kv.nz * sz), &sn, &cs);
+            }
+            px = kv.nx;
+            py = kv.ny;
+            pz = kv.nz;
+            const double *tt = tk + (size_t)k * rhs_cap * 6;
+            double sk = 0.0;
+#pragma unroll
+            for (int q = 0; q < GK_QMAX; ++q) {
+                if (q < nq) {
+                    const double *tx = tt + 12 * q, *ty = tx + 6;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        sk += xv[q][c] * (sn * ty[c] - cs * ty[3 + c]) +
+                              yv[q][c] * (sn * tx[c] - cs * tx[3 + c]);
+                }
+            }
+            acc[0] -= sk * (twopi_L * kv.nx);
+            acc[1] -= sk * (twopi_L * kv.ny);
+            acc[2] -= sk * (twopi_L * kv.nz);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double v = acc[c];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (sub == 0) red[w][c][bl] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 * GK_BEADS) {
+        const int b = threadIdx.x / 3, c = threadIdx.x % 3;
+        const int bead = blockIdx.x * GK_BEADS + b;
+        if (bead < N) {
+            double s = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < 4; ++ww) s += red[ww][c][b];
+            const size_t o = 3 * (size_t)bead + c;
+            gk[o] = accumulate ? gk[o] + s : s;
+        }
+    }
+}
+
+void launch_grad_kspace(const Ctx &c, const double *xy, int nq, int accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grad_kspace, dim3((c.N + GK_BEADS - 1) / GK_BEADS), dim3(256), 0, s, c.N,
+                       c.n3, c.nk, c.rhs_cap, nq, 2.0 * M_PI / c.L, accumulate, c.kvec, c.sfr, xy,
+                       c.tk, c.gk);
+}
+
+// gpos[3 l + c] = sum over the tile-column slots K (ascending) + reciprocal part.
+__global__ void k_grad_sum(int n3, int n3pad, int nbt, const double *__restrict__ gpart,
+                           const double *__restrict__ gk, double *__restrict__ gpos)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    double s = 0.0;
+    for (int K = 0; K < nbt; ++K) s += gpart[(size_t)K * n3pad + i];
+    gpos[i] = s + gk[i];
+}
+
+void launch_grad_sum(const Ctx &c, double *gpos, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grad_sum, dim3((c.n3 + 255) / 256), dim3(256), 0, s, c.n3, c.n3pad, c.nbt,
+                       c.gpart, c.gk, gpos);
+}
+
+}  // namespace rpy

@@ -176,6 +176,136 @@ RPY_HD inline void pair_block(double d0x, double d0y, double d0z, bool self,
 
 PairConst make_pair_const(double L, double a, double alpha, double rc);
 
+// ------------------------------------------------------- pair derivatives
+// d/dx of the M1 coefficients (eq. M1 differentiated, x = alpha r), with the
+// values: c1 = erfc(x) A + g B, c2 = erfc(x) A2 + g B2, g = e^{-x^2}/sqrt(pi),
+// d erfc/dx = -2 g, dg/dx = -2 x g.
+RPY_HD inline void m1_dcoeffs(double x, const PairConst &p, double &c1, double &c2, double &d1,
+                              double &d2)
+{
+    const double x2 = x * x;
+    const double e = erfc(x);
+    const double g = exp(-x2) * p.inv_sqrtpi;
+    const double ix = 1.0 / x, ix2 = ix * ix, ix3 = ix2 * ix, ix4 = ix2 * ix2;
+    const double A = 0.75 * p.A1 * ix + 0.5 * p.A3 * ix3;
+    const double Ap = -0.75 * p.A1 * ix2 - 1.5 * p.A3 * ix4;
+    const double B = p.A1 * (3.0 * x2 - 4.5) + p.A3 * ((4.0 * x2 - 20.0) * x2 + 14.0 + ix2);
+    const double Bp = 6.0 * p.A1 * x + p.A3 * ((16.0 * x2 - 40.0) * x - 2.0 * ix3);
+    const double A2 = 0.75 * p.A1 * ix - 1.5 * p.A3 * ix3;
+    const double A2p = -0.75 * p.A1 * ix2 + 4.5 * p.A3 * ix4;
+    const double B2 = p.A1 * (1.5 - 3.0 * x2) + p.A3 * ((16.0 - 4.0 * x2) * x2 - 2.0 - 3.0 * ix2);
+    const double B2p = -6.0 * p.A1 * x + p.A3 * ((32.0 - 16.0 * x2) * x + 6.0 * ix3);
+    c1 = e * A + g * B;
+    c2 = e * A2 + g * B2;
+    d1 = -2.0 * g * A + e * Ap + g * (Bp - 2.0 * x * B);
+    d2 = -2.0 * g * A2 + e * A2p + g * (B2p - 2.0 * x * B2);
+}
+
+// The smooth part S = Omega_A - M1 (see smooth_part) and its x-derivative:
+// below XSER the derivative of the power series in x^2, else the closed form
+// differentiated (d erf/dx = 2 g).
+RPY_HD inline void smooth_dpart(double x, const PairConst &p, double &s1, double &s2, double &ds1,
+                                double &ds2)
+{
+    const double x2 = x * x;
+    if (x < XSER) {
+        double u = p.s1[NSER - 1], v = p.s2[NSER - 1];
+        double du = (NSER - 1) * p.s1[NSER - 1], dv = (NSER - 1) * p.s2[NSER - 1];
+        for (int n = NSER - 2; n >= 1; --n) {
+            u = u * x2 + p.s1[n];
+            v = v * x2 + p.s2[n];
+            du = du * x2 + n * p.s1[n];
+            dv = dv * x2 + n * p.s2[n];
+        }
+        s1 = u * x2 + p.s1[0];
+        s2 = v * x2 + p.s2[0];
+        ds1 = 2.0 * x * du;
+        ds2 = 2.0 * x * dv;
+    } else {
+        const double ef = erf(x);
+        const double g = exp(-x2) * p.inv_sqrtpi;
+        const double ix = 1.0 / x, ix2 = ix * ix, ix3 = ix2 * ix, ix4 = ix2 * ix2;
+        const double P1 = 3.0 * x2 - 4.5, P1p = 6.0 * x;
+        const double Q1 = (4.0 * x2 - 20.0) * x2 + 14.0 + ix2, Q1p = (16.0 * x2 - 40.0) * x - 2.0 * ix3;
+        const double P2 = 1.5 - 3.0 * x2, P2p = -6.0 * x;
+        const double Q2 = (16.0 - 4.0 * x2) * x2 - 2.0 - 3.0 * ix2,
+                     Q2p = (32.0 - 16.0 * x2) * x + 6.0 * ix3;
+        const double e1 = ef * ix, e1p = 2.0 * g * ix - ef * ix2;
+        const double e3 = ef * ix3, e3p = 2.0 * g * ix3 - 3.0 * ef * ix4;
+        s1 = p.A1 * (0.75 * e1 - P1 * g) + p.A3 * (0.5 * e3 - Q1 * g);
+        s2 = p.A1 * (0.75 * e1 - P2 * g) + p.A3 * (-1.5 * e3 - Q2 * g);
+        ds1 = p.A1 * (0.75 * e1p - (P1p - 2.0 * x * P1) * g) +
+              p.A3 * (0.5 * e3p - (Q1p - 2.0 * x * Q1) * g);
+        ds2 = p.A1 * (0.75 * e1p - (P2p - 2.0 * x * P2) * g) +
+              p.A3 * (-1.5 * e3p - (Q2p - 2.0 * x * Q2) * g);
+    }
+}
+
+// Gradient with respect to the image separation d of Ws : (c1 I + c2 dhat
+// dhat) for one image (branches as add_image), Ws symmetric
+// {xx, xy, xz, yy, yz, zz}:
+//   grad = c1' dhat tr(Ws) + c2' dhat (dhat.Ws.dhat) + (c2/r)(2 Ws dhat - 2 dhat (dhat.Ws.dhat)),
+// primes = d/dr.  The pair term is not differentiable at r = 0; nothing is
+// added there.
+RPY_HD inline void add_image_grad(double dx, double dy, double dz, const PairConst &p,
+                                  const double Ws[6], double gr[3])
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const bool in_rc = r2 <= p.rc2;
+    const bool ov = r2 < p.a2x4;
+    if ((!in_rc && !ov) || r2 == 0.0) return;
+    const double r = sqrt(r2);
+    double c2, d1, d2;
+    if (!ov) {
+        double c1, e1, e2;
+        m1_dcoeffs(p.alpha * r, p, c1, c2, e1, e2);
+        d1 = p.alpha * e1;
+        d2 = p.alpha * e2;
+    } else if (in_rc) {
+        double s1, s2, e1, e2;
+        smooth_dpart(p.alpha * r, p, s1, s2, e1, e2);
+        c2 = 0.09375 * r / p.a - s2;
+        d1 = -0.28125 / p.a - p.alpha * e1;
+        d2 = 0.09375 / p.a - p.alpha * e2;
+    } else {
+        const double ar = p.a / r, ar3 = ar * ar * ar;
+        c2 = 0.09375 * r / p.a - (0.75 * ar - 1.5 * ar3);
+        d1 = -0.28125 / p.a + (0.75 * ar + 1.5 * ar3) / r;
+        d2 = 0.09375 / p.a + (0.75 * ar - 4.5 * ar3) / r;
+    }
+    const double ir = 1.0 / r;
+    const double hx = dx * ir, hy = dy * ir, hz = dz * ir;
+    const double tr = Ws[0] + Ws[3] + Ws[5];
+    const double wx = Ws[0] * hx + Ws[1] * hy + Ws[2] * hz;
+    const double wy = Ws[1] * hx + Ws[3] * hy + Ws[4] * hz;
+    const double wz = Ws[2] * hx + Ws[4] * hy + Ws[5] * hz;
+    const double hwh = hx * wx + hy * wy + hz * wz;
+    const double a0 = d1 * tr + d2 * hwh - 2.0 * c2 * ir * hwh;
+    const double b0 = 2.0 * c2 * ir;
+    gr[0] += a0 * hx + b0 * wx;
+    gr[1] += a0 * hy + b0 * wy;
+    gr[2] += a0 * hz + b0 * wz;
+}
+
+
+
+// Sum over the periodic images of one pair of distinct beads with wrapped
+// separation d0 of the gradient of Ws : D_pair(d) (add_image_grad).
+RPY_HD inline void pair_grad(double d0x, double d0y, double d0z, const PairConst &p,
+                             const double Ws[6], double gr[3])
+{
+    const int xl = image_lo(d0x, p), xh = image_hi(d0x, p);
+    const int yl = image_lo(d0y, p), yh = image_hi(d0y, p);
+    const int zl = image_lo(d0z, p), zh = image_hi(d0z, p);
+    for (int nx = xl; nx <= xh; ++nx) {
+        const double dx = d0x + nx * p.L;
+        for (int ny = yl; ny <= yh; ++ny) {
+            const double dy = d0y + ny * p.L;
+            for (int nz = zl; nz <= zh; ++nz) add_image_grad(dx, dy, d0z + nz * p.L, p, Ws, gr);
+        }
+    }
+}
+
 // --------------------------------------------------------------- k-space
 // Half-space wave-vector set: n with |n|^2 <= n2max and n > 0 in
 // lexicographic (x, y, z) order; each carries weight 2 m(k) (the +-k pair)
@@ -251,6 +381,13 @@ struct Ctx {
     int cheb_keep = 0;           // Chebyshev vectors kept for the adaptive order
     double *vhist = nullptr;     // [cheb_keep][rhs_cap][3N]
     int *flags = nullptr;        // [0] nonfinite
+    // reverse mode (allocated when created with grad != 0)
+    bool grad = false;
+    double *wgrad = nullptr;     // [ntiles][TS*TS] W = sum_q x_q y_q^T + y_q x_q^T, stored tiles
+    double *xy = nullptr;        // [cheb_keep][2][3N] adjoint pairs (x_q, y_q)
+    double *gpart = nullptr;     // [nbt][n3pad] real-space gradient partials per tile column
+    double *gk = nullptr;        // [3N] reciprocal-space gradient
+    double *mur = nullptr;       // [3][3N] adjoint vectors mu_p (ring)
     // cell list for excluded volume
     int ncell;                   // cells per side (0: no cell list)
     int *cell_start = nullptr;   // [ncell^3 + 1]
@@ -278,7 +415,7 @@ void launch_dense_copy(const Ctx &c, double *out, hipStream_t s);
 // partials of its input; launch_sf_reduce turns them into tk; the final
 // kernel adds the reciprocal back-projection to the tile partials and applies
 // the epilogue of `mode`.
-enum EpiMode { EPI_APPLY = 0, EPI_CHEB_FIRST = 1, EPI_CHEB_NEXT = 2 };
+enum EpiMode { EPI_APPLY = 0, EPI_CHEB_FIRST = 1, EPI_CHEB_NEXT = 2, EPI_ADJ = 3 };
 struct EpiArgs {
     int mode;
     int m;
@@ -289,6 +426,7 @@ struct EpiArgs {
     double *acc;           // sum c_p V_p
     double *dv;            // optional: D.V_0 (EPI_CHEB_FIRST)
     const double *scal;    // device scalars (ya, yb, coeffs)
+    double xs;             // EPI_ADJ: dv = xs * ya * vout
 };
 void launch_symv(const Ctx &c, int prec, const double *v, int j0, int mc, hipStream_t s);
 // FP32 / BF16 tiles, up to 16 vectors at once on the matrix cores; same
@@ -317,11 +455,23 @@ void launch_lanczos_step(int n, int j, const double *q, double *w, double *qprev
 void launch_cheb_resum(int n3, int m, int n_cheb, size_t pstride, const double *scal,
                        const double *vh, double *out, hipStream_t s);
 void launch_copy(double *dst, const double *src, size_t n, hipStream_t s);
+// reverse mode of u = D F + p(D) dW (rpy_grad.hip)
+void launch_adj_init(const Ctx &c, int p, double xs, const double *g, double *mu, double *xq,
+                     hipStream_t s);
+void launch_add(double *out, const double *a, const double *b, size_t n, hipStream_t s);
+void launch_grad_wtiles(const Ctx &c, int nq, hipStream_t s);
+void launch_grad_real(const Ctx &c, hipStream_t s);
+void launch_grad_sf(const Ctx &c, const double *v, int nv, hipStream_t s);
+void launch_grad_kspace(const Ctx &c, const double *xy, int nq, int accumulate, hipStream_t s);
+void launch_grad_sum(const Ctx &c, double *gpos, hipStream_t s);
 // step
 void launch_spring_forces(const Ctx &c, const double *pos, double *F, hipStream_t s);
 void launch_cell_list(const Ctx &c, const double *rt, double rcut, hipStream_t s);
 void launch_ev_forces(const Ctx &c, const double *rt, double zstar, double dstar, double rcut,
                       double *F, hipStream_t s);
+// g_pos += sum_mu J(d)(gF_nu - gF_mu): transpose of the excluded-volume Jacobian
+void launch_ev_vjp(const Ctx &c, const double *rt, double zstar, double dstar, double rcut,
+                   const double *gF, double *gpos, hipStream_t s);
 void launch_noise(double *out, int64_t count, uint64_t seed, uint64_t step, double dt,
                   hipStream_t s);
 void launch_philox(const uint32_t *ck, uint32_t *out, int64_t n, hipStream_t s);

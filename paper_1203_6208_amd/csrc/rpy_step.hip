@@ -148,18 +148,26 @@ void launch_cell_list(const Ctx &c, const double *rt, double rcut, hipStream_t s
 // batches of EV_CAP) are staged in LDS by parallel loads; each wave then
 // takes home beads in turn and its 64 lanes split the candidates; a fixed
 // xor tree combines the lanes.
+// VJP: the transpose of the force Jacobian applied to gF instead,
+//   out_nu += sum_mu J(d) (gF_nu - gF_mu),
+//   J(d) = (z*/d*^5) exp(-|d|^2 / (2 d*^2)) (I - d d^T / d*^2)
+// (J is the d-derivative of the pair force, symmetric and even in d).
 constexpr int EV_CAP = 1024;
 constexpr int EV_HMAX = 8;   // home beads per wave per batch
+template <bool VJP>
 __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double *__restrict__ rt,
                                                   const int *__restrict__ start,
                                                   const int *__restrict__ beads, double pref,
                                                   double inv2d2, double rcut2,
+                                                  const double *__restrict__ gF,
                                                   double *__restrict__ F)
 {
     __shared__ double sx[EV_CAP], sy[EV_CAP], sz[EV_CAP];
     __shared__ int sid[EV_CAP];
     __shared__ double hx[4 * EV_HMAX], hy[4 * EV_HMAX], hz[4 * EV_HMAX];
     __shared__ int hid[4 * EV_HMAX];
+    __shared__ double sg[VJP ? 3 * EV_CAP : 1];        // gF of the staged candidates
+    __shared__ double hg[VJP ? 3 * 4 * EV_HMAX : 1];   // gF of the home beads
     __shared__ int nbr_start[27];
     __shared__ int nbr_off[28];
     const int c = blockIdx.x;
@@ -191,6 +199,8 @@ __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double
             hx[threadIdx.x] = rt[3 * nu];
             hy[threadIdx.x] = rt[3 * nu + 1];
             hz[threadIdx.x] = rt[3 * nu + 2];
+            if (VJP)
+                for (int c = 0; c < 3; ++c) hg[3 * threadIdx.x + c] = gF[3 * nu + c];
         }
         double acc[EV_HMAX][3];
 #pragma unroll
@@ -207,6 +217,8 @@ __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double
                 sx[e] = rt[3 * mu];
                 sy[e] = rt[3 * mu + 1];
                 sz[e] = rt[3 * mu + 2];
+                if (VJP)
+                    for (int c = 0; c < 3; ++c) sg[3 * e + c] = gF[3 * mu + c];
             }
             __syncthreads();
 #pragma unroll
@@ -224,9 +236,19 @@ __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double
                         const double r2 = dx * dx + dy * dy + dz * dz;
                         if (r2 > rcut2) continue;
                         const double wgt = pref * exp(-r2 * inv2d2);
-                        acc[i][0] += wgt * dx;
-                        acc[i][1] += wgt * dy;
-                        acc[i][2] += wgt * dz;
+                        if (VJP) {
+                            const double ux = hg[3 * li] - sg[3 * e];
+                            const double uy = hg[3 * li + 1] - sg[3 * e + 1];
+                            const double uz = hg[3 * li + 2] - sg[3 * e + 2];
+                            const double du = (dx * ux + dy * uy + dz * uz) * (2.0 * inv2d2);
+                            acc[i][0] += wgt * (ux - dx * du);
+                            acc[i][1] += wgt * (uy - dy * du);
+                            acc[i][2] += wgt * (uz - dz * du);
+                        } else {
+                            acc[i][0] += wgt * dx;
+                            acc[i][1] += wgt * dy;
+                            acc[i][2] += wgt * dz;
+                        }
                     }
                 }
             }
@@ -253,8 +275,10 @@ __global__ __launch_bounds__(256) void k_ev_cells(double L, int nc, const double
 }
 
 // Without a cell list (fewer than 3 cells per side): all pairs per bead.
+template <bool VJP>
 __global__ void k_ev_pairs(int N, double L, const double *__restrict__ rt, double pref,
-                           double inv2d2, double rcut2, double *__restrict__ F)
+                           double inv2d2, double rcut2, const double *__restrict__ gF,
+                           double *__restrict__ F)
 {
     const int nu = blockIdx.x * blockDim.x + threadIdx.x;
     if (nu >= N) return;
@@ -270,28 +294,51 @@ __global__ void k_ev_pairs(int N, double L, const double *__restrict__ rt, doubl
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 > rcut2) continue;
         const double w = pref * exp(-r2 * inv2d2);
-        f0 += w * dx;
-        f1 += w * dy;
-        f2 += w * dz;
+        if (VJP) {
+            const double ux = gF[3 * nu] - gF[3 * mu], uy = gF[3 * nu + 1] - gF[3 * mu + 1],
+                         uz = gF[3 * nu + 2] - gF[3 * mu + 2];
+            const double du = (dx * ux + dy * uy + dz * uz) * (2.0 * inv2d2);
+            f0 += w * (ux - dx * du);
+            f1 += w * (uy - dy * du);
+            f2 += w * (uz - dz * du);
+        } else {
+            f0 += w * dx;
+            f1 += w * dy;
+            f2 += w * dz;
+        }
     }
     F[3 * nu] += f0;
     F[3 * nu + 1] += f1;
     F[3 * nu + 2] += f2;
 }
 
-void launch_ev_forces(const Ctx &c, const double *rt, double zstar, double dstar, double rcut,
-                      double *F, hipStream_t s)
+template <bool VJP>
+static void ev_launch(const Ctx &c, const double *rt, double zstar, double dstar, double rcut,
+                      const double *gF, double *F, hipStream_t s)
 {
     const double d2 = dstar * dstar;
     const double pref = zstar / (d2 * d2 * dstar);
     if (c.ncell >= 3) {
         const int ncells = c.ncell * c.ncell * c.ncell;
-        hipLaunchKernelGGL(k_ev_cells, dim3(ncells), dim3(256), 0, s, c.L, c.ncell, rt,
-                           c.cell_start, c.cell_beads, pref, 1.0 / (2.0 * d2), rcut * rcut, F);
+        hipLaunchKernelGGL(k_ev_cells<VJP>, dim3(ncells), dim3(256), 0, s, c.L, c.ncell, rt,
+                           c.cell_start, c.cell_beads, pref, 1.0 / (2.0 * d2), rcut * rcut, gF,
+                           F);
     } else {
-        hipLaunchKernelGGL(k_ev_pairs, dim3((c.N + 127) / 128), dim3(128), 0, s, c.N, c.L, rt,
-                           pref, 1.0 / (2.0 * d2), rcut * rcut, F);
+        hipLaunchKernelGGL(k_ev_pairs<VJP>, dim3((c.N + 127) / 128), dim3(128), 0, s, c.N, c.L,
+                           rt, pref, 1.0 / (2.0 * d2), rcut * rcut, gF, F);
     }
+}
+
+void launch_ev_forces(const Ctx &c, const double *rt, double zstar, double dstar, double rcut,
+                      double *F, hipStream_t s)
+{
+    ev_launch<false>(c, rt, zstar, dstar, rcut, nullptr, F, s);
+}
+
+void launch_ev_vjp(const Ctx &c, const double *rt, double zstar, double dstar, double rcut,
+                   const double *gF, double *gpos, hipStream_t s)
+{
+    ev_launch<true>(c, rt, zstar, dstar, rcut, gF, gpos, s);
 }
 
 // ------------------------------------------------------------------ Philox

@@ -30,6 +30,7 @@ class RpyParams(ctypes.Structure):
     _fields_ = [("n_beads", ctypes.c_int32), ("n_chains", ctypes.c_int32),
                 ("beads_per_chain", ctypes.c_int32), ("lowp", ctypes.c_int32),
                 ("max_rhs", ctypes.c_int32), ("cheb_keep", ctypes.c_int32),
+                ("grad", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("box_l", ctypes.c_double), ("a", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("r_c", ctypes.c_double),
                 ("k_c", ctypes.c_double)]
@@ -73,6 +74,9 @@ _SIG = {
     "rpy_strerror": (ctypes.c_char_p, [_i]),
     "rpy_lanczos_bounds": (_i, [_v, _i, ctypes.c_uint64, _v, _d, _P(_d), _P(_d), _P(_d), _P(_d), _v]),
     "chebyshev_sqrt_adaptive": (_i, [_v, _v, _v, _i, _i, _i, _d, _d, _d, _i, _P(_i), _v, _v]),
+    "rpy_u_forward": (_i, [_v, _v, _v, _v, _i, _d, _d, _v, _v, _v]),
+    "rpy_u_vjp": (_i, [_v, _v, _v, _v, _v, _v, _i, _d, _d, _v, _v, _v]),
+    "rpy_forces_vjp": (_i, [_v, _v, _d, _d, _d, _v, _v, _v]),
     "rpy_batch_create": (_i, [_P(_v), _P(RpyParams), _i, _i, _i]),
     "rpy_batch_destroy": (None, [_v]),
     "rpy_batch_padded_beads": (ctypes.c_int64, [_v]),
@@ -116,10 +120,10 @@ def rpy_strerror(code: int) -> str:
 
 
 def make_params(*, n_beads, n_chains, beads_per_chain, box_l, a, alpha, r_c, k_c,
-                lowp="f64", max_rhs=1, cheb_keep=0) -> RpyParams:
+                lowp="f64", max_rhs=1, cheb_keep=0, grad=0) -> RpyParams:
     return RpyParams(int(n_beads), int(n_chains), int(beads_per_chain), PREC[lowp],
-                     int(max_rhs), int(cheb_keep), float(box_l), float(a), float(alpha),
-                     float(r_c), float(k_c))
+                     int(max_rhs), int(cheb_keep), int(grad), 0, float(box_l), float(a),
+                     float(alpha), float(r_c), float(k_c))
 
 
 def rpy_create(params: RpyParams) -> ctypes.c_void_p:
@@ -245,6 +249,29 @@ def rpy_host_pair_block(params: RpyParams, d, self_pair: bool):
     return [out[i] for i in range(9)]
 
 
+def rpy_u_forward(ctx, pos, F, dw, n_cheb, d_min, d_max, u, vh=None, stream=None):
+    """u = D(pos) F + p(D(pos)) dW on the fixed interval; vh [n_cheb, N, 3]
+    receives the V_p when given."""
+    _check(_lib.rpy_u_forward(ctx, _dev(pos, "pos"), _dev(F, "F"), _dev(dw, "dw"), int(n_cheb),
+                              float(d_min), float(d_max), _dev(u, "u"), _dev(vh, "vh"),
+                              _stream(stream)), "rpy_u_forward")
+    return u
+
+
+def rpy_u_vjp(ctx, pos, F, dw, g, n_cheb, d_min, d_max, g_pos, g_F=None, vh=None, stream=None):
+    _check(_lib.rpy_u_vjp(ctx, _dev(pos, "pos"), _dev(F, "F"), _dev(dw, "dw"), _dev(vh, "vh"),
+                          _dev(g, "g"), int(n_cheb), float(d_min), float(d_max),
+                          _dev(g_pos, "g_pos"), _dev(g_F, "g_F"), _stream(stream)), "rpy_u_vjp")
+    return g_pos, g_F
+
+
+def rpy_forces_vjp(ctx, pos, zstar, dstar, rcut, gF, g_pos, stream=None):
+    _check(_lib.rpy_forces_vjp(ctx, _dev(pos, "pos"), float(zstar), float(dstar), float(rcut),
+                               _dev(gF, "gF"), _dev(g_pos, "g_pos"), _stream(stream)),
+           "rpy_forces_vjp")
+    return g_pos
+
+
 PROF_SYMV, PROF_BUILD, PROF_KSPACE, PROF_EPI, PROF_OTHER = range(5)
 
 
@@ -349,12 +376,12 @@ class Context:
         return rpy_num_kvectors(self.handle)
 
 
-def context_for(workload, lowp="f64", max_rhs=1, cheb_keep=0) -> Context:
+def context_for(workload, lowp="f64", max_rhs=1, cheb_keep=0, grad=0) -> Context:
     """Context for an ``inputs.Workload``."""
     return Context(n_beads=workload.n, n_chains=workload.nchains,
                    beads_per_chain=workload.bpc, box_l=workload.L, a=workload.a,
                    alpha=workload.alpha, r_c=workload.rc, k_c=workload.kc, lowp=lowp,
-                   max_rhs=max_rhs, cheb_keep=cheb_keep)
+                   max_rhs=max_rhs, cheb_keep=cheb_keep, grad=grad)
 
 
 # ------------------------------------------------------------------ batches
