@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batching form (for profiling)")
+    ap.add_argument("--diff-only", action="store_true",
+                    help="run only the differentiation form (for profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -308,6 +310,107 @@ def batch_study(torch, rpy, inputs, steps=5, per_box=True):
     return out
 
 
+def diff_study(torch, rpy, inputs, n_steps=100, every=10):
+    """Differentiation form at N = 2000 (40 chains x 50 beads, c/c* = 1,
+    narrow-Gaussian excluded volume): the mean-square displacement after a
+    100-step trajectory and its gradient with respect to the initial
+    positions and a spring-stiffness factor, through torch.autograd with a
+    checkpoint every 10 steps.  The Chebyshev interval is fixed for the
+    trajectory (60-step Lanczos bounds at the start, 5% margin).  Reports
+    forward and backward wall times, their ratio, the plain library step
+    (bd_step, FP64) for comparison, peak device memory, and the gradient's
+    agreement with central differences of the GPU forward along 4 directions
+    that move 100 beads each."""
+    from paper_1203_6208_amd import diff
+    w = inputs.workload("n2000")
+    nch = w.nch
+    rc = rpy.context_for(w, max_rhs=16, cheb_keep=nch, grad=1)
+    pos0 = torch.from_numpy(w.positions()).cuda()
+    rc.build(pos0)
+    lo, hi, _, _ = rc.lanczos_bounds(60, seed=1, margin=0.05)
+    ev = dict(w.ev)
+    dt = w.dt
+
+    def run(p0, k, every_):
+        return diff.trajectory(p0, rc, n_steps, dt, nch, lo, hi, seed=9, ev=ev, spring=k,
+                               every=every_)
+
+    one = torch.tensor(1.0, dtype=torch.float64, device="cuda")
+    with torch.no_grad():                       # warm-up and no-grad forward
+        run(pos0, one, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(pos0, one, 0)
+        torch.cuda.synchronize()
+        t_nograd = time.perf_counter() - t0
+    def grad_pass(every_):
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        p0 = pos0.clone().requires_grad_(True)
+        k = one.clone().requires_grad_(True)
+        t0 = time.perf_counter()
+        m = diff.msd(run(p0, k, every_), p0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        m.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return (float(m.detach()), float(k.grad), p0.grad.detach(), t1 - t0, t2 - t1,
+                (torch.cuda.max_memory_allocated() - base) / 1e6)
+
+    grad_pass(every)                            # warm-up (first-use costs)
+    mval, kgrad, gp, t_fwd, t_bwd, peak = grad_pass(every)
+    _, _, gp0, t_fwd0, t_bwd0, peak0 = grad_pass(0)
+    same = bool(torch.equal(gp, gp0))
+    # plain library step for comparison
+    bp = rpy.make_bd_params(dt=dt, n_cheb=nch, bounds_rule=rpy.BOUNDS_EXPLICIT, d_min=lo,
+                            d_max=hi, ev=ev)
+    pp = pos0.clone()
+    rc.step(pp, bp, seed=1, step=0)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for i in range(n_steps):
+        rc.step(pp, bp, seed=1, step=i)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t3
+    # u-term gradient against central differences (sparse directions)
+    rng = np.random.default_rng(3)
+    pos = w.positions()
+    F = torch.from_numpy(rng.standard_normal((w.n, 3))).cuda()
+    dW = torch.from_numpy(rng.standard_normal((w.n, 3)) * math.sqrt(dt)).cuda()
+    g = torch.from_numpy(rng.standard_normal((w.n, 3))).cuda()
+    gpos = torch.empty_like(pos0)
+    rpy.rpy_u_vjp(rc.handle, pos0, F, dW, g, nch, lo, hi, gpos, None, None)
+    u = torch.empty_like(pos0)
+    errs = []
+    h = 1e-6
+    for _ in range(4):
+        moved = rng.choice(w.n, size=100, replace=False)
+        e = np.zeros(pos.shape)
+        e[moved] = rng.standard_normal((100, 3))
+        te = torch.from_numpy(e).cuda()
+        rpy.rpy_u_forward(rc.handle, pos0 + h * te, F, dW, nch, lo, hi, u)
+        lp = float(torch.sum(g * u))
+        rpy.rpy_u_forward(rc.handle, pos0 - h * te, F, dW, nch, lo, hi, u)
+        lm = float(torch.sum(g * u))
+        an = float(torch.sum(gpos * te))
+        errs.append(abs((lp - lm) / (2 * h) - an) / float(torch.sum(torch.abs(gpos * te))))
+    rc.close()
+    return {"workload": "n2000: 40 x 50 beads, c/c*=1, EV z*=1 d*=0.5, N_Ch=30, dt=1e-3",
+            "steps": n_steps, "checkpoint_every": every, "msd": mval,
+            "d_msd_d_spring": kgrad, "grad_pos_norm": float(torch.linalg.norm(gp)),
+            "forward_s": t_fwd, "backward_s": t_bwd, "backward_over_forward": t_bwd / t_fwd,
+            "peak_mem_MB": peak,
+            "no_checkpoint": {"forward_s": t_fwd0, "backward_s": t_bwd0,
+                              "backward_over_forward": t_bwd0 / t_fwd0, "peak_mem_MB": peak0,
+                              "same_gradient_bits": same},
+            "forward_nograd_s": t_nograd, "plain_bd_step_s": t_plain,
+            "fd_check_u_term": {"directions": 4, "h": h, "max_rel_err": max(errs),
+                                "note": "directions move 100 beads; see the differentiation "
+                                        "tests for the cutoff-crossing rule"}}
+
+
 def cpu_baseline(w, seconds):
     """Oracle on a bounded sample of one step: block rows of D (real space,
     self term, reciprocal sum over the full +-k set) for a subset of beads, and
@@ -369,6 +472,9 @@ def main():
         torch.cuda.synchronize()
         print(f"# calibration copy: {nb * 8} bytes read and written per launch", file=sys.stderr)
         del a, b
+    if args.diff_only:
+        print(json.dumps({"differentiation": diff_study(torch, rpy, inputs)}))
+        return
     if args.batch_only:
         print(json.dumps({"batch": batch_study(torch, rpy, inputs, steps=args.steps,
                                                per_box=False)}))
@@ -416,6 +522,9 @@ def main():
         batch = batch_study(torch, rpy, inputs)
         print(f"# batch {batch}", file=sys.stderr, flush=True)
         forms["batched_256_boxes"] = batch
+        dstudy = diff_study(torch, rpy, inputs)
+        print(f"# differentiation {dstudy}", file=sys.stderr, flush=True)
+        forms["differentiation_n2000"] = dstudy
     cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_seconds)
     line = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,

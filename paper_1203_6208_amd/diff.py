@@ -112,7 +112,10 @@ def trajectory(pos0, rc, n_steps, dt, n_cheb, d_min, d_max, seed, ev=None, sprin
         return segment(p, step0, n_steps, spring)
     for s in range(0, n_steps, every):
         k = min(every, n_steps - s)
-        p = checkpoint(segment, p, step0 + s, k, spring, use_reentrant=False)
+        # the noise comes from the library's Philox stream keyed by (seed,
+        # step), not from torch's generator: no RNG state to preserve
+        p = checkpoint(segment, p, step0 + s, k, spring, use_reentrant=False,
+                       preserve_rng_state=False)
     return p
 
 
