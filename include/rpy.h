@@ -74,8 +74,15 @@ typedef struct {
                           x 3N doubles */
     int32_t grad;      /* 1: also hold the buffers of rpy_u_vjp (a second
                           stored-tile matrix and 2 cheb_keep + 4 vectors of
-                          3N); needs cheb_keep >= 2.  0: none */
-    int32_t reserved;  /* must be 0 */
+                          3N); needs cheb_keep >= 2 and lma = 0.  0: none */
+    int32_t lma;       /* 0: high-memory form, the real-space part of D is
+                          stored (symmetric tiles, 3N(3N+1)/2 doubles).
+                          1: low-memory form (section "Low memory
+                          algorithm"): nothing of size N^2 is stored; every
+                          product recomputes the real-space sum over a cell
+                          list of side >= max(r_c, 2a), which needs
+                          max(r_c, 2a) <= L/3; FP64 only (lowp is ignored),
+                          no rpy_real_space_dense, no grad */
     double box_l;
     double a;
     double alpha;

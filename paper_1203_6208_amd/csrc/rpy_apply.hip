@@ -405,7 +405,7 @@ void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
     RPY_RHS_GROUPS(f.m, {
         const size_t lds = sizeof(double) * (size_t)c.nk * (2 + 6 * MC);
         const int staged = lds <= 48 * 1024;
-        hipLaunchKernelGGL(k_kspace_epi<MC>, g, b, staged ? lds : 0, s, c.N, c.n3, c.n3pad, c.nbt,
+        hipLaunchKernelGGL(k_kspace_epi<MC>, g, b, staged ? lds : 0, s, c.N, c.n3, c.n3pad, c.nslot,
                            c.nk, c.rhs_cap, j0, staged, c.kvec, c.sfr, c.part, c.tk, f);
     });
 }

@@ -127,6 +127,10 @@ __global__ __launch_bounds__(256) void k_build_tiles(int N, const int2 *__restri
 
 void launch_build_tiles(const Ctx &c, hipStream_t s)
 {
+    if (c.lma) {   // low-memory form: only the cell list and sorted positions
+        launch_lma_build(c, s);
+        return;
+    }
     const dim3 g(c.ntiles), b(256);
     if (c.lowp == RPY_PREC_F32)
         hipLaunchKernelGGL(k_build_tiles<1>, g, b, 0, s, c.N, c.tile_ij, c.rt, c.pc, c.d64,

@@ -118,9 +118,20 @@ static int validate(const rpy_params *p, int *n2max_out)
         snprintf(g_err, sizeof g_err, "max_rhs must be in 1..%d", MAX_RHS);
         return RPY_EINVAL;
     }
-    if (p->reserved != 0) {
-        snprintf(g_err, sizeof g_err, "reserved must be 0");
+    if (p->lma != 0 && p->lma != 1) {
+        snprintf(g_err, sizeof g_err, "lma must be 0 or 1");
         return RPY_EINVAL;
+    }
+    if (p->lma && p->grad) {
+        snprintf(g_err, sizeof g_err, "grad needs the stored form (lma = 0)");
+        return RPY_EINVAL;
+    }
+    if (p->lma) {
+        const double reach = p->r_c > 2.0 * p->a ? p->r_c : 2.0 * p->a;
+        if (!(3.0 * reach <= p->box_l)) {
+            snprintf(g_err, sizeof g_err, "lma needs max(r_c, 2a) <= L/3 (3 cells per side)");
+            return RPY_EINVAL;
+        }
     }
     if (p->grad != 0 && p->grad != 1) {
         snprintf(g_err, sizeof g_err, "grad must be 0 or 1");
@@ -195,6 +206,7 @@ extern "C" void rpy_destroy(rpy_ctx *x)
                     c.vpk, c.part32, c.tkm,
                     c.sfpart, c.tk, c.sfr, c.work, c.scal, c.red, c.flags, c.cell_start, c.lanc,
                     c.vhist, c.wgrad, c.xy, c.gpart, c.gk, c.mur,
+                    c.lma_start, c.lma_beads, c.rt_sorted, c.v_sorted,
                     c.cell_beads};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -232,14 +244,22 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     c.max_rhs = p->max_rhs;
     c.cheb_keep = p->cheb_keep;
     c.grad = p->grad != 0;
+    c.lma = p->lma != 0;
     c.rhs_cap = c.max_rhs > 2 ? c.max_rhs : 2;
-    c.block = c.lowp != RPY_PREC_F64 && c.max_rhs >= BLOCK_MIN_RHS;
+    c.block = !c.lma && c.lowp != RPY_PREC_F64 && c.max_rhs >= BLOCK_MIN_RHS;
     if (c.block) c.rhs_cap = BLOCK_RHS;  // block kernels write all 16 columns
     c.pc = make_pair_const(c.L, c.a, c.alpha, c.rc);
     c.nbt = (c.N + TB - 1) / TB;
     c.ntiles = c.nbt * (c.nbt + 1) / 2;
     c.n3pad = c.nbt * TS;
     c.nsfc = (c.N + SF_BEADS - 1) / SF_BEADS;
+    c.nslot = c.nbt;
+    if (c.lma) {   // no stored tiles: one partial slot, cells of side >= max(r_c, 2a)
+        c.nslot = 1;
+        c.lowp = RPY_PREC_F64;
+        const int nc = (int)floor(c.L / c.pc.reach);
+        c.lma_nc = nc > 128 ? 128 : nc;
+    }
 
     // half-space wave vectors, lexicographically positive
     std::vector<KVec> kv;
@@ -269,7 +289,8 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     for (int I = 0; I < c.nbt; ++I)
         for (int J = I; J < c.nbt; ++J) tij.push_back(make_int2(I, J));
 
-    const size_t te = (size_t)c.ntiles * TILE_ELEMS;
+    const size_t te = c.lma ? 0 : (size_t)c.ntiles * TILE_ELEMS;
+    const size_t lcells = c.lma ? (size_t)c.lma_nc * c.lma_nc * c.lma_nc : 0;
     const size_t nv = (size_t)c.n3;
     const size_t mv = (size_t)c.rhs_cap * nv;
     c.work_elems = 2 * nv + 2 * nv + nv + nv + 2 * mv + mv + mv;
@@ -277,10 +298,14 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     const size_t ncells_cap = (size_t)ncell_cap * ncell_cap * ncell_cap;
     if ((rc = dalloc(&c.rt, nv)) || (rc = dalloc(&c.rt_ev, nv)) || (rc = dalloc(&c.etab, nv * (c.nmax + 1))) ||
         (rc = dalloc(&c.kvec, kv.size())) || (rc = dalloc(&c.kcoef, kc.size())) ||
-        (rc = dalloc(&c.tile_ij, tij.size())) || (rc = dalloc(&c.d64, te)) ||
+        (rc = dalloc(&c.tile_ij, tij.size())) || (!c.lma && (rc = dalloc(&c.d64, te))) ||
+        (c.lma && ((rc = dalloc(&c.lma_start, 2 * lcells + 1)) ||
+                   (rc = dalloc(&c.lma_beads, (size_t)c.N)) ||
+                   (rc = dalloc(&c.rt_sorted, nv)) ||
+                   (rc = dalloc(&c.v_sorted, (size_t)c.rhs_cap * nv)))) ||
         (c.lowp == RPY_PREC_F32 && (rc = dalloc(&c.d32, te))) ||
         (c.lowp == RPY_PREC_BF16 && (rc = dalloc(&c.d16, te))) ||
-        (rc = dalloc(&c.part, (size_t)c.nbt * c.rhs_cap * c.n3pad)) ||
+        (rc = dalloc(&c.part, (size_t)c.nslot * c.rhs_cap * c.n3pad)) ||
         (c.block && ((rc = dalloc(reinterpret_cast<uint32_t **>(&c.xpk),
                                   (size_t)c.n3pad * BLOCK_RHS)) ||
                      (rc = dalloc(&c.vpk, (size_t)c.n3pad * BLOCK_RHS)) ||
@@ -317,7 +342,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
         (e = hipMemcpy(c.kcoef, kc.data(), kc.size() * sizeof(KCoef), hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(c.tile_ij, tij.data(), tij.size() * sizeof(int2), hipMemcpyHostToDevice)) ||
         (e = hipMemset(c.flags, 0, 4 * sizeof(int))) ||
-        (e = hipMemset(c.d64, 0, te * sizeof(double))) ||
+        (te && (e = hipMemset(c.d64, 0, te * sizeof(double)))) ||
         (c.block && (e = hipMemset(c.tkm, 0, (size_t)c.nk4 * 6 * BLOCK_RHS * sizeof(double))))) {
         rc = hip_fail(e, "rpy_create upload");
         rpy_destroy(x);
@@ -382,6 +407,20 @@ static void product(rpy_ctx *x, const double *v, int m, int prec, const EpiArgs 
                     hipStream_t s)
 {
     const Ctx &c = x->c;
+    if (c.lma) {   // matrix-free real space + structure factors of v
+        {
+            ProfScope ps(x, RPY_PROF_SYMV, s);
+            launch_lma_real(c, v, m, s);
+        }
+        {
+            ProfScope ps(x, RPY_PROF_KSPACE, s);
+            launch_lma_sf(c, v, m, s);
+            launch_sf_reduce(c, m, s);
+        }
+        ProfScope ps(x, RPY_PROF_EPI, s);
+        launch_kspace_epi(c, f, s);
+        return;
+    }
     if (c.block && prec != RPY_PREC_F64 && m >= BLOCK_MIN_RHS) {
         {
             ProfScope ps(x, RPY_PROF_SYMV, s);
@@ -942,6 +981,10 @@ extern "C" int rpy_status(rpy_ctx *x, void *stream)
 extern "C" int rpy_real_space_dense(rpy_ctx *x, double *out, void *stream)
 {
     if (!x || !out) return RPY_EINVAL;
+    if (x->c.lma) {
+        snprintf(g_err, sizeof g_err, "the low-memory form stores no real-space matrix");
+        return RPY_EINVAL;
+    }
     launch_dense_copy(x->c, out, S(stream));
     return check_launch("rpy_real_space_dense");
 }

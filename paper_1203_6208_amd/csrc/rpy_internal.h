@@ -381,6 +381,15 @@ struct Ctx {
     int cheb_keep = 0;           // Chebyshev vectors kept for the adaptive order
     double *vhist = nullptr;     // [cheb_keep][rhs_cap][3N]
     int *flags = nullptr;        // [0] nonfinite
+    // low-memory (matrix-free) form: no stored tiles; the real-space part is
+    // recomputed per product over a cell list of side >= max(r_c, 2a)
+    bool lma = false;
+    int nslot = 0;               // tile-column slots summed by the back-projection (1 for lma)
+    int lma_nc = 0;              // cells per side
+    int *lma_start = nullptr;    // [lma_nc^3 + 1] + cursor area [lma_nc^3]
+    int *lma_beads = nullptr;    // [N] beads sorted by cell
+    double *rt_sorted = nullptr; // [N][3] wrapped positions in cell order
+    double *v_sorted = nullptr;  // [rhs_cap][N][3] product input in cell order
     // reverse mode (allocated when created with grad != 0)
     bool grad = false;
     double *wgrad = nullptr;     // [ntiles][TS*TS] W = sum_q x_q y_q^T + y_q x_q^T, stored tiles
@@ -467,6 +476,14 @@ void launch_grad_sum(const Ctx &c, double *gpos, hipStream_t s);
 // step
 void launch_spring_forces(const Ctx &c, const double *pos, double *F, hipStream_t s);
 void launch_cell_list(const Ctx &c, const double *rt, double rcut, hipStream_t s);
+void launch_cell_list_into(int N, double L, int nc, const double *rt, int *start, int *beads,
+                           hipStream_t s);
+// low-memory form (rpy_lma.hip): cell list + positions in cell order; the
+// matrix-free real-space product into part slot 0 and the structure-factor
+// partials of the product's input
+void launch_lma_build(const Ctx &c, hipStream_t s);
+void launch_lma_real(const Ctx &c, const double *v, int m, hipStream_t s);
+void launch_lma_sf(const Ctx &c, const double *v, int m, hipStream_t s);
 void launch_ev_forces(const Ctx &c, const double *rt, double zstar, double dstar, double rcut,
                       double *F, hipStream_t s);
 // g_pos += sum_mu J(d)(gF_nu - gF_mu): transpose of the excluded-volume Jacobian

@@ -1,0 +1,145 @@
+// rpy_lma.hip -- the low-memory form of the diffusion-tensor product
+// (arXiv:1203.6208, section "Low memory algorithm"): nothing of size N x N is
+// stored; every product recomputes the real-space sum (self term, M1 over
+// the images within r_c, the overlap form below 2a) from a cell list, and
+// takes the reciprocal sum from the structure factors of its input as the
+// stored form does.  Requires max(r_c, 2a) < L/3, so that cells of that side
+// number at least 3 per axis and the 27 cells around a bead's cell hold every
+// bead any of whose images is within reach (each pair then has one such image
+// at most).
+#include "rpy_internal.h"
+#include "rpy_sf.h"
+
+namespace rpy {
+
+// out[j][k] = in[j][beads[k]] (3 components), j < m: positions or vectors in
+// cell order.
+__global__ void k_lma_gather(int N, int m, int n3, const int *__restrict__ beads,
+                             const double *__restrict__ in, double *__restrict__ out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * N) return;
+    const int j = e / N, k = e % N;
+    const int b = beads[k];
+    const double *src = in + (size_t)j * n3 + 3 * (size_t)b;
+    double *dst = out + (size_t)j * n3 + 3 * (size_t)k;
+    dst[0] = src[0];
+    dst[1] = src[1];
+    dst[2] = src[2];
+}
+
+void launch_lma_build(const Ctx &c, hipStream_t s)
+{
+    launch_cell_list_into(c.N, c.L, c.lma_nc, c.rt, c.lma_start, c.lma_beads, s);
+    hipLaunchKernelGGL(k_lma_gather, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, 1, c.n3,
+                       c.lma_beads, c.rt, c.rt_sorted);
+}
+
+// Real-space product, matrix-free.  Workgroup: 16 consecutive beads in cell
+// order, one wave per 4 of them.  For a home bead h (sorted index) the 64
+// lanes walk the 27 cells around its cell, each cell's beads in order; a
+// candidate k contributes the 3 x 3 pair block summed over its images
+// (pair_block; the self term for k = h) times v_k.  The lanes are combined by
+// a fixed xor tree; the result goes to part slot 0 at the bead's own index.
+constexpr int LMA_HOMES = 16;
+template <int M>
+__global__ __launch_bounds__(256) void k_lma_real(int N, int n3, int n3pad, int rhs_cap, int j0,
+                                                  double L, int nc, PairConst p,
+                                                  const int *__restrict__ start,
+                                                  const int *__restrict__ beads,
+                                                  const double *__restrict__ rt_s,
+                                                  const double *__restrict__ vs,
+                                                  double *__restrict__ part)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = 0; i < LMA_HOMES / 4; ++i) {
+        const int h = blockIdx.x * LMA_HOMES + 4 * w + i;   // wave-uniform
+        if (h >= N) break;
+        const double hx = rt_s[3 * (size_t)h], hy = rt_s[3 * (size_t)h + 1],
+                     hz = rt_s[3 * (size_t)h + 2];
+        int cx = (int)(hx / L * nc), cy = (int)(hy / L * nc), cz = (int)(hz / L * nc);
+        cx = min(max(cx, 0), nc - 1);
+        cy = min(max(cy, 0), nc - 1);
+        cz = min(max(cz, 0), nc - 1);
+        double acc[M][3];
+#pragma unroll
+        for (int j = 0; j < M; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+        for (int q = 0; q < 27; ++q) {
+            const int ex = (cx + q % 3 - 1 + nc) % nc, ey = (cy + (q / 3) % 3 - 1 + nc) % nc,
+                      ez = (cz + q / 9 - 1 + nc) % nc;
+            const int cc = (ez * nc + ey) * nc + ex;
+            const int k0 = start[cc], k1 = start[cc + 1];
+            for (int k = k0 + lane; k < k1; k += 64) {
+                double b[6];
+                pair_block(hx - rt_s[3 * (size_t)k], hy - rt_s[3 * (size_t)k + 1],
+                           hz - rt_s[3 * (size_t)k + 2], k == h, p, b);
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    const double *v = vs + (size_t)(j0 + j) * n3 + 3 * (size_t)k;
+                    const double v0 = v[0], v1 = v[1], v2 = v[2];
+                    acc[j][0] += b[0] * v0 + b[1] * v1 + b[2] * v2;
+                    acc[j][1] += b[1] * v0 + b[3] * v1 + b[4] * v2;
+                    acc[j][2] += b[2] * v0 + b[4] * v1 + b[5] * v2;
+                }
+            }
+        }
+        const int nu = beads[h];
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double v = acc[j][c];
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+                if (lane == 0) part[(size_t)(j0 + j) * n3pad + 3 * (size_t)nu + c] = v;
+            }
+    }
+}
+
+void launch_lma_real(const Ctx &c, const double *v, int m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lma_gather, dim3((m * c.N + 255) / 256), dim3(256), 0, s, c.N, m, c.n3,
+                       c.lma_beads, v, c.v_sorted);
+    const dim3 g((c.N + LMA_HOMES - 1) / LMA_HOMES);
+#define RPY_LMA_REAL(MC)                                                                        \
+    hipLaunchKernelGGL(k_lma_real<MC>, g, dim3(256), 0, s, c.N, c.n3, c.n3pad, c.rhs_cap, j0, \
+                       c.L, c.lma_nc, c.pc, c.lma_start, c.lma_beads, c.rt_sorted, c.v_sorted, \
+                       c.part)
+    for (int j0 = 0; j0 < m;) {   // groups of 4, 2, 1 vectors
+        const int mc = (m - j0) >= 4 ? 4 : (m - j0) >= 2 ? 2 : 1;
+        if (mc == 4) RPY_LMA_REAL(4);
+        else if (mc == 2) RPY_LMA_REAL(2);
+        else RPY_LMA_REAL(1);
+        j0 += mc;
+    }
+#undef RPY_LMA_REAL
+}
+
+// Structure-factor partials of the m input vectors (one or two at a time).
+__global__ __launch_bounds__(256) void k_lma_sf(int N, int n3, int nk, int nmax, int rhs_cap,
+                                                int nkb, int m, const KVec *__restrict__ kvec,
+                                                const double2 *__restrict__ etab,
+                                                const double *__restrict__ v,
+                                                double *__restrict__ sfpart)
+{
+    extern __shared__ double smem[];
+    for (int j0 = 0; j0 < m; j0 += 2) {
+        if (j0 > 0) __syncthreads();   // the vector slots are rewritten
+        if (m - j0 >= 2)
+            sf_partial_block<2>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
+                                sfpart, smem, j0 == 0);
+        else
+            sf_partial_block<1>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
+                                sfpart, smem, j0 == 0);
+    }
+}
+
+void launch_lma_sf(const Ctx &c, const double *v, int m, hipStream_t s)
+{
+    const int nkb = (c.nk + 255) / 256;
+    const size_t lds = sizeof(double) * (size_t)(2 * SF_BEADS * 3 * (c.nmax + 1) + SF_BEADS * 2 * 3);
+    hipLaunchKernelGGL(k_lma_sf, dim3(c.nsfc * nkb), dim3(256), lds, s, c.N, c.n3, c.nk, c.nmax,
+                       c.rhs_cap, nkb, m, c.kvec, c.etab, v, c.sfpart);
+}
+
+}  // namespace rpy

@@ -125,20 +125,27 @@ __global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start
     }
 }
 
+// Cell list of N wrapped positions rt into nc^3 cells: start [nc^3 + 1] (and a
+// cursor area of nc^3 more ints after it), beads [N] sorted by cell, by index
+// inside a cell.
+void launch_cell_list_into(int N, double L, int nc, const double *rt, int *start, int *beads,
+                           hipStream_t s)
+{
+    if (nc < 3) return;
+    const int ncells = nc * nc * nc;
+    int *count = start + ncells + 1;  // cursor area
+    hipLaunchKernelGGL(k_cell_zero, dim3((ncells + 255) / 256), dim3(256), 0, s, ncells, count);
+    hipLaunchKernelGGL(k_cell_count, dim3((N + 255) / 256), dim3(256), 0, s, N, L, nc, rt, count);
+    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, ncells, count, start);
+    hipLaunchKernelGGL(k_cell_fill, dim3((N + 255) / 256), dim3(256), 0, s, N, L, nc, rt, start,
+                       count, beads);
+    hipLaunchKernelGGL(k_cell_sort, dim3(ncells), dim3(256), 0, s, start, beads);
+}
+
 void launch_cell_list(const Ctx &c, const double *rt, double rcut, hipStream_t s)
 {
     (void)rcut;
-    const int nc = c.ncell;
-    if (nc < 3) return;
-    const int ncells = nc * nc * nc;
-    int *count = reinterpret_cast<int *>(c.cell_start) + ncells + 1;  // cursor area
-    hipLaunchKernelGGL(k_cell_zero, dim3((ncells + 255) / 256), dim3(256), 0, s, ncells, count);
-    hipLaunchKernelGGL(k_cell_count, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, c.L, nc, rt,
-                       count);
-    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, ncells, count, c.cell_start);
-    hipLaunchKernelGGL(k_cell_fill, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, c.L, nc, rt,
-                       c.cell_start, count, c.cell_beads);
-    hipLaunchKernelGGL(k_cell_sort, dim3(ncells), dim3(256), 0, s, c.cell_start, c.cell_beads);
+    launch_cell_list_into(c.N, c.L, c.ncell, rt, c.cell_start, c.cell_beads, s);
 }
 
 // Narrow-Gaussian excluded volume, minimum image (rcut < L/2):

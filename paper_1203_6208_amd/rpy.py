@@ -30,7 +30,7 @@ class RpyParams(ctypes.Structure):
     _fields_ = [("n_beads", ctypes.c_int32), ("n_chains", ctypes.c_int32),
                 ("beads_per_chain", ctypes.c_int32), ("lowp", ctypes.c_int32),
                 ("max_rhs", ctypes.c_int32), ("cheb_keep", ctypes.c_int32),
-                ("grad", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("grad", ctypes.c_int32), ("lma", ctypes.c_int32),
                 ("box_l", ctypes.c_double), ("a", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("r_c", ctypes.c_double),
                 ("k_c", ctypes.c_double)]
@@ -120,9 +120,9 @@ def rpy_strerror(code: int) -> str:
 
 
 def make_params(*, n_beads, n_chains, beads_per_chain, box_l, a, alpha, r_c, k_c,
-                lowp="f64", max_rhs=1, cheb_keep=0, grad=0) -> RpyParams:
+                lowp="f64", max_rhs=1, cheb_keep=0, grad=0, lma=0) -> RpyParams:
     return RpyParams(int(n_beads), int(n_chains), int(beads_per_chain), PREC[lowp],
-                     int(max_rhs), int(cheb_keep), int(grad), 0, float(box_l), float(a),
+                     int(max_rhs), int(cheb_keep), int(grad), int(lma), float(box_l), float(a),
                      float(alpha), float(r_c), float(k_c))
 
 
@@ -376,12 +376,12 @@ class Context:
         return rpy_num_kvectors(self.handle)
 
 
-def context_for(workload, lowp="f64", max_rhs=1, cheb_keep=0, grad=0) -> Context:
+def context_for(workload, lowp="f64", max_rhs=1, cheb_keep=0, grad=0, lma=0) -> Context:
     """Context for an ``inputs.Workload``."""
     return Context(n_beads=workload.n, n_chains=workload.nchains,
                    beads_per_chain=workload.bpc, box_l=workload.L, a=workload.a,
                    alpha=workload.alpha, r_c=workload.rc, k_c=workload.kc, lowp=lowp,
-                   max_rhs=max_rhs, cheb_keep=cheb_keep, grad=grad)
+                   max_rhs=max_rhs, cheb_keep=cheb_keep, grad=grad, lma=lma)
 
 
 # ------------------------------------------------------------------ batches

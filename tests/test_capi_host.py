@@ -138,3 +138,16 @@ def test_batch_create_rejects_invalid(rpy, case):
     assert rc == code
     assert not h.value
     assert rpy.rpy_strerror(rc)
+
+
+@pytest.mark.parametrize("over", [dict(lma=2), dict(lma=1, grad=1, cheb_keep=4),
+                                  dict(lma=1)])
+def test_create_rejects_invalid_lma(rpy, over):
+    """The low-memory form needs max(r_c, 2a) <= L/3 (the n100 workload has
+    r_c = 0.58 L) and excludes the reverse-mode buffers."""
+    p = _params(rpy, **over)
+    h = ctypes.c_void_p()
+    rc = rpy._lib.rpy_create(ctypes.byref(h), ctypes.byref(p))
+    assert rc == -1
+    assert not h.value
+    assert rpy.rpy_strerror(rc)
