@@ -56,6 +56,8 @@ def parse():
                     help="run only the batching form (for profiling)")
     ap.add_argument("--diff-only", action="store_true",
                     help="run only the differentiation form (for profiling)")
+    ap.add_argument("--lma-only", action="store_true",
+                    help="run only the high/low-memory crossover study")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -411,6 +413,64 @@ def diff_study(torch, rpy, inputs, n_steps=100, every=10):
                                         "tests for the cutoff-crossing rule"}}
 
 
+def lma_study(torch, rpy, inputs, sizes=(2000, 8000, 16000, 32000)):
+    """High-memory (stored real-space tiles, alpha L = 6) against low-memory
+    (matrix-free cell-list recomputation, alpha L = 12 and 14) forms at
+    c/c* = 1 with 50-bead chains: FP64 product (m = 1) and build times from
+    HIP events on the library's stream, a full bd_step (N_Ch = 30, paper
+    rule), the bytes the stored form keeps, and the relative difference of
+    D.v between the two forms (both truncate the same Ewald sum at
+    M = 3.5, so they agree to the truncation error, not to rounding)."""
+    out = []
+    for n in sizes:
+        row = {"N": n}
+        forms = {"hma": (6.0, 0), "lma_aL12": (12.0, 1), "lma_aL14": (14.0, 1)}
+        ref = None
+        for name, (aL, lma) in forms.items():
+            w = inputs.Workload(f"x{n}", n // 50, 50, 1.0, alphaL=aL, nch=30,
+                                seed=inputs.POSITION_SEED_BASE + 500 + n)
+            ctx = rpy.context_for(w, lma=lma)
+            pos = torch.from_numpy(w.positions()).cuda()
+            v = torch.from_numpy(np.random.default_rng(1).standard_normal((1, w.n, 3))).cuda()
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            ctx.build(pos)
+            y = ctx.apply(v)
+            torch.cuda.synchronize()
+            e0.record()
+            ctx.build(pos)
+            e1.record()
+            for _ in range(5):
+                y = ctx.apply(v)
+            e2.record()
+            torch.cuda.synchronize()
+            bp = rpy.make_bd_params(dt=1e-3, n_cheb=30, bounds_rule=rpy.BOUNDS_PAPER,
+                                    bounds_C=BOUNDS_C)
+            p2 = pos.clone()
+            ctx.step(p2, bp, seed=1, step=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(3):
+                ctx.step(p2, bp, seed=1, step=i)
+            torch.cuda.synchronize()
+            st = (time.perf_counter() - t0) / 3
+            rec = {"alphaL": aL, "n_k_half": ctx.num_kvectors(),
+                   "build_ms": e0.elapsed_time(e1), "product_ms": e1.elapsed_time(e2) / 5,
+                   "step_ms": 1e3 * st,
+                   "stored_GB": 0.0 if lma else (3 * n) * (3 * n + 1) / 2 * 8 / 1e9}
+            if ref is None:
+                ref = y
+            else:
+                rec["rel_diff_vs_hma"] = float(torch.max(torch.abs(y - ref)) /
+                                               torch.max(torch.abs(ref)))
+            row[name] = rec
+            ctx.close()
+            del ctx, y
+            torch.cuda.empty_cache()
+        out.append(row)
+        print(f"# lma {row}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(w, seconds):
     """Oracle on a bounded sample of one step: block rows of D (real space,
     self term, reciprocal sum over the full +-k set) for a subset of beads, and
@@ -472,6 +532,9 @@ def main():
         torch.cuda.synchronize()
         print(f"# calibration copy: {nb * 8} bytes read and written per launch", file=sys.stderr)
         del a, b
+    if args.lma_only:
+        print(json.dumps({"lma": lma_study(torch, rpy, inputs)}))
+        return
     if args.diff_only:
         print(json.dumps({"differentiation": diff_study(torch, rpy, inputs)}))
         return
@@ -525,6 +588,7 @@ def main():
         dstudy = diff_study(torch, rpy, inputs)
         print(f"# differentiation {dstudy}", file=sys.stderr, flush=True)
         forms["differentiation_n2000"] = dstudy
+        forms["hma_lma_crossover"] = lma_study(torch, rpy, inputs)
     cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_seconds)
     line = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,

@@ -93,8 +93,9 @@ __global__ void k_cell_fill(int N, double L, int nc, const double *__restrict__ 
 
 // One workgroup per cell: order the cell's beads by index (each entry's rank
 // among the distinct indices) so that every later sum over a cell runs in a
-// fixed order.  Cells above SORT_CAP entries fall back to a serial sort.
-constexpr int SORT_CAP = 1024;
+// fixed order.  Cells above SORT_CAP entries (more than a quarter of a
+// million beads in 27 cells) fall back to a serial sort.
+constexpr int SORT_CAP = 8192;
 __global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start, int *beads)
 {
     __shared__ int sb[SORT_CAP];
