@@ -34,12 +34,17 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on 1 GiB device copies in the same process).  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "9bd0f334b875f7a45214a4edc8282700c01cd7333a6a03db0a49431671ac41a2",
+TRAFFIC = {"src_sha256": "ef18088023681def505895a0430381ab4023caf8992d95df8f485a07019ea48e",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 607757516}
-TRAFFIC_BLOCK = {"src_sha256": "f0f3bbb8ce13c8c4b7b0d02395885f53e199e4c8260166a65893acf34eef528b",
+           "bytes_per_launch": 607770986}
+TRAFFIC_BLOCK = {"src_sha256": "1212ff32b4bee16a4494b3236ffeb093131ae7fa7fdc4c63290e99aaed0b8b0e",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f32": 312432364 + 48771072, "bf16": 159657310 + 48771072}}
+                 "bytes_per_launch": {"f32": 312236895 + 48771072, "bf16": 159636202 + 48771072}}
+# The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
+# same calibration (FETCH x 2.0, WRITE x 1.0).
+TRAFFIC_BATCH = {"src_sha256": "6772e6305d6ba6ef687cb51a4ccdcfcfa72f2eecead380924c9de7d756b2a0b1",
+                 "files": ("rpy_batch.hip", "rpy_internal.h"),
+                 "bytes_per_launch": 7152715290}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 
@@ -58,6 +63,8 @@ def parse():
                     help="run only the differentiation form (for profiling)")
     ap.add_argument("--lma-only", action="store_true",
                     help="run only the high/low-memory crossover study")
+    ap.add_argument("--no-studies", action="store_true",
+                    help="skip the eigenvalue, batching, differentiation and crossover studies")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -264,7 +271,9 @@ def batch_study(torch, rpy, inputs, steps=5, per_box=True):
     alg = sum(3 * w.n * (3 * w.n + 1) // 2 for w in ws) * 4
     out["f32_product"] = {"us": us, "algorithmic_bytes": alg,
                           "GBs": alg / (us * 1e-6) / 1e9,
-                          "hbm_frac": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+                          "hbm_frac": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                          "tile_kernel_traffic_bytes": (measured_traffic(TRAFFIC_BATCH)
+                                                        if best == 64 else None)}
     # accuracy of the FP32 form on one step against FP64 products (same state)
     B64 = rpy.Batch(ws, lowp="f64", tile_beads=best)
     p64 = B64.pack(pos_np)
@@ -575,11 +584,12 @@ def main():
         for k, v in errs.items():
             forms.setdefault(k, {}).update(v)
         forms["f64"].update({"steps_per_s": value, "ms_per_step": ms_step})
-    eigen = None if args.no_forms else eigen_study(w, torch, rpy)
+    studies = not (args.no_forms or args.no_studies)
+    eigen = eigen_study(w, torch, rpy) if studies else None
     if eigen:
         print(f"# eigen {eigen}", file=sys.stderr, flush=True)
     batch = None
-    if not args.no_forms:
+    if studies:
         del ctx, tpos
         torch.cuda.empty_cache()
         batch = batch_study(torch, rpy, inputs)

@@ -286,29 +286,40 @@ void launch_sf_reduce(const Ctx &c, int m, hipStream_t s)
 //                  dv = xs ya mu_p
 constexpr int EPI_BEADS = 16;
 constexpr int EPI_SLICES = 64;
+// When `staged` (nk <= 1024 and at most EPI_STAGE_PER x 1024 values of tk),
+// the wave vectors and this launch's 6 M values of tk per k are copied to LDS
+// once per workgroup -- [nk + 1] KVec then [nk][M][6] + 1 -- with every load
+// issued before the first LDS write (clamped indices; the copies of the
+// clamped loads land in the slack entries, so no write is conditional).
+constexpr int EPI_STAGE_PER = 6;
 template <int M>
 __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, int nbt, int nk,
                                                      int rhs_cap, int j0, int staged,
-                                                     const KVec *__restrict__ kvec,
+                                                     const KVec *kvec,
                                                      const double *__restrict__ sfr,
                                                      const double *__restrict__ part,
-                                                     const double *__restrict__ tk_g, EpiArgs f)
+                                                     const double *tk_g, EpiArgs f)
 {
     __shared__ double red[16][3][EPI_BEADS];
-    // when `staged`, the wave vectors and this launch's 6 M values of tk per
-    // k are copied to LDS once per workgroup: [nk] KVec then [nk][M][6]
     extern __shared__ double lds[];
     const KVec *kv_s = staged ? reinterpret_cast<const KVec *>(lds) : kvec;
-    const double *tk_s = staged ? lds + 2 * nk : tk_g + (size_t)j0 * 6;
+    const double *tk_s = staged ? lds + 2 * (nk + 1) : tk_g + (size_t)j0 * 6;
     const int tk_ld = staged ? 6 * M : 6 * rhs_cap;
     if (staged) {
         KVec *kd = reinterpret_cast<KVec *>(lds);
-        for (int e = threadIdx.x; e < nk; e += blockDim.x) kd[e] = kvec[e];
-        double *td = lds + 2 * nk;
-        for (int e = threadIdx.x; e < nk * 6 * M; e += blockDim.x) {
+        double *td = lds + 2 * (nk + 1);
+        const int ntk = nk * 6 * M;
+        const KVec kv0 = kvec[min((int)threadIdx.x, nk - 1)];
+        double tv[EPI_STAGE_PER];
+#pragma unroll
+        for (int i = 0; i < EPI_STAGE_PER; ++i) {
+            const int e = min((int)threadIdx.x + 1024 * i, ntk - 1);
             const int k = e / (6 * M), r = e % (6 * M);
-            td[e] = tk_g[((size_t)k * rhs_cap + j0) * 6 + r];
+            tv[i] = tk_g[((size_t)k * rhs_cap + j0) * 6 + r];
         }
+        kd[min((int)threadIdx.x, nk)] = kv0;
+#pragma unroll
+        for (int i = 0; i < EPI_STAGE_PER; ++i) td[min((int)threadIdx.x + 1024 * i, ntk)] = tv[i];
         __syncthreads();
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -403,8 +414,9 @@ void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
 {
     const dim3 g((c.N + EPI_BEADS - 1) / EPI_BEADS), b(1024);
     RPY_RHS_GROUPS(f.m, {
-        const size_t lds = sizeof(double) * (size_t)c.nk * (2 + 6 * MC);
-        const int staged = lds <= 48 * 1024;
+        const size_t lds = sizeof(double) * ((size_t)c.nk * (2 + 6 * MC) + 3);
+        const int staged = c.nk <= 1024 && (size_t)c.nk * 6 * MC <= 1024 * EPI_STAGE_PER &&
+                           lds <= 48 * 1024;
         hipLaunchKernelGGL(k_kspace_epi<MC>, g, b, staged ? lds : 0, s, c.N, c.n3, c.n3pad, c.nslot,
                            c.nk, c.rhs_cap, j0, staged, c.kvec, c.sfr, c.part, c.tk, f);
     });
