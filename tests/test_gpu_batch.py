@@ -264,3 +264,34 @@ def test_autotuner_picks_a_measured_candidate(ref):
     assert set(times) == {32, 64}
     assert best in times and times[best] == min(times.values())
     assert all(t > 0 for t in times.values())
+
+
+@pytest.mark.parametrize("tb", [32, 64])
+def test_batch_tiny_and_single_boxes(orc, tb):
+    """Edge sizes: a single box; boxes smaller than one tile (20 beads) next
+    to a box of exactly one tile (32 or 64 beads) and a ragged one; D.v per box
+    against the oracle to 1e-12 and a graph step equal to the eager step."""
+    _say(f"batch edge sizes tb={tb}")
+    base = inputs.POSITION_SEED_BASE + 900
+    ws = [inputs.Workload("t20", 2, 10, 1.0, nch=10, seed=base),
+          inputs.Workload("tfull", tb // 16, 16, 1.5, nch=10, seed=base + 1),
+          inputs.Workload("t150", 5, 30, 0.8, nch=10, seed=base + 2)]
+    for group in (ws[:1], ws):
+        B = rpy.Batch(group, lowp="f64", tile_beads=tb)
+        pos_np = [w.positions() for w in group]
+        pos = B.pack(pos_np)
+        B.build(pos)
+        vs = [np.random.default_rng(i).standard_normal((w.n, 3)) for i, w in enumerate(group)]
+        out = B.unpack(B.apply(B.pack(vs, m=1))[0].cpu())
+        for w, p, v, g in zip(group, pos_np, vs, out):
+            D = orc.diffusion_matrix(p, w.L, w.a, w.alpha, w.rc, w.n2max)
+            assert _rel(g.numpy().reshape(-1), D @ v.reshape(-1)) < TOL, w.name
+        bp = rpy.make_bd_params(dt=1e-3, n_cheb=10, bounds_rule=rpy.BOUNDS_PAPER,
+                                bounds_C=C_RULE)
+        pe, pg = pos.clone(), pos.clone()
+        B.step(pe, bp, seed=4, step=1)
+        B.run(pg, bp, seed=4, step0=1, n_steps=1)
+        torch.cuda.synchronize()
+        assert torch.equal(pe, pg)
+        assert B.status() == 0
+        B.close()
