@@ -37,11 +37,45 @@ void launch_lma_build(const Ctx &c, hipStream_t s)
 
 // Real-space product, matrix-free.  Workgroup: 16 consecutive beads in cell
 // order, one wave per 4 of them.  For a home bead h (sorted index) the 64
-// lanes walk the 27 cells around its cell, each cell's beads in order; a
-// candidate k contributes the 3 x 3 pair block summed over its images
-// (pair_block; the self term for k = h) times v_k.  The lanes are combined by
-// a fixed xor tree; the result goes to part slot 0 at the bead's own index.
+// lanes walk the 27 cells around its cell, each cell's beads in order, and
+// test each candidate k cheaply (minimum-image |d|^2 against r_c^2 and
+// (2a)^2, the test add_image applies to that image, or k = h); the
+// candidates that pass are appended to a per-wave LDS queue (ballot +
+// prefix count), and whenever 64 are queued every lane evaluates one of
+// them: the 3 x 3 pair block summed over its images (pair_block; the self
+// term for k = h) times v_k.  Only about a sixth of the stencil is within
+// reach, so the expensive pair terms run on full waves.  The lanes are
+// combined by a fixed xor tree; the result goes to part slot 0 at the bead's
+// own index.  Every step of the walk is deterministic.
 constexpr int LMA_HOMES = 16;
+constexpr int LMA_QCAP = 128;
+
+__device__ inline void lma_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int M>
+__device__ inline void lma_pair(double hx, double hy, double hz, int k, int h,
+                                const PairConst &p, const double *__restrict__ rt_s,
+                                const double *__restrict__ vs, int n3, int j0,
+                                double acc[M][3])
+{
+    double b[6];
+    pair_block(hx - rt_s[3 * (size_t)k], hy - rt_s[3 * (size_t)k + 1],
+               hz - rt_s[3 * (size_t)k + 2], k == h, p, b);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const double *v = vs + (size_t)(j0 + j) * n3 + 3 * (size_t)k;
+        const double v0 = v[0], v1 = v[1], v2 = v[2];
+        acc[j][0] += b[0] * v0 + b[1] * v1 + b[2] * v2;
+        acc[j][1] += b[1] * v0 + b[3] * v1 + b[4] * v2;
+        acc[j][2] += b[2] * v0 + b[4] * v1 + b[5] * v2;
+    }
+}
+
 template <int M>
 __global__ __launch_bounds__(256) void k_lma_real(int N, int n3, int n3pad, int rhs_cap, int j0,
                                                   double L, int nc, PairConst p,
@@ -51,7 +85,10 @@ __global__ __launch_bounds__(256) void k_lma_real(int N, int n3, int n3pad, int 
                                                   const double *__restrict__ vs,
                                                   double *__restrict__ part)
 {
+    __shared__ int queue[4][LMA_QCAP];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int *q = queue[w];
+    const double invL = 1.0 / L;
     for (int i = 0; i < LMA_HOMES / 4; ++i) {
         const int h = blockIdx.x * LMA_HOMES + 4 * w + i;   // wave-uniform
         if (h >= N) break;
@@ -64,25 +101,43 @@ __global__ __launch_bounds__(256) void k_lma_real(int N, int n3, int n3pad, int 
         double acc[M][3];
 #pragma unroll
         for (int j = 0; j < M; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
-        for (int q = 0; q < 27; ++q) {
-            const int ex = (cx + q % 3 - 1 + nc) % nc, ey = (cy + (q / 3) % 3 - 1 + nc) % nc,
-                      ez = (cz + q / 9 - 1 + nc) % nc;
+        int qn = 0;   // queued candidates (wave-uniform)
+        for (int cq = 0; cq < 27; ++cq) {
+            const int ex = (cx + cq % 3 - 1 + nc) % nc, ey = (cy + (cq / 3) % 3 - 1 + nc) % nc,
+                      ez = (cz + cq / 9 - 1 + nc) % nc;
             const int cc = (ez * nc + ey) * nc + ex;
             const int k0 = start[cc], k1 = start[cc + 1];
-            for (int k = k0 + lane; k < k1; k += 64) {
-                double b[6];
-                pair_block(hx - rt_s[3 * (size_t)k], hy - rt_s[3 * (size_t)k + 1],
-                           hz - rt_s[3 * (size_t)k + 2], k == h, p, b);
-#pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    const double *v = vs + (size_t)(j0 + j) * n3 + 3 * (size_t)k;
-                    const double v0 = v[0], v1 = v[1], v2 = v[2];
-                    acc[j][0] += b[0] * v0 + b[1] * v1 + b[2] * v2;
-                    acc[j][1] += b[1] * v0 + b[3] * v1 + b[4] * v2;
-                    acc[j][2] += b[2] * v0 + b[4] * v1 + b[5] * v2;
+            for (int base = k0; base < k1; base += 64) {
+                const int k = base + lane;
+                bool in = false;
+                if (k < k1) {
+                    double dx = hx - rt_s[3 * (size_t)k], dy = hy - rt_s[3 * (size_t)k + 1],
+                           dz = hz - rt_s[3 * (size_t)k + 2];
+                    dx -= L * rint(dx * invL);
+                    dy -= L * rint(dy * invL);
+                    dz -= L * rint(dz * invL);
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    in = k == h || r2 <= p.rc2 || r2 < p.a2x4;
+                }
+                const unsigned long long mask = __ballot(in);
+                const int before = __popcll(mask & ((1ull << lane) - 1ull));
+                if (in) q[qn + before] = k;
+                qn += __popcll(mask);
+                if (qn >= 64) {   // a full wave of pair terms
+                    lma_wave_sync();
+                    const int kk = q[lane];
+                    const int rest = qn - 64;
+                    const int moved = lane < rest ? q[64 + lane] : 0;
+                    lma_wave_sync();
+                    if (lane < rest) q[lane] = moved;
+                    qn = rest;
+                    lma_pair<M>(hx, hy, hz, kk, h, p, rt_s, vs, n3, j0, acc);
                 }
             }
         }
+        lma_wave_sync();
+        if (lane < qn) lma_pair<M>(hx, hy, hz, q[lane], h, p, rt_s, vs, n3, j0, acc);
+        lma_wave_sync();   // the queue is reused by the next home bead
         const int nu = beads[h];
 #pragma unroll
         for (int j = 0; j < M; ++j)
