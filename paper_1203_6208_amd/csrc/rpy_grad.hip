@@ -189,9 +189,9 @@ void launch_grad_real(const Ctx &c, hipStream_t s)
 }
 
 // ------------------------------------------------ reciprocal-space gradient
-// Structure-factor partials of nv vectors v[0 .. nv-1] (stride 3N), two at a
-// time (the phase tables stay in LDS): sfpart as in a forward product, for
-// the reduction of launch_sf_reduce.
+// Structure-factor partials of nv (even) vectors v[0 .. nv-1] (stride 3N),
+// four at a time and a last pair (the phase tables stay in LDS): sfpart as in
+// a forward product, for the reduction of launch_sf_reduce.
 __global__ __launch_bounds__(256) void k_grad_sf(int N, int n3, int nk, int nmax, int rhs_cap,
                                                  int nkb, int nv, const KVec *__restrict__ kvec,
                                                  const double2 *__restrict__ etab,
@@ -199,27 +199,36 @@ __global__ __launch_bounds__(256) void k_grad_sf(int N, int n3, int nk, int nmax
                                                  double *__restrict__ sfpart)
 {
     extern __shared__ double smem[];
-    for (int j0 = 0; j0 < nv; j0 += 2) {
+    for (int j0 = 0; j0 < nv;) {
         if (j0 > 0) __syncthreads();   // the vector slots are rewritten
-        sf_partial_block<2>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v, sfpart,
-                            smem, j0 == 0);
+        if (nv - j0 >= 4) {
+            sf_partial_block<4>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
+                                sfpart, smem, j0 == 0);
+            j0 += 4;
+        } else {
+            sf_partial_block<2>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
+                                sfpart, smem, j0 == 0);
+            j0 += 2;
+        }
     }
 }
 
 void launch_grad_sf(const Ctx &c, const double *v, int nv, hipStream_t s)
 {
     const int nkb = (c.nk + 255) / 256;
-    const size_t lds = sizeof(double) * (size_t)(2 * SF_BEADS * 3 * (c.nmax + 1) + SF_BEADS * 2 * 3);
+    const size_t lds = sizeof(double) * (size_t)(2 * SF_BEADS * 3 * (c.nmax + 1) + SF_BEADS * 4 * 3);
     hipLaunchKernelGGL(k_grad_sf, dim3(c.nsfc * nkb), dim3(256), lds, s, c.N, c.n3, c.nk, c.nmax,
                        c.rhs_cap, nkb, nv, c.kvec, c.etab, v, c.sfpart);
 }
 
 // Per bead l: the reciprocal term above for the nq pairs whose T_k are in
-// tk[k][2 qq + (0: x, 1: y)][6].  Workgroup: 16 beads x 16 wave-vector slices
-// (phases by the n_z recursion as in the product's back-projection); slices
-// are combined in a fixed order; gk = (or +=, accumulate) the result.
-constexpr int GK_BEADS = 16;
-constexpr int GK_SLICES = 16;
+// tk[k][2 qq + (0: x, 1: y)][6].  Workgroup: 4 beads x 64 wave-vector slices
+// (lane = bead (low 2 bits) and 16 slices, 4 waves; phases by the n_z
+// recursion as in the product's back-projection); slices are combined in a
+// fixed order (xor tree over the lanes of a bead, then the 4 waves); gk =
+// (or +=, accumulate) the result.
+constexpr int GK_BEADS = 4;
+constexpr int GK_SLICES = 64;
 constexpr int GK_QMAX = 8;
 __global__ __launch_bounds__(256) void k_grad_kspace(int N, int n3, int nk, int rhs_cap, int nq,
                                                       double twopi_L, int accumulate,
@@ -231,8 +240,8 @@ __global__ __launch_bounds__(256) void k_grad_kspace(int N, int n3, int nk, int 
 {
     __shared__ double red[4][3][GK_BEADS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int bl = lane & 15, sub = lane >> 4;
-    const int u = 4 * w + sub;   // slice 0 .. 15
+    const int bl = lane & 3, sub = lane >> 2;
+    const int u = 16 * w + sub;   // slice 0 .. 63
     const int nu = blockIdx.x * GK_BEADS + bl;
     const bool live = nu < N;
     double xv[GK_QMAX][3], yv[GK_QMAX][3];
@@ -285,8 +294,8 @@ __global__ __launch_bounds__(256) void k_grad_kspace(int N, int n3, int nk, int 
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         double v = acc[c];
-        v += __shfl_xor(v, 16);
-        v += __shfl_xor(v, 32);
+#pragma unroll
+        for (int o = 4; o <= 32; o <<= 1) v += __shfl_xor(v, o);
         if (sub == 0) red[w][c][bl] = v;
     }
     __syncthreads();
