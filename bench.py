@@ -215,6 +215,23 @@ def eigen_study(w, torch, rpy):
     _, ef, n = ctx.sqrt_adaptive(dw, lo, hi, 1e-3, 256, allow_etol=True)
     t_ad = time.perf_counter() - t0
     out["adaptive_tol_1e-3"] = {"n_cheb": n, "E_f": float(ef[0]), "seconds": t_ad}
+    # the FP64 step at stated accuracy: the Lanczos interval (computed once,
+    # held for the timed steps) with the order of eq. nint and with the
+    # adaptive order above
+    for tag, nch in (("step_lanczos_nint", out["lanczos_60"]["n_cheb_rule"]),
+                     ("step_lanczos_adaptive", n)):
+        bp = rpy.make_bd_params(dt=w.dt, n_cheb=nch, bounds_rule=rpy.BOUNDS_EXPLICIT,
+                                d_min=lo, d_max=hi, ev=w.ev)
+        p = pos.clone()
+        _, _, e_f = ctx.step(p, bp, seed=7, step=0, want=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(10):
+            ctx.step(p, bp, seed=7, step=1 + i)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / 10
+        out[tag] = {"n_cheb": nch, "E_f": float(e_f[0]), "steps_per_s": 1.0 / dt_s,
+                    "ms_per_step": 1e3 * dt_s}
     del ctx
     return out
 

@@ -295,3 +295,23 @@ def test_batch_tiny_and_single_boxes(orc, tb):
         assert torch.equal(pe, pg)
         assert B.status() == 0
         B.close()
+
+
+def test_batch_entry_points_reject_invalid(ref):
+    """m outside 1..2, an unknown precision, a bad interval or order."""
+    ws = [r[0] for r in ref][:2]
+    B = rpy.Batch(ws, lowp="f32", tile_beads=32)
+    v = B.pack([r[1] for r in ref][:2])
+    for m in (0, 3):
+        out = torch.empty((max(m, 1), B.G, 3), dtype=torch.float64, device="cuda")
+        with pytest.raises(rpy.RpyError):
+            rpy.rpy_batch_apply(B.handle, v, out, m)
+    with pytest.raises(rpy.RpyError):
+        rpy.rpy_batch_apply(B.handle, v, torch.empty_like(v), 1, prec="bf16")
+    for kw in (dict(n_cheb=1), dict(bounds_rule=rpy.BOUNDS_EXPLICIT, d_min=2.0, d_max=1.0),
+               dict(bounds_rule=rpy.BOUNDS_PAPER, C=0.0)):
+        args = dict(n_cheb=10, bounds_rule=rpy.BOUNDS_PAPER, C=8.0, d_min=0.0, d_max=0.0)
+        args.update(kw)
+        with pytest.raises(rpy.RpyError):
+            rpy.rpy_batch_chebyshev(B.handle, v, torch.empty_like(v), **args)
+    B.close()

@@ -246,3 +246,19 @@ def test_vjp_needs_grad_context():
     with pytest.raises(rpy.RpyError):
         rpy.rpy_u_vjp(rc.handle, t, t, t, t, 20, 0.1, 2.0, torch.empty_like(t))
     rc.close()
+
+
+def test_u_entry_points_reject_invalid():
+    """Interval, order and n_cheb > cheb_keep are refused before any launch."""
+    w = inputs.workload("n100")
+    rc = rpy.context_for(w, max_rhs=16, cheb_keep=10, grad=1)
+    t = _cuda(w.positions())
+    u = torch.empty_like(t)
+    for nch, lo, hi in ((1, 0.1, 2.0), (10, 0.0, 2.0), (10, 2.0, 1.0), (10, 0.1, float("inf"))):
+        with pytest.raises(rpy.RpyError):
+            rpy.rpy_u_forward(rc.handle, t, t, t, nch, lo, hi, u)
+    with pytest.raises(rpy.RpyError):   # more terms than kept vectors
+        rpy.rpy_u_vjp(rc.handle, t, t, t, t, 11, 0.1, 2.0, torch.empty_like(t))
+    with pytest.raises(rpy.RpyError):   # excluded volume with rcut >= L/2
+        rpy.rpy_forces_vjp(rc.handle, t, 1.0, 0.5, 0.6 * w.L, t, torch.empty_like(t))
+    rc.close()
