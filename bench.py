@@ -179,9 +179,7 @@ def time_block(w, prec, reps, torch, rpy):
         n, ms = rpy.rpy_profile_read(ctx.handle, kind)
         stage[nm + "_us"] = 1e3 * ms / nprod
     rpy.rpy_profile_enable(ctx.handle, 0)
-    n3 = 3 * w.n
-    esize = {"f64": 8, "f32": 4, "bf16": 2}[prec]
-    gbs = n3 * (n3 + 1) // 2 * esize / (stage["tile_product_us"] * 1e-6) / 1e9
+    gbs = tile_bytes(w.n, prec) / (stage["tile_product_us"] * 1e-6) / 1e9
     del ctx
     return {"ms_per_block": 1e3 * wall, "us_per_product": 1e6 * wall / nprod,
             **stage, "tile_product_GBs": gbs, "tile_product_hbm_frac": gbs / HBM_PEAK_GBS,
@@ -482,7 +480,7 @@ def lma_study(torch, rpy, inputs, sizes=(2000, 8000, 16000, 32000)):
             rec = {"alphaL": aL, "n_k_half": ctx.num_kvectors(),
                    "build_ms": e0.elapsed_time(e1), "product_ms": e1.elapsed_time(e2) / 5,
                    "step_ms": 1e3 * st,
-                   "stored_GB": 0.0 if lma else (3 * n) * (3 * n + 1) / 2 * 8 / 1e9}
+                   "stored_GB": 0.0 if lma else tile_bytes(n, "f64") / 1e9}
             if ref is None:
                 ref = y
             else:
@@ -528,6 +526,17 @@ def cpu_baseline(w, seconds):
                        f"over 1236 k, brute force) plus {2 + w.nch - 1} row-block products; "
                        f"{tb + tm:.1f} s measured, scaled by N/{nb}; forces and update omitted "
                        f"(O(N))")}
+
+
+def tile_bytes(n, prec):
+    """Algorithmic bytes one product streams: the unique entries of the
+    real-space matrix.  FP64 tiles keep the 6 distinct entries of each
+    symmetric 3 x 3 bead-pair block for the N(N+1)/2 pairs i <= j; FP32 and
+    BF16 tiles keep the symmetric half of the 3N x 3N matrix."""
+    if prec == "f64":
+        return 3 * n * (n + 1) * 8
+    n3 = 3 * n
+    return n3 * (n3 + 1) // 2 * (4 if prec == "f32" else 2)
 
 
 def measured_traffic(t=TRAFFIC, key=None):
@@ -577,8 +586,7 @@ def main():
     print(f"# f64: {ms_step:.3f} ms/step (events {gpu_ms / args.steps:.3f}) status={st}",
           file=sys.stderr, flush=True)
     prof = profile_pass(ctx, rpy, tpos, bp, args.steps, torch)
-    n3 = 3 * w.n
-    alg_bytes = n3 * (n3 + 1) // 2 * 8
+    alg_bytes = tile_bytes(w.n, "f64")
     sym = prof["tile_product"]
     achieved = alg_bytes / (sym["avg_us"] * 1e-6) / 1e9
     print(f"# profile {json.dumps(prof)}", file=sys.stderr, flush=True)
@@ -590,7 +598,7 @@ def main():
             forms[prec] = {"steps_per_s": args.steps / wl2, "ms_per_step": 1e3 * wl2 / args.steps,
                            "speedup_vs_f64": (args.steps / wl2) / value,
                            "tile_product_avg_us": pr2["tile_product"]["avg_us"],
-                           "tile_product_GBs": n3 * (n3 + 1) // 2 * (4 if prec == "f32" else 2)
+                           "tile_product_GBs": tile_bytes(w.n, prec)
                            / (pr2["tile_product"]["avg_us"] * 1e-6) / 1e9}
             del c2
             print(f"# {prec}: {forms[prec]}", file=sys.stderr, flush=True)
@@ -629,7 +637,7 @@ def main():
                    "n_beads": w.n, "n_cheb": w.nch, "box_l": w.L, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_symv<double,1> (symmetric tile product, FP64, m=1)",
+                     "kernel": "k_symv6<1> (packed symmetric tile product, FP64, m=1)",
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_us": sym["avg_us"], "launches": sym["launches"]},
         "kernels": prof,

@@ -16,23 +16,11 @@ namespace rpy {
     }
 
 // ------------------------------------------------------------------ SYMV
-// Element types of the stored tiles.  Each lane of a 16-lane row group owns
-// 12 fixed columns of the 192-column tile row and loads them with 16-byte
-// (or 8-byte) vector loads that are contiguous across the row group.
+// Element types of the FP32 / BF16 tiles (TS x TS row-major).  Each lane of a
+// 16-lane row group owns 12 fixed columns of the 192-column tile row and
+// loads them with 16-byte (or 8-byte) vector loads that are contiguous across
+// the row group.
 template <typename T> struct TileT;
-template <> struct TileT<double> {
-    using acc_t = double;
-    __device__ static int col(int q, int e) { return 32 * (e >> 1) + 2 * q + (e & 1); }
-    __device__ static void load(const double *row, int q, acc_t a[12])
-    {
-#pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            const double *p = row + 32 * s + 2 * q;
-            a[2 * s] = __builtin_nontemporal_load(p);
-            a[2 * s + 1] = __builtin_nontemporal_load(p + 1);
-        }
-    }
-};
 template <> struct TileT<float> {
     using acc_t = float;
     __device__ static int col(int q, int e) { return 64 * (e >> 2) + 4 * q + (e & 3); }
@@ -168,6 +156,128 @@ __global__ __launch_bounds__(256) void k_symv(int N, int n3, int n3pad, int rhs_
     }
 }
 
+// FP64 product on the packed tiles (6 planes per bead row, d64[t][i][c][j]).
+// Workgroups [0, nsf) compute structure-factor partials of v; each further
+// workgroup (4 waves) takes one stored tile (I, J).  Wave w, row group g (16
+// lanes), lane q: bead rows i = 16 it + 4 w + g (it = 0..3); lane q owns the
+// bead columns jb(e) = 32 (e >> 1) + 2 q + (e & 1), e = 0..3, and reads each
+// plane with two 16-byte non-temporal loads (256 contiguous bytes per row
+// group and load).  With B the symmetric 3 x 3 block of (i, j), the row sums
+// of B x_j over the 16 lanes give A_IJ x_J -> part[J][j][rows of I]; for
+// off-diagonal tiles each lane also accumulates B x_i for its columns, and the
+// 4 row groups and 4 waves are combined in a fixed order -> part[I][j][rows
+// of J].  Diagonal tiles hold both (i, j) and (j, i) and take row sums only.
+__device__ inline int p6col(int q, int e) { return 32 * (e >> 1) + 2 * q + (e & 1); }
+
+template <int M>
+__global__ __launch_bounds__(256) void k_symv6(int N, int n3, int n3pad, int rhs_cap, int j0,
+                                               int nsf, int nkb, int nk, int nmax,
+                                               const KVec *__restrict__ kvec,
+                                               const double2 *__restrict__ etab,
+                                               double *__restrict__ sfpart,
+                                               const int2 *__restrict__ tile_ij,
+                                               const double *__restrict__ tiles,
+                                               const double *__restrict__ v,
+                                               double *__restrict__ part)
+{
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    extern __shared__ double smem[];
+    if ((int)blockIdx.x < nsf) {
+        sf_partial_block<M>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
+                            sfpart, smem);
+        return;
+    }
+    double(*sx)[TS] = reinterpret_cast<double(*)[TS]>(smem);                    // [M][TS]
+    double(*scol)[M][TS] = reinterpret_cast<double(*)[M][TS]>(smem + M * TS);  // [4][M][TS]
+    const int t = blockIdx.x - nsf;
+    const int2 ij = tile_ij[t];
+    const int I = ij.x, J = ij.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, q = lane & 15;
+    for (int e = threadIdx.x; e < M * TS; e += blockDim.x) {
+        const int j = e / TS, r = e % TS, row = I * TS + r;
+        sx[j][r] = row < n3 ? v[(size_t)(j0 + j) * n3 + row] : 0.0;
+    }
+    double xj[M][4][3];
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int col = J * TS + 3 * p6col(q, e) + c;
+                xj[j][e][c] = col < n3 ? v[(size_t)(j0 + j) * n3 + col] : 0.0;
+            }
+    double cacc[M][4][3];
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cacc[j][e][0] = cacc[j][e][1] = cacc[j][e][2] = 0.0;
+    __syncthreads();
+    const double *tile = tiles + (size_t)t * TILE6;
+    const bool offd = I != J;
+#pragma unroll
+    for (int it = 0; it < TB / 16; ++it) {
+        const int i = 16 * it + 4 * w + g;
+        const double *row = tile + (size_t)i * 6 * TB + 2 * q;
+        double b[6][4];
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const d2v u = __builtin_nontemporal_load(
+                    reinterpret_cast<const d2v *>(row + c * TB + 32 * h));
+                b[c][2 * h] = u.x;
+                b[c][2 * h + 1] = u.y;
+            }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double x0 = xj[j][e][0], x1 = xj[j][e][1], x2 = xj[j][e][2];
+                r0 += b[0][e] * x0 + b[1][e] * x1 + b[2][e] * x2;
+                r1 += b[1][e] * x0 + b[3][e] * x1 + b[4][e] * x2;
+                r2 += b[2][e] * x0 + b[4][e] * x1 + b[5][e] * x2;
+            }
+            r0 = sum16(r0);
+            r1 = sum16(r1);
+            r2 = sum16(r2);
+            if (q < 3)
+                part[((size_t)J * rhs_cap + j0 + j) * n3pad + I * TS + 3 * i + q] =
+                    q == 0 ? r0 : q == 1 ? r1 : r2;
+            if (offd) {
+                const double y0 = sx[j][3 * i], y1 = sx[j][3 * i + 1], y2 = sx[j][3 * i + 2];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    cacc[j][e][0] += b[0][e] * y0 + b[1][e] * y1 + b[2][e] * y2;
+                    cacc[j][e][1] += b[1][e] * y0 + b[3][e] * y1 + b[4][e] * y2;
+                    cacc[j][e][2] += b[2][e] * y0 + b[4][e] * y1 + b[5][e] * y2;
+                }
+            }
+        }
+    }
+    if (!offd) return;
+    // combine the 4 row groups of a wave, then the 4 waves through LDS
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double s = cacc[j][e][c];
+                s += __shfl_xor(s, 16);
+                s += __shfl_xor(s, 32);
+                if (g == 0) scol[w][j][3 * p6col(q, e) + c] = s;
+            }
+    __syncthreads();
+    for (int e = threadIdx.x; e < M * TS; e += blockDim.x) {
+        const int j = e / TS, cidx = e % TS;
+        const double s = ((scol[0][j][cidx] + scol[1][j][cidx]) + scol[2][j][cidx]) + scol[3][j][cidx];
+        part[((size_t)I * rhs_cap + j0 + j) * n3pad + J * TS + cidx] = s;
+    }
+}
+
 template <typename T, int M> static size_t symv_lds(const Ctx &c)
 {
     // sx occupies M*TS double slots (whatever A is), then scol[4][M][TS]
@@ -182,9 +292,14 @@ static void symv_launch(const Ctx &c, const T *tiles, const double *v, int j0, h
     const int nkb = (c.nk + 255) / 256;
     const int nsf = c.nsfc * nkb;
     const size_t lds = symv_lds<T, M>(c);
-    hipLaunchKernelGGL((k_symv<T, M>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N,
-                       c.n3, c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab,
-                       c.sfpart, c.tile_ij, tiles, v, c.part);
+    if constexpr (sizeof(T) == sizeof(double))   // packed FP64 tiles
+        hipLaunchKernelGGL((k_symv6<M>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N,
+                           c.n3, c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab,
+                           c.sfpart, c.tile_ij, tiles, v, c.part);
+    else
+        hipLaunchKernelGGL((k_symv<T, M>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N,
+                           c.n3, c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab,
+                           c.sfpart, c.tile_ij, tiles, v, c.part);
 }
 
 template <typename T>

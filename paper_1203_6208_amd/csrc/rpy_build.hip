@@ -102,7 +102,6 @@ __global__ __launch_bounds__(256) void k_build_tiles(int N, const int2 *__restri
     const int bj = tid & (TB - 1);
     const int bi0 = tid >> 6;
     const int mu = J * TB + bj;
-    const size_t tbase = (size_t)t * TILE_ELEMS;
     for (int s = 0; s < TB / 4; ++s) {
         const int bi = bi0 + 4 * s;
         const int nu = I * TB + bi;
@@ -111,15 +110,20 @@ __global__ __launch_bounds__(256) void k_build_tiles(int N, const int2 *__restri
             pair_block(sI[3 * bi] - sJ[3 * bj], sI[3 * bi + 1] - sJ[3 * bj + 1],
                        sI[3 * bi + 2] - sJ[3 * bj + 2], nu == mu, p, b);
         }
-        const double v[9] = {b[0], b[1], b[2], b[1], b[3], b[4], b[2], b[4], b[5]};
-        const size_t o = tbase + (size_t)(3 * bi) * TS + 3 * bj;
+        // packed FP64 planes: a wave writes 512 contiguous bytes per plane
+        const size_t o6 = (size_t)t * TILE6 + (size_t)bi * 6 * TB + bj;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
+        for (int e = 0; e < 6; ++e) d64[o6 + (size_t)e * TB] = b[e];
+        if (LOWP) {
+            const double v[9] = {b[0], b[1], b[2], b[1], b[3], b[4], b[2], b[4], b[5]};
+            const size_t o = (size_t)t * TILE_ELEMS + (size_t)(3 * bi) * TS + 3 * bj;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                d64[o + (size_t)i * TS + j] = v[3 * i + j];
-                if (LOWP == 1) d32[o + (size_t)i * TS + j] = (float)v[3 * i + j];
-                if (LOWP == 2) d16[o + (size_t)i * TS + j] = to_bf16(v[3 * i + j]);
+            for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    if (LOWP == 1) d32[o + (size_t)i * TS + j] = (float)v[3 * i + j];
+                    if (LOWP == 2) d16[o + (size_t)i * TS + j] = to_bf16(v[3 * i + j]);
+                }
             }
         }
     }
@@ -151,12 +155,14 @@ __global__ void k_dense_copy(int n3, int nbt, const double *__restrict__ d64,
     if (idx >= (size_t)n3 * n3) return;
     int row = (int)(idx / n3), col = (int)(idx % n3);
     int I = row / TS, J = col / TS, r = row % TS, cc = col % TS;
-    if (I > J) {
+    if (I > J) {   // the transposed block: the same, each block being symmetric
         int t = I; I = J; J = t;
         t = r; r = cc; cc = t;
     }
     const size_t tidx = (size_t)I * nbt - (size_t)I * (I - 1) / 2 + (J - I);
-    out[idx] = d64[tidx * TILE_ELEMS + (size_t)r * TS + cc];
+    const int a = min(r % 3, cc % 3), b = max(r % 3, cc % 3);
+    const int plane = 3 * a - a * (a - 1) / 2 + (b - a);   // xx xy xz yy yz zz
+    out[idx] = d64[tidx * TILE6 + ((size_t)(r / 3) * 6 + plane) * TB + cc / 3];
 }
 
 void launch_dense_copy(const Ctx &c, double *out, hipStream_t s)

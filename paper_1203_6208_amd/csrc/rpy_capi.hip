@@ -290,6 +290,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
         for (int J = I; J < c.nbt; ++J) tij.push_back(make_int2(I, J));
 
     const size_t te = c.lma ? 0 : (size_t)c.ntiles * TILE_ELEMS;
+    const size_t te6 = c.lma ? 0 : (size_t)c.ntiles * TILE6;
     const size_t lcells = c.lma ? (size_t)c.lma_nc * c.lma_nc * c.lma_nc : 0;
     const size_t nv = (size_t)c.n3;
     const size_t mv = (size_t)c.rhs_cap * nv;
@@ -298,7 +299,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     const size_t ncells_cap = (size_t)ncell_cap * ncell_cap * ncell_cap;
     if ((rc = dalloc(&c.rt, nv)) || (rc = dalloc(&c.rt_ev, nv)) || (rc = dalloc(&c.etab, nv * (c.nmax + 1))) ||
         (rc = dalloc(&c.kvec, kv.size())) || (rc = dalloc(&c.kcoef, kc.size())) ||
-        (rc = dalloc(&c.tile_ij, tij.size())) || (!c.lma && (rc = dalloc(&c.d64, te))) ||
+        (rc = dalloc(&c.tile_ij, tij.size())) || (!c.lma && (rc = dalloc(&c.d64, te6))) ||
         (c.lma && ((rc = dalloc(&c.lma_start, 2 * lcells + 1)) ||
                    (rc = dalloc(&c.lma_beads, (size_t)c.N)) ||
                    (rc = dalloc(&c.rt_sorted, nv)) ||
@@ -342,7 +343,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
         (e = hipMemcpy(c.kcoef, kc.data(), kc.size() * sizeof(KCoef), hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(c.tile_ij, tij.data(), tij.size() * sizeof(int2), hipMemcpyHostToDevice)) ||
         (e = hipMemset(c.flags, 0, 4 * sizeof(int))) ||
-        (te && (e = hipMemset(c.d64, 0, te * sizeof(double)))) ||
+        (te6 && (e = hipMemset(c.d64, 0, te6 * sizeof(double)))) ||
         (c.block && (e = hipMemset(c.tkm, 0, (size_t)c.nk4 * 6 * BLOCK_RHS * sizeof(double))))) {
         rc = hip_fail(e, "rpy_create upload");
         rpy_destroy(x);

@@ -2,12 +2,18 @@
 //
 // Storage of the real-space diffusion matrix: the 3N x 3N matrix is cut into
 // square tiles of TB = 64 beads (TS = 192 rows/columns).  Only the tiles
-// (I, J) with I <= J are stored (D is symmetric), each TS x TS row-major and
-// contiguous, in the order t = I*nbt - I*(I-1)/2 + (J - I).  Rows and columns
-// past 3N are zero.  A product y = D.x reads every stored tile once and
-// produces both A_IJ x_J (rows of I) and A_IJ^T x_I (rows of J); the partial
-// results land in part[K][j][row] so that row r of y is the fixed-order sum
-// over K of part[K][j][r] (K = the tile column the contribution came from).
+// (I, J) with I <= J are stored (D is symmetric), contiguous, in the order
+// t = I*nbt - I*(I-1)/2 + (J - I).  Beads past N have zero entries.
+//   FP64 tiles (d64): every 3 x 3 bead-pair block of D is itself symmetric
+//   (each pair term is a I + b rhat rhat), so a tile keeps 6 entries per bead
+//   pair, as planes: d64[t][i][c][j] (TILE6 doubles), i, j the beads of I and
+//   J within the tile, c = xx, xy, xz, yy, yz, zz.
+//   FP32 / BF16 tiles (d32, d16): TS x TS row-major (TILE_ELEMS), the operand
+//   layout of the matrix-core block product.
+// A product y = D.x reads every stored tile once and produces both A_IJ x_J
+// (rows of I) and A_IJ^T x_I (rows of J); the partial results land in
+// part[K][j][row] so that row r of y is the fixed-order sum over K of
+// part[K][j][r] (K = the tile column the contribution came from).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,6 +28,7 @@ namespace rpy {
 constexpr int TB = 64;          // beads per tile side
 constexpr int TS = 3 * TB;      // matrix rows per tile side
 constexpr int TILE_ELEMS = TS * TS;
+constexpr int TILE6 = 6 * TB * TB;   // packed FP64 tile: 6 planes per bead row
 constexpr int NSER = 20;        // terms of the small-r series of S(r)
 constexpr double XSER = 0.75;   // use the series for alpha*r below this
 constexpr int MAX_RHS = 16;
@@ -358,7 +365,7 @@ struct Ctx {
     KVec *kvec = nullptr;        // [nk]
     KCoef *kcoef = nullptr;      // [nk]
     int2 *tile_ij = nullptr;     // [ntiles]
-    double *d64 = nullptr;       // [ntiles][TS*TS]
+    double *d64 = nullptr;       // [ntiles][TILE6], packed symmetric blocks
     float *d32 = nullptr;
     uint16_t *d16 = nullptr;
     double *part = nullptr;      // [nbt][rhs_cap][n3pad] tile-column partials
