@@ -420,23 +420,9 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
     const KVec *kv_s = staged ? reinterpret_cast<const KVec *>(lds) : kvec;
     const double *tk_s = staged ? lds + 2 * (nk + 1) : tk_g + (size_t)j0 * 6;
     const int tk_ld = staged ? 6 * M : 6 * rhs_cap;
-    if (staged) {
-        KVec *kd = reinterpret_cast<KVec *>(lds);
-        double *td = lds + 2 * (nk + 1);
-        const int ntk = nk * 6 * M;
-        const KVec kv0 = kvec[min((int)threadIdx.x, nk - 1)];
-        double tv[EPI_STAGE_PER];
-#pragma unroll
-        for (int i = 0; i < EPI_STAGE_PER; ++i) {
-            const int e = min((int)threadIdx.x + 1024 * i, ntk - 1);
-            const int k = e / (6 * M), r = e % (6 * M);
-            tv[i] = tk_g[((size_t)k * rhs_cap + j0) * 6 + r];
-        }
-        kd[min((int)threadIdx.x, nk)] = kv0;
-#pragma unroll
-        for (int i = 0; i < EPI_STAGE_PER; ++i) td[min((int)threadIdx.x + 1024 * i, ntk)] = tv[i];
-        __syncthreads();
-    }
+    // Loads that do not depend on the staged tables are issued first: the
+    // bead's fractional position, its tile-column partials and, for the 3
+    // EPI_BEADS threads that apply the epilogue, the recurrence operands.
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int bl = lane & 15, sub = lane >> 4;
     const int u = 4 * w + sub;
@@ -457,6 +443,35 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
                 y[j][2] += pp[2];
             }
         }
+    }
+    const int eb = (int)threadIdx.x / 3, ec = (int)threadIdx.x % 3;
+    const int ebead = blockIdx.x * EPI_BEADS + eb;
+    const bool eth = threadIdx.x < 3 * EPI_BEADS && ebead < N;
+    double pv[M], pv2[M], pa[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const size_t o = (size_t)(j0 + j) * n3 + 3 * (size_t)ebead + ec;
+        pv[j] = eth && f.mode != EPI_APPLY ? f.vprev[o] : 0.0;
+        pv2[j] = eth && f.vprev2 && (f.mode == EPI_CHEB_NEXT || f.mode == EPI_ADJ) ? f.vprev2[o]
+                                                                                    : 0.0;
+        pa[j] = eth && (f.mode == EPI_CHEB_NEXT || f.mode == EPI_ADJ) ? f.acc[o] : 0.0;
+    }
+    if (staged) {
+        KVec *kd = reinterpret_cast<KVec *>(lds);
+        double *td = lds + 2 * (nk + 1);
+        const int ntk = nk * 6 * M;
+        const KVec kv0 = kvec[min((int)threadIdx.x, nk - 1)];
+        double tv[EPI_STAGE_PER];
+#pragma unroll
+        for (int i = 0; i < EPI_STAGE_PER; ++i) {
+            const int e = min((int)threadIdx.x + 1024 * i, ntk - 1);
+            const int k = e / (6 * M), r = e % (6 * M);
+            tv[i] = tk_g[((size_t)k * rhs_cap + j0) * 6 + r];
+        }
+        kd[min((int)threadIdx.x, nk)] = kv0;
+#pragma unroll
+        for (int i = 0; i < EPI_STAGE_PER; ++i) td[min((int)threadIdx.x + 1024 * i, ntk)] = tv[i];
+        __syncthreads();
     }
     const int klo = (int)((long)u * nk / EPI_SLICES), khi = (int)((long)(u + 1) * nk / EPI_SLICES);
     double ezr, ezi;
@@ -492,36 +507,30 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
             if (sub == 0) red[w][c][bl] = v;
         }
         __syncthreads();
-        if (threadIdx.x < 3 * EPI_BEADS) {
-            const int b = threadIdx.x / 3, c = threadIdx.x % 3;
-            const int bead = blockIdx.x * EPI_BEADS + b;
-            if (bead < N) {
-                double yy = 0.0;
+        if (eth) {
+            double yy = 0.0;
 #pragma unroll
-                for (int ww = 0; ww < 16; ++ww) yy += red[ww][c][b];
-                const size_t o = (size_t)(j0 + j) * n3 + 3 * bead + c;
-                if (f.mode == EPI_APPLY) {
-                    f.vout[o] = yy;
-                } else if (f.mode == EPI_CHEB_FIRST) {
-                    const double v0 = f.vprev[o];
-                    const double v1 = ya * yy - yb * v0;
-                    f.vout[o] = v1;
-                    f.acc[o] = 0.5 * f.scal[8] * v0 + f.scal[9] * v1;
-                    if (f.dv) f.dv[o] = yy;
-                } else if (f.mode == EPI_CHEB_NEXT) {
-                    const double vp = 2.0 * (ya * yy - yb * f.vprev[o]) - f.vprev2[o];
-                    f.vout[o] = vp;
-                    f.acc[o] += f.scal[8 + f.p] * vp;
-                } else {
-                    const double mp = f.scal[8 + f.p] * f.acc[o] +
-                                      2.0 * (ya * yy - yb * f.vprev[o]) -
-                                      (f.vprev2 ? f.vprev2[o] : 0.0);
-                    f.vout[o] = mp;
-                    f.dv[o] = f.xs * ya * mp;
-                }
+            for (int ww = 0; ww < 16; ++ww) yy += red[ww][ec][eb];
+            const size_t o = (size_t)(j0 + j) * n3 + 3 * (size_t)ebead + ec;
+            if (f.mode == EPI_APPLY) {
+                f.vout[o] = yy;
+            } else if (f.mode == EPI_CHEB_FIRST) {
+                const double v0 = pv[j];
+                const double v1 = ya * yy - yb * v0;
+                f.vout[o] = v1;
+                f.acc[o] = 0.5 * f.scal[8] * v0 + f.scal[9] * v1;
+                if (f.dv) f.dv[o] = yy;
+            } else if (f.mode == EPI_CHEB_NEXT) {
+                const double vp = 2.0 * (ya * yy - yb * pv[j]) - pv2[j];
+                f.vout[o] = vp;
+                f.acc[o] = pa[j] + f.scal[8 + f.p] * vp;
+            } else {
+                const double mp = f.scal[8 + f.p] * pa[j] + 2.0 * (ya * yy - yb * pv[j]) - pv2[j];
+                f.vout[o] = mp;
+                f.dv[o] = f.xs * ya * mp;
             }
         }
-        __syncthreads();
+        if (j + 1 < M) __syncthreads();   // red is rewritten by the next vector
     }
 }
 

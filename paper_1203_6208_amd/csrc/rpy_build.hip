@@ -77,10 +77,32 @@ __device__ inline uint16_t to_bf16(double d)
     return (uint16_t)(u >> 16);
 }
 
-// One workgroup per stored tile (I <= J).  Thread (bi0, bj) computes the
-// pair blocks (I*64 + bi0 + 4s, J*64 + bj), s = 0..15, over all periodic
-// images and writes the 3x3 block into the row-major tile; LOWP also writes
-// the FP32 (1) or BF16 (2) copy of the same tile.
+// One workgroup per stored tile (I <= J).  Wave w takes the bead rows
+// bi = w + 4 s (s = 0..15), its 64 lanes the bead columns bj, so each step
+// computes 64 pair blocks (I*64 + bi, J*64 + bj) over their periodic images.
+// Whenever every axis has at most two candidate image shifts (always when
+// max(r_c, 2a) < L), a pair's candidates are the corners ci = 4 ix + 2 iy +
+// iz of a 2 x 2 x 2 cube (valid if ix < nxc, iy < nyc, iz < nzc; the order
+// nx, ny, nz of pair_block).  The lanes test their candidates
+// cheaply (|d|^2 against r_c^2 and (2a)^2), append those that contribute to
+// a per-wave LDS queue (ballot + prefix count) and evaluate the queue 64 at a
+// time, so the erfc / exp work runs on full waves (without the queue every
+// lane waits for the costliest candidate of all 64 lanes, about eight
+// evaluations per pair).  Each lane then adds its images' terms in candidate
+// order (the operations of pair_block, so the block is bit-identical).  A
+// step in which some pair has three or more shifts on an axis falls back to
+// pair_block.  The block goes to the packed FP64 planes; LOWP also writes
+// the FP32 (1) or BF16 (2) row-major tile.
+constexpr int IMG_SLOTS = 8;
+constexpr int IMG_QCAP = 128;
+
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int LOWP>
 __global__ __launch_bounds__(256) void k_build_tiles(int N, const int2 *__restrict__ tile_ij,
                                                      const double *__restrict__ rt, PairConst p,
@@ -89,6 +111,9 @@ __global__ __launch_bounds__(256) void k_build_tiles(int N, const int2 *__restri
                                                      uint16_t *__restrict__ d16)
 {
     __shared__ double sI[TS], sJ[TS];
+    __shared__ double q_r2[4][IMG_QCAP];
+    __shared__ int q_id[4][IMG_QCAP];
+    __shared__ double2 res[4][IMG_SLOTS][64];   // (c1, c2) of lane's candidate
     const int t = blockIdx.x;
     const int2 ij = tile_ij[t];
     const int I = ij.x, J = ij.y;
@@ -99,16 +124,86 @@ __global__ __launch_bounds__(256) void k_build_tiles(int N, const int2 *__restri
         sJ[e] = bJ < N ? rt[3 * (size_t)J * TB + e] : 0.0;
     }
     __syncthreads();
-    const int bj = tid & (TB - 1);
-    const int bi0 = tid >> 6;
+    const int lane = tid & 63, w = tid >> 6;
+    const int bj = lane;
     const int mu = J * TB + bj;
+    double *qr = q_r2[w];
+    int *qi = q_id[w];
     for (int s = 0; s < TB / 4; ++s) {
-        const int bi = bi0 + 4 * s;
+        const int bi = w + 4 * s;
         const int nu = I * TB + bi;
+        const bool live = nu < N && mu < N;
+        const bool self = nu == mu;
+        const double d0x = sI[3 * bi] - sJ[3 * bj], d0y = sI[3 * bi + 1] - sJ[3 * bj + 1],
+                     d0z = sI[3 * bi + 2] - sJ[3 * bj + 2];
+        const int xl = image_lo(d0x, p), yl = image_lo(d0y, p), zl = image_lo(d0z, p);
+        const int nxc = max(0, image_hi(d0x, p) - xl + 1), nyc = max(0, image_hi(d0y, p) - yl + 1),
+                  nzc = max(0, image_hi(d0z, p) - zl + 1);
         double b[6] = {0, 0, 0, 0, 0, 0};
-        if (nu < N && mu < N) {
-            pair_block(sI[3 * bi] - sJ[3 * bj], sI[3 * bi + 1] - sJ[3 * bj + 1],
-                       sI[3 * bi + 2] - sJ[3 * bj + 2], nu == mu, p, b);
+        if (__any(live && (nxc > 2 || nyc > 2 || nzc > 2))) {   // wave-uniform: the plain walk
+            if (live) pair_block(d0x, d0y, d0z, self, p, b);
+        } else {
+            const double dxs[2] = {d0x + xl * p.L, d0x + (xl + 1) * p.L};
+            const double dys[2] = {d0y + yl * p.L, d0y + (yl + 1) * p.L};
+            const double dzs[2] = {d0z + zl * p.L, d0z + (zl + 1) * p.L};
+            unsigned inmask = 0u;   // this lane's contributing candidates
+            int qn = 0;             // wave-uniform
+#pragma unroll
+            for (int ci = 0; ci < IMG_SLOTS; ++ci) {
+                const int ix = ci >> 2, iy = (ci >> 1) & 1, iz = ci & 1;
+                const double dx = dxs[ix], dy = dys[iy], dz = dzs[iz];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const bool in = live && ix < nxc && iy < nyc && iz < nzc &&
+                                !(self && xl + ix == 0 && yl + iy == 0 && zl + iz == 0) &&
+                                (r2 <= p.rc2 || r2 < p.a2x4);
+                inmask |= in ? 1u << ci : 0u;
+                const unsigned long long mask = __ballot(in);
+                const int before = __popcll(mask & ((1ull << lane) - 1ull));
+                if (in) {
+                    qr[qn + before] = r2;
+                    qi[qn + before] = ci * 64 + lane;
+                }
+                qn += __popcll(mask);
+                if (qn >= 64) {   // a full wave of image terms
+                    wave_sync();
+                    const double er2 = qr[lane];
+                    const int eid = qi[lane];
+                    const int rest = qn - 64;
+                    const double mr2 = lane < rest ? qr[64 + lane] : 0.0;
+                    const int mid = lane < rest ? qi[64 + lane] : 0;
+                    wave_sync();
+                    if (lane < rest) {
+                        qr[lane] = mr2;
+                        qi[lane] = mid;
+                    }
+                    qn = rest;
+                    double c1, c2;
+                    image_coeffs(er2, p, c1, c2);
+                    res[w][eid >> 6][eid & 63] = make_double2(c1, c2);
+                }
+            }
+            wave_sync();
+            if (lane < qn) {
+                double c1, c2;
+                image_coeffs(qr[lane], p, c1, c2);
+                const int eid = qi[lane];
+                res[w][eid >> 6][eid & 63] = make_double2(c1, c2);
+            }
+            wave_sync();
+#pragma unroll
+            for (int ci = 0; ci < IMG_SLOTS; ++ci) {   // this lane's images, in order
+                if (!(inmask & (1u << ci))) continue;
+                const double dx = dxs[ci >> 2], dy = dys[(ci >> 1) & 1], dz = dzs[ci & 1];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double2 cc = res[w][ci][lane];
+                add_coeffs(dx, dy, dz, r2, cc.x, cc.y, b);
+            }
+            if (self) {
+                b[0] += p.self_coeff;
+                b[3] += p.self_coeff;
+                b[5] += p.self_coeff;
+            }
+            wave_sync();   // res and the queue are reused by the next step
         }
         // packed FP64 planes: a wave writes 512 contiguous bytes per plane
         const size_t o6 = (size_t)t * TILE6 + (size_t)bi * 6 * TB + bj;

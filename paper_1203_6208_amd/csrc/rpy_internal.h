@@ -105,15 +105,13 @@ RPY_HD inline void smooth_part(double x, const PairConst &p, double &s1, double 
 //   |d| <= rc, |d| >= 2a : M1(d)
 //   |d| <= rc, |d| <  2a : M1 + M* = Omega_B - S   (stable at small r)
 //   |d| >  rc, |d| <  2a : M* = Omega_B - Omega_A  (eq. cor5)
-RPY_HD inline void add_image(double dx, double dy, double dz, const PairConst &p,
-                             double b[6])
+// The coefficients c1 (of I) and c2 (of rhat rhat) of an image at squared
+// distance r2 that contributes (r2 <= rc^2 or r2 < (2a)^2).
+RPY_HD inline void image_coeffs(double r2, const PairConst &p, double &c1, double &c2)
 {
-    const double r2 = dx * dx + dy * dy + dz * dz;
     const bool in_rc = r2 <= p.rc2;
     const bool ov = r2 < p.a2x4;
-    if (!in_rc && !ov) return;
     const double r = sqrt(r2);
-    double c1, c2;
     if (!ov) {
         m1_coeffs(r, p, c1, c2);
     } else {
@@ -131,6 +129,12 @@ RPY_HD inline void add_image(double dx, double dy, double dz, const PairConst &p
             c2 = ob2 - (0.75 * ar - 1.5 * ar3);
         }
     }
+}
+
+// b += c1 I + (c2 / r2) d d^T for an image d (r2 = |d|^2).
+RPY_HD inline void add_coeffs(double dx, double dy, double dz, double r2, double c1, double c2,
+                              double b[6])
+{
     b[0] += c1;
     b[3] += c1;
     b[5] += c1;
@@ -143,6 +147,16 @@ RPY_HD inline void add_image(double dx, double dy, double dz, const PairConst &p
         b[4] += w * dy * dz;
         b[5] += w * dz * dz;
     }
+}
+
+RPY_HD inline void add_image(double dx, double dy, double dz, const PairConst &p,
+                             double b[6])
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 <= p.rc2) && !(r2 < p.a2x4)) return;
+    double c1, c2;
+    image_coeffs(r2, p, c1, c2);
+    add_coeffs(dx, dy, dz, r2, c1, c2, b);
 }
 
 RPY_HD inline int image_lo(double d, const PairConst &p)
