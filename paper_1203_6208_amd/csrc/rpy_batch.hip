@@ -146,7 +146,9 @@ __global__ void k_bstep_set(unsigned long long *stepc, unsigned long long v)
 
 // ------------------------------------------------------------- real space
 // One workgroup per stored tile (box, I, J); as k_build_tiles with the box's
-// pair constants and TBB-bead tiles.
+// pair constants and TBB-bead tiles, written as packed planes
+// tile[i][c][j] (6 TBB^2 values, c = xx, xy, xz, yy, yz, zz: each 3 x 3
+// bead-pair block is symmetric), FP64 and, with LOWP, FP32.
 template <int TBB, int LOWP>
 __global__ __launch_bounds__(256) void k_bbuild(const int4 *__restrict__ stor,
                                                 const BoxDev *__restrict__ boxes,
@@ -169,7 +171,6 @@ __global__ __launch_bounds__(256) void k_bbuild(const int4 *__restrict__ stor,
     __syncthreads();
     const int bj = tid % TBB, bi0 = tid / TBB;
     const int mu = J * TBB + bj;
-    const size_t tbase = (size_t)t * TSB * TSB;
     for (int s = 0; s < TBB / STEP; ++s) {
         const int bi = bi0 + STEP * s;
         const int nu = I * TBB + bi;
@@ -177,72 +178,67 @@ __global__ __launch_bounds__(256) void k_bbuild(const int4 *__restrict__ stor,
         if (nu < d.N && mu < d.N)
             pair_block(sI[3 * bi] - sJ[3 * bj], sI[3 * bi + 1] - sJ[3 * bj + 1],
                        sI[3 * bi + 2] - sJ[3 * bj + 2], nu == mu, d.pc, b);
-        const double v[9] = {b[0], b[1], b[2], b[1], b[3], b[4], b[2], b[4], b[5]};
-        const size_t o = tbase + (size_t)(3 * bi) * TSB + 3 * bj;
+        const size_t o6 = (size_t)t * 6 * TBB * TBB + (size_t)bi * 6 * TBB + bj;
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                d64[o + (size_t)i * TSB + j] = v[3 * i + j];
-                if (LOWP) d32[o + (size_t)i * TSB + j] = (float)v[3 * i + j];
-            }
+        for (int e = 0; e < 6; ++e) {
+            d64[o6 + (size_t)e * TBB] = b[e];
+            if (LOWP) d32[o6 + (size_t)e * TBB] = (float)b[e];
+        }
     }
 }
 
 // ------------------------------------------------------------------ product
-// Columns of a tile row owned by lane q (0..15) of a 16-lane row group and
-// their loads: FP64 tiles in 16-byte pairs at 32 s + 2 q; FP32 tiles in
-// 16-byte quads at 64 s + 4 q (64-bead tiles) or a quad at 4 q plus a pair
-// at 64 + 2 q (32-bead tiles).  Every row is read once, contiguously across
-// the row group.
-// Tiles are read once per product: non-temporal loads.
+// Packed tiles: a bead row i of a tile holds 6 planes of TBB values.  Lane q
+// (0..15) of a 16-lane row group owns NE = TBB/16 bead columns of every
+// plane and reads them with one or two 16-byte (8-byte for FP32 32-bead
+// tiles) non-temporal loads, contiguous across the row group.
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 template <typename T, int TBB> struct BLd;
-template <int TBB> struct BLd<double, TBB> {
-    static constexpr int NE = 3 * TBB / 16;
+template <> struct BLd<double, 64> {
+    static constexpr int NE = 4;
     __device__ static int col(int q, int e) { return 32 * (e >> 1) + 2 * q + (e & 1); }
     __device__ static void load(const double *row, int q, double a[NE])
     {
-#pragma unroll
-        for (int s = 0; s < NE / 2; ++s) {
-            const d2v v =
-                __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 32 * s + 2 * q));
-            a[2 * s] = v.x;
-            a[2 * s + 1] = v.y;
-        }
+        const d2v u = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 2 * q));
+        const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 32 + 2 * q));
+        a[0] = u.x;
+        a[1] = u.y;
+        a[2] = v.x;
+        a[3] = v.y;
+    }
+};
+template <> struct BLd<double, 32> {
+    static constexpr int NE = 2;
+    __device__ static int col(int q, int e) { return 2 * q + e; }
+    __device__ static void load(const double *row, int q, double a[NE])
+    {
+        const d2v u = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 2 * q));
+        a[0] = u.x;
+        a[1] = u.y;
     }
 };
 template <> struct BLd<float, 64> {
-    static constexpr int NE = 12;
-    __device__ static int col(int q, int e) { return 64 * (e >> 2) + 4 * q + (e & 3); }
+    static constexpr int NE = 4;
+    __device__ static int col(int q, int e) { return 4 * q + e; }
     __device__ static void load(const float *row, int q, double a[NE])
     {
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            const f4v v =
-                __builtin_nontemporal_load(reinterpret_cast<const f4v *>(row + 64 * s + 4 * q));
-            a[4 * s] = v.x;
-            a[4 * s + 1] = v.y;
-            a[4 * s + 2] = v.z;
-            a[4 * s + 3] = v.w;
-        }
+        const f4v u = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(row + 4 * q));
+        a[0] = u.x;
+        a[1] = u.y;
+        a[2] = u.z;
+        a[3] = u.w;
     }
 };
 template <> struct BLd<float, 32> {
-    static constexpr int NE = 6;
-    __device__ static int col(int q, int e) { return e < 4 ? 4 * q + e : 64 + 2 * q + (e - 4); }
+    static constexpr int NE = 2;
+    __device__ static int col(int q, int e) { return 2 * q + e; }
     __device__ static void load(const float *row, int q, double a[NE])
     {
-        const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(row + 4 * q));
-        const f2v u = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(row + 64 + 2 * q));
-        a[0] = v.x;
-        a[1] = v.y;
-        a[2] = v.z;
-        a[3] = v.w;
-        a[4] = u.x;
-        a[5] = u.y;
+        const f2v u = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(row + 2 * q));
+        a[0] = u.x;
+        a[1] = u.y;
     }
 };
 
@@ -251,9 +247,9 @@ template <> struct BLd<float, 32> {
 // per k:
 //   sfpart[chunk][6 j + c][k] = sum over the chunk's real beads of
 //   {cos, sin}(k.r) v_c.
-// The other workgroups: one stored tile each, as k_symv (4 waves; row group of
-// 16 lanes per tile row; each lane owns the TSB/16 columns of BLd; FP64
-// accumulation for both tile types).
+// The other workgroups: one stored packed tile each, as the single-box FP64
+// product (4 waves; a 16-lane row group per bead row; each lane owns the
+// NE bead columns of BLd; FP64 accumulation for both tile types).
 template <int TBB, typename T, int M>
 __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb, int nk, int nm1,
                                                const int *__restrict__ tile_box,
@@ -267,7 +263,7 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb
                                                double *__restrict__ part)
 {
     constexpr int TSB = 3 * TBB;
-    constexpr int NE = BLd<T, TBB>::NE;   // columns per lane
+    constexpr int NE = BLd<T, TBB>::NE;   // bead columns per lane
     extern __shared__ double smem[];
     // workgroup i is structure-factor workgroup i / sfr when i is a multiple
     // of sfr below nsf * sfr, else tile i - (structure-factor workgroups
@@ -323,8 +319,7 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb
             for (int c = 0; c < 6; ++c) o[(size_t)(6 * j + c) * nk] = acc[j][c];
         return;
     }
-    typedef double A;
-    A(*sx)[TSB] = reinterpret_cast<A(*)[TSB]>(smem);                          // [M][TSB]
+    double(*sx)[TSB] = reinterpret_cast<double(*)[TSB]>(smem);                    // [M][TSB]
     double(*scol)[M][TSB] = reinterpret_cast<double(*)[M][TSB]>(smem + M * TSB);  // [4][M][TSB]
     const int t = bid - nsf_before;
     const int4 e = stor[t];
@@ -337,37 +332,55 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb
         const int j = z / TSB, r = z % TSB;
         sx[j][r] = v[(size_t)j * G3 + rowI + r];
     }
-    A xj[M][NE];
+    double xj[M][NE][3];
 #pragma unroll
     for (int j = 0; j < M; ++j)
 #pragma unroll
         for (int c = 0; c < NE; ++c)
-            xj[j][c] = v[(size_t)j * G3 + rowJ + BLd<T, TBB>::col(q, c)];
-    A cacc[M][NE];
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+                xj[j][c][x] = v[(size_t)j * G3 + rowJ + 3 * BLd<T, TBB>::col(q, c) + x];
+    double cacc[M][NE][3];
 #pragma unroll
     for (int j = 0; j < M; ++j)
 #pragma unroll
-        for (int c = 0; c < NE; ++c) cacc[j][c] = 0.0;
+        for (int c = 0; c < NE; ++c) cacc[j][c][0] = cacc[j][c][1] = cacc[j][c][2] = 0.0;
     __syncthreads();
-    const T *tile = tiles + (size_t)t * TSB * TSB;
+    const T *tile = tiles + (size_t)t * 6 * TBB * TBB;
     const bool offd = I != J;
-#pragma unroll 4
-    for (int it = 0; it < TSB / 16; ++it) {
-        const int r = 16 * it + 4 * w + g;
-        A a[NE];
-        BLd<T, TBB>::load(tile + (size_t)r * TSB, q, a);
+#pragma unroll
+    for (int it = 0; it < TBB / 16; ++it) {
+        const int i = 16 * it + 4 * w + g;
+        const T *row = tile + (size_t)i * 6 * TBB;
+        double b[6][NE];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) BLd<T, TBB>::load(row + c * TBB, q, b[c]);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            A rs = 0.0;
+            double r0 = 0.0, r1 = 0.0, r2 = 0.0;
 #pragma unroll
-            for (int c = 0; c < NE; ++c) rs += a[c] * xj[j][c];
+            for (int c = 0; c < NE; ++c) {
+                const double x0 = xj[j][c][0], x1 = xj[j][c][1], x2 = xj[j][c][2];
+                r0 += b[0][c] * x0 + b[1][c] * x1 + b[2][c] * x2;
+                r1 += b[1][c] * x0 + b[3][c] * x1 + b[4][c] * x2;
+                r2 += b[2][c] * x0 + b[4][c] * x1 + b[5][c] * x2;
+            }
 #pragma unroll
-            for (int o = 8; o >= 1; o >>= 1) rs += __shfl_xor(rs, o, 16);
-            if (q == 0) part[((size_t)J * BRC + j) * G3 + rowI + r] = rs;
+            for (int o = 8; o >= 1; o >>= 1) {
+                r0 += __shfl_xor(r0, o, 16);
+                r1 += __shfl_xor(r1, o, 16);
+                r2 += __shfl_xor(r2, o, 16);
+            }
+            if (q < 3)
+                part[((size_t)J * BRC + j) * G3 + rowI + 3 * i + q] = q == 0 ? r0 : q == 1 ? r1 : r2;
             if (offd) {
-                const A xr = sx[j][r];
+                const double y0 = sx[j][3 * i], y1 = sx[j][3 * i + 1], y2 = sx[j][3 * i + 2];
 #pragma unroll
-                for (int c = 0; c < NE; ++c) cacc[j][c] += a[c] * xr;
+                for (int c = 0; c < NE; ++c) {
+                    cacc[j][c][0] += b[0][c] * y0 + b[1][c] * y1 + b[2][c] * y2;
+                    cacc[j][c][1] += b[1][c] * y0 + b[3][c] * y1 + b[4][c] * y2;
+                    cacc[j][c][2] += b[2][c] * y0 + b[4][c] * y1 + b[5][c] * y2;
+                }
             }
         }
     }
@@ -375,12 +388,14 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb
 #pragma unroll
     for (int j = 0; j < M; ++j)
 #pragma unroll
-        for (int c = 0; c < NE; ++c) {
-            double s = cacc[j][c];
-            s += __shfl_xor(s, 16);
-            s += __shfl_xor(s, 32);
-            if (g == 0) scol[w][j][BLd<T, TBB>::col(q, c)] = s;
-        }
+        for (int c = 0; c < NE; ++c)
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                double s = cacc[j][c][x];
+                s += __shfl_xor(s, 16);
+                s += __shfl_xor(s, 32);
+                if (g == 0) scol[w][j][3 * BLd<T, TBB>::col(q, c) + x] = s;
+            }
     __syncthreads();
     for (int z = threadIdx.x; z < M * TSB; z += blockDim.x) {
         const int j = z / TSB, ci = z % TSB;
@@ -752,7 +767,7 @@ struct rpy_batch {
     KCoef *kcoef = nullptr;       // [nbox][nk]
     double *rt = nullptr, *sfr = nullptr;   // [G][3]
     double2 *etab = nullptr;      // [G][3][nmax + 1]
-    double *d64 = nullptr;        // [nstor][TSB * TSB]
+    double *d64 = nullptr;        // [nstor][6 TBB^2] packed planes
     float *d32 = nullptr;
     double *part = nullptr;       // [maxnbt][BRC][3G]
     double *sfpart = nullptr;     // [ntb][6 BRC][nk]
@@ -847,7 +862,7 @@ extern "C" int rpy_batch_create(rpy_batch **out, const rpy_params *bp, int nbox,
     b->nbox = nbox;
     b->tbb = tile_beads;
     b->lowp = lowp;
-    const int TBB = tile_beads, TSB = 3 * tile_beads;
+    const int TBB = tile_beads;
     int nmax = (int)floor(sqrt((double)n2max));
     while ((nmax + 1) * (nmax + 1) <= n2max) ++nmax;
     while (nmax * nmax > n2max) --nmax;
@@ -925,7 +940,7 @@ extern "C" int rpy_batch_create(rpy_batch **out, const rpy_params *bp, int nbox,
     }
 
     const size_t G3 = 3 * (size_t)b->G;
-    const size_t te = (size_t)b->nstor * TSB * TSB;
+    const size_t te = (size_t)b->nstor * 6 * TBB * TBB;
     int rc;
     if ((rc = balloc(&b->boxes, nbox)) || (rc = balloc(&b->tile_box, b->ntb)) ||
         (rc = balloc(&b->stor, b->nstor)) || (rc = balloc(&b->chains, b->nchain)) ||
