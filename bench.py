@@ -34,17 +34,17 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on 1 GiB device copies in the same process).  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "ef18088023681def505895a0430381ab4023caf8992d95df8f485a07019ea48e",
+TRAFFIC = {"src_sha256": "fa59f88641a546e0b85d5c6ff702951127f2c6d9f978e9e0bc4e56c495892043",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 607770986}
-TRAFFIC_BLOCK = {"src_sha256": "1212ff32b4bee16a4494b3236ffeb093131ae7fa7fdc4c63290e99aaed0b8b0e",
+           "bytes_per_launch": 409642667}
+TRAFFIC_BLOCK = {"src_sha256": "5abfa89c82dff85286e5a56da84134a6e6101d14931229953277db0b2d79748c",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f32": 312236895 + 48771072, "bf16": 159636202 + 48771072}}
+                 "bytes_per_launch": {"f32": 312316961 + 48771072, "bf16": 159672889 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "6772e6305d6ba6ef687cb51a4ccdcfcfa72f2eecead380924c9de7d756b2a0b1",
+TRAFFIC_BATCH = {"src_sha256": "5d8414f9a8ba7e8e72e61241008ea028dd69bba96f7614f5cd460e18d6d61798",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 7152715290}
+                 "bytes_per_launch": 4931225421}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 
@@ -179,7 +179,7 @@ def time_block(w, prec, reps, torch, rpy):
         n, ms = rpy.rpy_profile_read(ctx.handle, kind)
         stage[nm + "_us"] = 1e3 * ms / nprod
     rpy.rpy_profile_enable(ctx.handle, 0)
-    gbs = tile_bytes(w.n, prec) / (stage["tile_product_us"] * 1e-6) / 1e9
+    gbs = tile_bytes(w.n, prec, packed=prec == "f64") / (stage["tile_product_us"] * 1e-6) / 1e9
     del ctx
     return {"ms_per_block": 1e3 * wall, "us_per_product": 1e6 * wall / nprod,
             **stage, "tile_product_GBs": gbs, "tile_product_hbm_frac": gbs / HBM_PEAK_GBS,
@@ -528,15 +528,17 @@ def cpu_baseline(w, seconds):
                        f"(O(N))")}
 
 
-def tile_bytes(n, prec):
-    """Algorithmic bytes one product streams: the unique entries of the
-    real-space matrix.  FP64 tiles keep the 6 distinct entries of each
-    symmetric 3 x 3 bead-pair block for the N(N+1)/2 pairs i <= j; FP32 and
-    BF16 tiles keep the symmetric half of the 3N x 3N matrix."""
-    if prec == "f64":
-        return 3 * n * (n + 1) * 8
+def tile_bytes(n, prec, packed=True):
+    """Algorithmic bytes one product streams.  Packed tiles (every product of
+    up to 4 vectors) keep the 6 distinct entries of each symmetric 3 x 3
+    bead-pair block for the N(N+1)/2 pairs i <= j; the matrix-core block
+    product (FP32 / BF16, 5-16 vectors) reads the symmetric half of the
+    3N x 3N matrix."""
+    esize = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+    if packed:
+        return 3 * n * (n + 1) * esize
     n3 = 3 * n
-    return n3 * (n3 + 1) // 2 * (4 if prec == "f32" else 2)
+    return n3 * (n3 + 1) // 2 * esize
 
 
 def measured_traffic(t=TRAFFIC, key=None):

@@ -16,50 +16,6 @@ namespace rpy {
     }
 
 // ------------------------------------------------------------------ SYMV
-// Element types of the FP32 / BF16 tiles (TS x TS row-major).  Each lane of a
-// 16-lane row group owns 12 fixed columns of the 192-column tile row and
-// loads them with 16-byte (or 8-byte) vector loads that are contiguous across
-// the row group.
-template <typename T> struct TileT;
-template <> struct TileT<float> {
-    using acc_t = float;
-    __device__ static int col(int q, int e) { return 64 * (e >> 2) + 4 * q + (e & 3); }
-    __device__ static void load(const float *row, int q, acc_t a[12])
-    {
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            const float *p = row + 64 * s + 4 * q;
-            a[4 * s] = __builtin_nontemporal_load(p);
-            a[4 * s + 1] = __builtin_nontemporal_load(p + 1);
-            a[4 * s + 2] = __builtin_nontemporal_load(p + 2);
-            a[4 * s + 3] = __builtin_nontemporal_load(p + 3);
-        }
-    }
-};
-template <> struct TileT<uint16_t> {
-    using acc_t = float;
-    __device__ static int col(int q, int e) { return e < 8 ? 8 * q + e : 128 + 4 * q + (e - 8); }
-    __device__ static float bf(uint32_t w, int hi)
-    {
-        return __uint_as_float(hi ? (w & 0xFFFF0000u) : (w << 16));
-    }
-    __device__ static void load(const uint16_t *row, int q, acc_t a[12])
-    {
-        typedef uint32_t u4v __attribute__((ext_vector_type(4)));
-        typedef uint32_t u2v __attribute__((ext_vector_type(2)));
-        const u4v v4 = __builtin_nontemporal_load(reinterpret_cast<const u4v *>(row + 8 * q));
-        const u2v v2 = __builtin_nontemporal_load(reinterpret_cast<const u2v *>(row + 128 + 4 * q));
-        const uint4 v = make_uint4(v4.x, v4.y, v4.z, v4.w);
-        const uint2 u = make_uint2(v2.x, v2.y);
-        a[0] = bf(v.x, 0); a[1] = bf(v.x, 1);
-        a[2] = bf(v.y, 0); a[3] = bf(v.y, 1);
-        a[4] = bf(v.z, 0); a[5] = bf(v.z, 1);
-        a[6] = bf(v.w, 0); a[7] = bf(v.w, 1);
-        a[8] = bf(u.x, 0); a[9] = bf(u.x, 1);
-        a[10] = bf(u.y, 0); a[11] = bf(u.y, 1);
-    }
-};
-
 template <typename A> __device__ inline A sum16(A x)
 {
 #pragma unroll
@@ -67,120 +23,71 @@ template <typename A> __device__ inline A sum16(A x)
     return x;
 }
 
-// Product kernel.  Workgroups [0, nsf) compute structure-factor partials of
-// v (above); each further workgroup (4 waves) takes one stored tile (I, J).
-// Wave w, row group g (16 lanes), lane q: rows r = 16 it + 4 w + g,
-// it = 0..11.  Row sums give A_IJ x_J -> part[J][j][rows of I]; column sums
-// (off-diagonal tiles only) give A_IJ^T x_I -> part[I][j][rows of J].
+// Loads of a packed plane row (64 values of one bead row and one entry of
+// the 3 x 3 blocks): lane q (0..15) of a 16-lane row group owns the bead
+// columns col(q, e), e = 0..3, read with 16-byte (FP64, FP32) or 8-byte
+// (BF16) non-temporal loads that are contiguous across the row group.
+template <typename T> struct P6;
+template <> struct P6<double> {
+    __device__ static int col(int q, int e) { return 32 * (e >> 1) + 2 * q + (e & 1); }
+    __device__ static void load(const double *row, int q, double a[4])
+    {
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        const d2v u = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 2 * q));
+        const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 32 + 2 * q));
+        a[0] = u.x;
+        a[1] = u.y;
+        a[2] = v.x;
+        a[3] = v.y;
+    }
+};
+template <> struct P6<float> {
+    __device__ static int col(int q, int e) { return 4 * q + e; }
+    __device__ static void load(const float *row, int q, double a[4])
+    {
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        const f4v u = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(row + 4 * q));
+        a[0] = u.x;
+        a[1] = u.y;
+        a[2] = u.z;
+        a[3] = u.w;
+    }
+};
+template <> struct P6<uint16_t> {
+    __device__ static int col(int q, int e) { return 4 * q + e; }
+    __device__ static void load(const uint16_t *row, int q, double a[4])
+    {
+        typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+        const u2v u = __builtin_nontemporal_load(reinterpret_cast<const u2v *>(row + 4 * q));
+        a[0] = __uint_as_float(u.x << 16);
+        a[1] = __uint_as_float(u.x & 0xFFFF0000u);
+        a[2] = __uint_as_float(u.y << 16);
+        a[3] = __uint_as_float(u.y & 0xFFFF0000u);
+    }
+};
+
+// Product on the packed tiles (6 planes per bead row, tile[t][i][c][j]),
+// FP64, FP32 or BF16 entries, FP64 arithmetic.  Workgroups [0, nsf) compute
+// structure-factor partials of v; each further workgroup (4 waves) takes one
+// stored tile (I, J).  Wave w, row group g (16 lanes), lane q: bead rows
+// i = 16 it + 4 w + g (it = 0..3); lane q owns the bead columns
+// jb(e) = P6<T>::col(q, e), e = 0..3, of every plane.  With B the symmetric
+// 3 x 3 block of (i, j), the row sums of B x_j over the 16 lanes give
+// A_IJ x_J -> part[J][j][rows of I]; for off-diagonal tiles each lane also
+// accumulates B x_i for its columns, and the 4 row groups and 4 waves are
+// combined in a fixed order -> part[I][j][rows of J].  Diagonal tiles hold
+// both (i, j) and (j, i) and take row sums only.
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_symv(int N, int n3, int n3pad, int rhs_cap, int j0,
-                                              int nsf, int nkb, int nk, int nmax,
-                                              const KVec *__restrict__ kvec,
-                                              const double2 *__restrict__ etab,
-                                              double *__restrict__ sfpart,
-                                              const int2 *__restrict__ tile_ij,
-                                              const T *__restrict__ tiles,
-                                              const double *__restrict__ v,
-                                              double *__restrict__ part)
-{
-    using A = typename TileT<T>::acc_t;
-    extern __shared__ double smem[];
-    if ((int)blockIdx.x < nsf) {
-        sf_partial_block<M>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
-                            sfpart, smem);
-        return;
-    }
-    A(*sx)[TS] = reinterpret_cast<A(*)[TS]>(smem);                       // [M][TS]
-    double(*scol)[M][TS] = reinterpret_cast<double(*)[M][TS]>(smem + M * TS);  // [4][M][TS]
-    const int t = blockIdx.x - nsf;
-    const int2 ij = tile_ij[t];
-    const int I = ij.x, J = ij.y;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int g = lane >> 4, q = lane & 15;
-    for (int e = threadIdx.x; e < M * TS; e += blockDim.x) {
-        const int j = e / TS, r = e % TS, row = I * TS + r;
-        sx[j][r] = row < n3 ? (A)v[(size_t)(j0 + j) * n3 + row] : (A)0;
-    }
-    A xj[M][12];
-#pragma unroll
-    for (int j = 0; j < M; ++j)
-#pragma unroll
-        for (int e = 0; e < 12; ++e) {
-            const int col = J * TS + TileT<T>::col(q, e);
-            xj[j][e] = col < n3 ? (A)v[(size_t)(j0 + j) * n3 + col] : (A)0;
-        }
-    A cacc[M][12];
-#pragma unroll
-    for (int j = 0; j < M; ++j)
-#pragma unroll
-        for (int e = 0; e < 12; ++e) cacc[j][e] = (A)0;
-    __syncthreads();
-    const T *tile = tiles + (size_t)t * TILE_ELEMS;
-    const bool offd = I != J;
-#pragma unroll 4
-    for (int it = 0; it < TS / 16; ++it) {
-        const int r = 16 * it + 4 * w + g;
-        A a[12];
-        TileT<T>::load(tile + (size_t)r * TS, q, a);
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            A rs = (A)0;
-#pragma unroll
-            for (int e = 0; e < 12; ++e) rs += a[e] * xj[j][e];
-            rs = sum16(rs);
-            if (q == 0)
-                part[((size_t)J * rhs_cap + j0 + j) * n3pad + I * TS + r] = (double)rs;
-            if (offd) {
-                const A xr = sx[j][r];
-#pragma unroll
-                for (int e = 0; e < 12; ++e) cacc[j][e] += a[e] * xr;
-            }
-        }
-    }
-    if (!offd) return;
-    // combine the 4 row groups of a wave, then the 4 waves through LDS
-#pragma unroll
-    for (int j = 0; j < M; ++j)
-#pragma unroll
-        for (int e = 0; e < 12; ++e) {
-            double s = (double)cacc[j][e];
-            s += __shfl_xor(s, 16);
-            s += __shfl_xor(s, 32);
-            if (g == 0) scol[w][j][TileT<T>::col(q, e)] = s;
-        }
-    __syncthreads();
-    for (int e = threadIdx.x; e < M * TS; e += blockDim.x) {
-        const int j = e / TS, cidx = e % TS;
-        const double s = ((scol[0][j][cidx] + scol[1][j][cidx]) + scol[2][j][cidx]) + scol[3][j][cidx];
-        part[((size_t)I * rhs_cap + j0 + j) * n3pad + J * TS + cidx] = s;
-    }
-}
-
-// FP64 product on the packed tiles (6 planes per bead row, d64[t][i][c][j]).
-// Workgroups [0, nsf) compute structure-factor partials of v; each further
-// workgroup (4 waves) takes one stored tile (I, J).  Wave w, row group g (16
-// lanes), lane q: bead rows i = 16 it + 4 w + g (it = 0..3); lane q owns the
-// bead columns jb(e) = 32 (e >> 1) + 2 q + (e & 1), e = 0..3, and reads each
-// plane with two 16-byte non-temporal loads (256 contiguous bytes per row
-// group and load).  With B the symmetric 3 x 3 block of (i, j), the row sums
-// of B x_j over the 16 lanes give A_IJ x_J -> part[J][j][rows of I]; for
-// off-diagonal tiles each lane also accumulates B x_i for its columns, and the
-// 4 row groups and 4 waves are combined in a fixed order -> part[I][j][rows
-// of J].  Diagonal tiles hold both (i, j) and (j, i) and take row sums only.
-__device__ inline int p6col(int q, int e) { return 32 * (e >> 1) + 2 * q + (e & 1); }
-
-template <int M>
 __global__ __launch_bounds__(256) void k_symv6(int N, int n3, int n3pad, int rhs_cap, int j0,
                                                int nsf, int nkb, int nk, int nmax,
                                                const KVec *__restrict__ kvec,
                                                const double2 *__restrict__ etab,
                                                double *__restrict__ sfpart,
                                                const int2 *__restrict__ tile_ij,
-                                               const double *__restrict__ tiles,
+                                               const T *__restrict__ tiles,
                                                const double *__restrict__ v,
                                                double *__restrict__ part)
 {
-    typedef double d2v __attribute__((ext_vector_type(2)));
     extern __shared__ double smem[];
     if ((int)blockIdx.x < nsf) {
         sf_partial_block<M>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
@@ -205,7 +112,7 @@ __global__ __launch_bounds__(256) void k_symv6(int N, int n3, int n3pad, int rhs
         for (int e = 0; e < 4; ++e)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const int col = J * TS + 3 * p6col(q, e) + c;
+                const int col = J * TS + 3 * P6<T>::col(q, e) + c;
                 xj[j][e][c] = col < n3 ? v[(size_t)(j0 + j) * n3 + col] : 0.0;
             }
     double cacc[M][4][3];
@@ -214,22 +121,15 @@ __global__ __launch_bounds__(256) void k_symv6(int N, int n3, int n3pad, int rhs
 #pragma unroll
         for (int e = 0; e < 4; ++e) cacc[j][e][0] = cacc[j][e][1] = cacc[j][e][2] = 0.0;
     __syncthreads();
-    const double *tile = tiles + (size_t)t * TILE6;
+    const T *tile = tiles + (size_t)t * TILE6;
     const bool offd = I != J;
 #pragma unroll
     for (int it = 0; it < TB / 16; ++it) {
         const int i = 16 * it + 4 * w + g;
-        const double *row = tile + (size_t)i * 6 * TB + 2 * q;
+        const T *row = tile + (size_t)i * 6 * TB;
         double b[6][4];
 #pragma unroll
-        for (int c = 0; c < 6; ++c)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const d2v u = __builtin_nontemporal_load(
-                    reinterpret_cast<const d2v *>(row + c * TB + 32 * h));
-                b[c][2 * h] = u.x;
-                b[c][2 * h + 1] = u.y;
-            }
+        for (int c = 0; c < 6; ++c) P6<T>::load(row + c * TB, q, b[c]);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             double r0 = 0.0, r1 = 0.0, r2 = 0.0;
@@ -268,7 +168,7 @@ __global__ __launch_bounds__(256) void k_symv6(int N, int n3, int n3pad, int rhs
                 double s = cacc[j][e][c];
                 s += __shfl_xor(s, 16);
                 s += __shfl_xor(s, 32);
-                if (g == 0) scol[w][j][3 * p6col(q, e) + c] = s;
+                if (g == 0) scol[w][j][3 * P6<T>::col(q, e) + c] = s;
             }
     __syncthreads();
     for (int e = threadIdx.x; e < M * TS; e += blockDim.x) {
@@ -292,14 +192,9 @@ static void symv_launch(const Ctx &c, const T *tiles, const double *v, int j0, h
     const int nkb = (c.nk + 255) / 256;
     const int nsf = c.nsfc * nkb;
     const size_t lds = symv_lds<T, M>(c);
-    if constexpr (sizeof(T) == sizeof(double))   // packed FP64 tiles
-        hipLaunchKernelGGL((k_symv6<M>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N,
-                           c.n3, c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab,
-                           c.sfpart, c.tile_ij, tiles, v, c.part);
-    else
-        hipLaunchKernelGGL((k_symv<T, M>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N,
-                           c.n3, c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab,
-                           c.sfpart, c.tile_ij, tiles, v, c.part);
+    hipLaunchKernelGGL((k_symv6<T, M>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N, c.n3,
+                       c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab, c.sfpart,
+                       c.tile_ij, tiles, v, c.part);
 }
 
 template <typename T>
@@ -314,9 +209,9 @@ static void symv_group(const Ctx &c, const T *tiles, const double *v, int j0, in
 void launch_symv(const Ctx &c, int prec, const double *v, int j0, int mc, hipStream_t s)
 {
     if (prec == RPY_PREC_F32)
-        symv_group<float>(c, c.d32, v, j0, mc, s);
+        symv_group<float>(c, c.p32, v, j0, mc, s);
     else if (prec == RPY_PREC_BF16)
-        symv_group<uint16_t>(c, c.d16, v, j0, mc, s);
+        symv_group<uint16_t>(c, c.p16, v, j0, mc, s);
     else
         symv_group<double>(c, c.d64, v, j0, mc, s);
 }

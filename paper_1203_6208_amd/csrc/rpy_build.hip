@@ -92,7 +92,8 @@ __device__ inline uint16_t to_bf16(double d)
 // order (the operations of pair_block, so the block is bit-identical).  A
 // step in which some pair has three or more shifts on an axis falls back to
 // pair_block.  The block goes to the packed FP64 planes; LOWP also writes
-// the FP32 (1) or BF16 (2) row-major tile.
+// packed FP32 (1) or BF16 (2) planes and, with rowmajor, the row-major tile
+// of the block product.
 constexpr int IMG_SLOTS = 8;
 constexpr int IMG_QCAP = 128;
 
@@ -107,8 +108,10 @@ template <int LOWP>
 __global__ __launch_bounds__(256) void k_build_tiles(int N, const int2 *__restrict__ tile_ij,
                                                      const double *__restrict__ rt, PairConst p,
                                                      double *__restrict__ d64,
+                                                     float *__restrict__ p32,
+                                                     uint16_t *__restrict__ p16,
                                                      float *__restrict__ d32,
-                                                     uint16_t *__restrict__ d16)
+                                                     uint16_t *__restrict__ d16, int rowmajor)
 {
     __shared__ double sI[TS], sJ[TS];
     __shared__ double q_r2[4][IMG_QCAP];
@@ -205,11 +208,15 @@ __global__ __launch_bounds__(256) void k_build_tiles(int N, const int2 *__restri
             }
             wave_sync();   // res and the queue are reused by the next step
         }
-        // packed FP64 planes: a wave writes 512 contiguous bytes per plane
+        // packed planes: a wave writes 512 contiguous bytes per FP64 plane
         const size_t o6 = (size_t)t * TILE6 + (size_t)bi * 6 * TB + bj;
 #pragma unroll
-        for (int e = 0; e < 6; ++e) d64[o6 + (size_t)e * TB] = b[e];
-        if (LOWP) {
+        for (int e = 0; e < 6; ++e) {
+            d64[o6 + (size_t)e * TB] = b[e];
+            if (LOWP == 1) p32[o6 + (size_t)e * TB] = (float)b[e];
+            if (LOWP == 2) p16[o6 + (size_t)e * TB] = to_bf16(b[e]);
+        }
+        if (LOWP && rowmajor) {
             const double v[9] = {b[0], b[1], b[2], b[1], b[3], b[4], b[2], b[4], b[5]};
             const size_t o = (size_t)t * TILE_ELEMS + (size_t)(3 * bi) * TS + 3 * bj;
 #pragma unroll
@@ -233,13 +240,13 @@ void launch_build_tiles(const Ctx &c, hipStream_t s)
     const dim3 g(c.ntiles), b(256);
     if (c.lowp == RPY_PREC_F32)
         hipLaunchKernelGGL(k_build_tiles<1>, g, b, 0, s, c.N, c.tile_ij, c.rt, c.pc, c.d64,
-                           c.d32, c.d16);
+                           c.p32, c.p16, c.d32, c.d16, c.block ? 1 : 0);
     else if (c.lowp == RPY_PREC_BF16)
         hipLaunchKernelGGL(k_build_tiles<2>, g, b, 0, s, c.N, c.tile_ij, c.rt, c.pc, c.d64,
-                           c.d32, c.d16);
+                           c.p32, c.p16, c.d32, c.d16, c.block ? 1 : 0);
     else
         hipLaunchKernelGGL(k_build_tiles<0>, g, b, 0, s, c.N, c.tile_ij, c.rt, c.pc, c.d64,
-                           c.d32, c.d16);
+                           c.p32, c.p16, c.d32, c.d16, c.block ? 1 : 0);
 }
 
 // Dense row-major copy of the stored FP64 real-space matrix (test helper).

@@ -202,7 +202,7 @@ extern "C" void rpy_destroy(rpy_ctx *x)
     (void)hipDeviceSynchronize();
     Ctx &c = x->c;
     void *bufs[] = {c.rt, c.rt_ev, c.eph, c.etab, c.kvec, c.kcoef, c.tile_ij, c.d64, c.d32,
-                    c.d16, c.part, c.xpk, c.ypart,
+                    c.d16, c.p32, c.p16, c.part, c.xpk, c.ypart,
                     c.vpk, c.part32, c.tkm,
                     c.sfpart, c.tk, c.sfr, c.work, c.scal, c.red, c.flags, c.cell_start, c.lanc,
                     c.vhist, c.wgrad, c.xy, c.gpart, c.gk, c.mur,
@@ -304,8 +304,10 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
                    (rc = dalloc(&c.lma_beads, (size_t)c.N)) ||
                    (rc = dalloc(&c.rt_sorted, nv)) ||
                    (rc = dalloc(&c.v_sorted, (size_t)c.rhs_cap * nv)))) ||
-        (c.lowp == RPY_PREC_F32 && (rc = dalloc(&c.d32, te))) ||
-        (c.lowp == RPY_PREC_BF16 && (rc = dalloc(&c.d16, te))) ||
+        (c.lowp == RPY_PREC_F32 && (rc = dalloc(&c.p32, te6))) ||
+        (c.lowp == RPY_PREC_BF16 && (rc = dalloc(&c.p16, te6))) ||
+        (c.block && c.lowp == RPY_PREC_F32 && (rc = dalloc(&c.d32, te))) ||
+        (c.block && c.lowp == RPY_PREC_BF16 && (rc = dalloc(&c.d16, te))) ||
         (rc = dalloc(&c.part, (size_t)c.nslot * c.rhs_cap * c.n3pad)) ||
         (c.block && ((rc = dalloc(reinterpret_cast<uint32_t **>(&c.xpk),
                                   (size_t)c.n3pad * BLOCK_RHS)) ||

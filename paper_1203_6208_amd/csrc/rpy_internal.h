@@ -8,8 +8,9 @@
 //   (each pair term is a I + b rhat rhat), so a tile keeps 6 entries per bead
 //   pair, as planes: d64[t][i][c][j] (TILE6 doubles), i, j the beads of I and
 //   J within the tile, c = xx, xy, xz, yy, yz, zz.
-//   FP32 / BF16 tiles (d32, d16): TS x TS row-major (TILE_ELEMS), the operand
-//   layout of the matrix-core block product.
+//   FP32 / BF16 tiles: packed the same way (p32, p16) for the products of up
+//   to 4 vectors, and, when the matrix-core block product is enabled, also
+//   TS x TS row-major (d32, d16, TILE_ELEMS), its operand layout.
 // A product y = D.x reads every stored tile once and produces both A_IJ x_J
 // (rows of I) and A_IJ^T x_I (rows of J); the partial results land in
 // part[K][j][row] so that row r of y is the fixed-order sum over K of
@@ -380,8 +381,10 @@ struct Ctx {
     KCoef *kcoef = nullptr;      // [nk]
     int2 *tile_ij = nullptr;     // [ntiles]
     double *d64 = nullptr;       // [ntiles][TILE6], packed symmetric blocks
-    float *d32 = nullptr;
+    float *d32 = nullptr;        // [ntiles][TILE_ELEMS] row-major, block products only
     uint16_t *d16 = nullptr;
+    float *p32 = nullptr;        // [ntiles][TILE6] packed planes, lowp FP32
+    uint16_t *p16 = nullptr;     // [ntiles][TILE6] packed planes, lowp BF16
     double *part = nullptr;      // [nbt][rhs_cap][n3pad] tile-column partials
     // block products (FP32 / BF16 tiles, up to 16 vectors on the matrix cores)
     bool block = false;          // enabled: lowp tiles and max_rhs >= BLOCK_MIN_RHS
