@@ -42,8 +42,8 @@ void launch_lma_build(const Ctx &c, hipStream_t s)
 // (2a)^2, the test add_image applies to that image, or k = h); the
 // candidates that pass are appended to a per-wave LDS queue (ballot +
 // prefix count), and whenever 64 are queued every lane evaluates one of
-// them: the 3 x 3 pair block summed over its images (pair_block; the self
-// term for k = h) times v_k.  Only about a sixth of the stencil is within
+// them: the 3 x 3 pair block of its minimum image (the self term for k = h)
+// times v_k.  Only about a sixth of the stencil is within
 // reach, so the expensive pair terms run on full waves.  The lanes are
 // combined by a fixed xor tree; the result goes to part slot 0 at the bead's
 // own index.  Every step of the walk is deterministic.
@@ -57,15 +57,27 @@ __device__ inline void lma_wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The block of one queued pair.  With max(r_c, 2a) < L/3 only the minimum
+// image of a pair can be within reach (any other is farther than 2L/3), and
+// a bead has no image of itself within reach: the block is add_image of the
+// minimum image (the term pair_block would sum), or the self term.
 template <int M>
 __device__ inline void lma_pair(double hx, double hy, double hz, int k, int h,
                                 const PairConst &p, const double *__restrict__ rt_s,
                                 const double *__restrict__ vs, int n3, int j0,
                                 double acc[M][3])
 {
-    double b[6];
-    pair_block(hx - rt_s[3 * (size_t)k], hy - rt_s[3 * (size_t)k + 1],
-               hz - rt_s[3 * (size_t)k + 2], k == h, p, b);
+    double b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (k == h) {
+        b[0] = b[3] = b[5] = p.self_coeff;
+    } else {
+        double dx = hx - rt_s[3 * (size_t)k], dy = hy - rt_s[3 * (size_t)k + 1],
+               dz = hz - rt_s[3 * (size_t)k + 2];
+        dx -= p.L * rint(dx * p.invL);
+        dy -= p.L * rint(dy * p.invL);
+        dz -= p.L * rint(dz * p.invL);
+        add_image(dx, dy, dz, p, b);
+    }
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         const double *v = vs + (size_t)(j0 + j) * n3 + 3 * (size_t)k;
@@ -76,8 +88,11 @@ __device__ inline void lma_pair(double hx, double hy, double hz, int k, int h,
     }
 }
 
+// Four waves per SIMD (at most 128 VGPRs; the compiler spills a few values
+// to scratch) ran the N = 32000 product 1.3x faster than the three that 169
+// VGPRs allow; five or six waves were slower.
 template <int M>
-__global__ __launch_bounds__(256) void k_lma_real(int N, int n3, int n3pad, int rhs_cap, int j0,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_lma_real(int N, int n3, int n3pad, int rhs_cap, int j0,
                                                   double L, int nc, PairConst p,
                                                   const int *__restrict__ start,
                                                   const int *__restrict__ beads,
