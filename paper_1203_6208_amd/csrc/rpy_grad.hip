@@ -189,9 +189,12 @@ void launch_grad_real(const Ctx &c, hipStream_t s)
 }
 
 // ------------------------------------------------ reciprocal-space gradient
-// Structure-factor partials of nv (even) vectors v[0 .. nv-1] (stride 3N),
-// four at a time and a last pair (the phase tables stay in LDS): sfpart as in
-// a forward product, for the reduction of launch_sf_reduce.
+// Structure-factor partials of nv (even) vectors v[0 .. nv-1] (stride 3N):
+// workgroup (chunk x wave-vector block, y) takes the vectors 4 y .. 4 y + 3
+// (a last pair when nv is not a multiple of 4); sfpart as in a forward
+// product, for the reduction of launch_sf_reduce.  One group of vectors per
+// workgroup keeps 4x more workgroups busy than looping over the groups
+// (at N = 2000 the loop ran 96 workgroups on 256 compute units).
 __global__ __launch_bounds__(256) void k_grad_sf(int N, int n3, int nk, int nmax, int rhs_cap,
                                                  int nkb, int nv, const KVec *__restrict__ kvec,
                                                  const double2 *__restrict__ etab,
@@ -199,26 +202,21 @@ __global__ __launch_bounds__(256) void k_grad_sf(int N, int n3, int nk, int nmax
                                                  double *__restrict__ sfpart)
 {
     extern __shared__ double smem[];
-    for (int j0 = 0; j0 < nv;) {
-        if (j0 > 0) __syncthreads();   // the vector slots are rewritten
-        if (nv - j0 >= 4) {
-            sf_partial_block<4>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
-                                sfpart, smem, j0 == 0);
-            j0 += 4;
-        } else {
-            sf_partial_block<2>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
-                                sfpart, smem, j0 == 0);
-            j0 += 2;
-        }
-    }
+    const int j0 = 4 * blockIdx.y;
+    if (nv - j0 >= 4)
+        sf_partial_block<4>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v, sfpart,
+                            smem);
+    else
+        sf_partial_block<2>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v, sfpart,
+                            smem);
 }
 
 void launch_grad_sf(const Ctx &c, const double *v, int nv, hipStream_t s)
 {
     const int nkb = (c.nk + 255) / 256;
     const size_t lds = sizeof(double) * (size_t)(2 * SF_BEADS * 3 * (c.nmax + 1) + SF_BEADS * 4 * 3);
-    hipLaunchKernelGGL(k_grad_sf, dim3(c.nsfc * nkb), dim3(256), lds, s, c.N, c.n3, c.nk, c.nmax,
-                       c.rhs_cap, nkb, nv, c.kvec, c.etab, v, c.sfpart);
+    hipLaunchKernelGGL(k_grad_sf, dim3(c.nsfc * nkb, (nv + 3) / 4), dim3(256), lds, s, c.N, c.n3,
+                       c.nk, c.nmax, c.rhs_cap, nkb, nv, c.kvec, c.etab, v, c.sfpart);
 }
 
 // Per bead l: the reciprocal term above for the nq pairs whose T_k are in
