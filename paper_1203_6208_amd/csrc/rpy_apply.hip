@@ -286,7 +286,8 @@ void launch_sf_reduce(const Ctx &c, int m, hipStream_t s)
 //   y_u = sum_K part[K][j][3 nu + c] + sum_k cos(k.r_nu) Tc_k + sin(k.r_nu) Ts_k
 // with k.r_nu = 2 pi n.s_nu.  The wave vectors are sorted by (n_x, n_y) and
 // then n_z, so inside a run of equal (n_x, n_y) the phase advances by
-// e^{i 2 pi s_z}.  Slices are combined in a fixed order (xor tree over the
+// e^{i 2 pi s_z}; a run starts from the product of the bead's phase-table
+// entries (staged in LDS), with no transcendental call.  Slices are combined in a fixed order (xor tree over the
 // sub-slices, then the 16 waves in LDS), then the epilogue of `mode`:
 //   EPI_APPLY      out = y
 //   EPI_CHEB_FIRST V_1 = ya y - yb V_0, acc = (c_0/2) V_0 + c_1 V_1, dv = y
@@ -304,27 +305,28 @@ constexpr int EPI_SLICES = 64;
 constexpr int EPI_STAGE_PER = 6;
 template <int M>
 __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, int nbt, int nk,
-                                                     int rhs_cap, int j0, int staged,
+                                                     int nmax, int rhs_cap, int j0, int staged,
                                                      const KVec *kvec,
-                                                     const double *__restrict__ sfr,
+                                                     const double2 *__restrict__ etab,
                                                      const double *__restrict__ part,
                                                      const double *tk_g, EpiArgs f)
 {
     __shared__ double red[16][3][EPI_BEADS];
     extern __shared__ double lds[];
-    const KVec *kv_s = staged ? reinterpret_cast<const KVec *>(lds) : kvec;
-    const double *tk_s = staged ? lds + 2 * (nk + 1) : tk_g + (size_t)j0 * 6;
+    const int nm1 = nmax + 1;
+    double2 *tabs = reinterpret_cast<double2 *>(lds);          // [EPI_BEADS][3 nm1]
+    double *stage = lds + 2 * EPI_BEADS * 3 * nm1;
+    const KVec *kv_s = staged ? reinterpret_cast<const KVec *>(stage) : kvec;
+    const double *tk_s = staged ? stage + 2 * (nk + 1) : tk_g + (size_t)j0 * 6;
     const int tk_ld = staged ? 6 * M : 6 * rhs_cap;
     // Loads that do not depend on the staged tables are issued first: the
-    // bead's fractional position, its tile-column partials and, for the 3
-    // EPI_BEADS threads that apply the epilogue, the recurrence operands.
+    // bead's tile-column partials and, for the 3 EPI_BEADS threads that apply
+    // the epilogue, the recurrence operands.
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int bl = lane & 15, sub = lane >> 4;
     const int u = 4 * w + sub;
     const int nu = blockIdx.x * EPI_BEADS + bl;
     const bool live = nu < N;
-    const double sx = live ? sfr[3 * nu] : 0.0, sy = live ? sfr[3 * nu + 1] : 0.0,
-                 sz = live ? sfr[3 * nu + 2] : 0.0;
     double y[M][3];
 #pragma unroll
     for (int j = 0; j < M; ++j) y[j][0] = y[j][1] = y[j][2] = 0.0;
@@ -351,9 +353,15 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
                                                                                     : 0.0;
         pa[j] = eth && (f.mode == EPI_CHEB_NEXT || f.mode == EPI_ADJ) ? f.acc[o] : 0.0;
     }
+    // the phase tables e^{i 2 pi j s_a} of the workgroup's beads (zero past N)
+    const int ntab = EPI_BEADS * 3 * nm1;
+    const size_t tab0 = (size_t)blockIdx.x * EPI_BEADS * 3 * nm1;
+    const int nlive = min(EPI_BEADS, N - (int)blockIdx.x * EPI_BEADS) * 3 * nm1;
+    for (int e = threadIdx.x; e < ntab; e += blockDim.x)
+        tabs[e] = e < nlive ? etab[tab0 + e] : make_double2(0.0, 0.0);
     if (staged) {
-        KVec *kd = reinterpret_cast<KVec *>(lds);
-        double *td = lds + 2 * (nk + 1);
+        KVec *kd = reinterpret_cast<KVec *>(stage);
+        double *td = stage + 2 * (nk + 1);
         const int ntk = nk * 6 * M;
         const KVec kv0 = kvec[min((int)threadIdx.x, nk - 1)];
         double tv[EPI_STAGE_PER];
@@ -366,11 +374,12 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
         kd[min((int)threadIdx.x, nk)] = kv0;
 #pragma unroll
         for (int i = 0; i < EPI_STAGE_PER; ++i) td[min((int)threadIdx.x + 1024 * i, ntk)] = tv[i];
-        __syncthreads();
     }
+    __syncthreads();
     const int klo = (int)((long)u * nk / EPI_SLICES), khi = (int)((long)(u + 1) * nk / EPI_SLICES);
-    double ezr, ezi;
-    sincospi(2.0 * sz, &ezi, &ezr);
+    const double2 *tb = tabs + bl * 3 * nm1;
+    const double2 ez = nm1 > 1 ? tb[2 * nm1 + 1] : make_double2(1.0, 0.0);   // e^{i 2 pi s_z}
+    const double ezr = ez.x, ezi = ez.y;
     double cs = 1.0, sn = 0.0;
     int px = -(1 << 30), py = 0, pz = 0;
     for (int k = klo; k < khi; ++k) {
@@ -379,8 +388,10 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
             const double c2 = cs * ezr - sn * ezi;
             sn = cs * ezi + sn * ezr;
             cs = c2;
-        } else {
-            sincospi(2.0 * (kv.nx * sx + kv.ny * sy + kv.nz * sz), &sn, &cs);
+        } else {   // a run start: the phase from the bead's tables
+            const double2 e = kphase(kv, tb, nm1);
+            cs = e.x;
+            sn = e.y;
         }
         px = kv.nx;
         py = kv.ny;
@@ -432,12 +443,14 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
 void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
 {
     const dim3 g((c.N + EPI_BEADS - 1) / EPI_BEADS), b(1024);
+    const size_t tabs = sizeof(double) * 2 * EPI_BEADS * 3 * (size_t)(c.nmax + 1);
     RPY_RHS_GROUPS(f.m, {
         const size_t lds = sizeof(double) * ((size_t)c.nk * (2 + 6 * MC) + 3);
         const int staged = c.nk <= 1024 && (size_t)c.nk * 6 * MC <= 1024 * EPI_STAGE_PER &&
-                           lds <= 48 * 1024;
-        hipLaunchKernelGGL(k_kspace_epi<MC>, g, b, staged ? lds : 0, s, c.N, c.n3, c.n3pad, c.nslot,
-                           c.nk, c.rhs_cap, j0, staged, c.kvec, c.sfr, c.part, c.tk, f);
+                           tabs + lds <= 48 * 1024;
+        hipLaunchKernelGGL(k_kspace_epi<MC>, g, b, tabs + (staged ? lds : 0), s, c.N, c.n3,
+                           c.n3pad, c.nslot, c.nk, c.nmax, c.rhs_cap, j0, staged, c.kvec, c.etab,
+                           c.part, c.tk, f);
     });
 }
 
