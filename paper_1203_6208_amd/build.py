@@ -19,11 +19,12 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
-# Per-file additions.  The block-product kernels keep their MFMA accumulators
-# in ordinary VGPRs: with the default heuristic the loop-carried FP64
-# accumulators are copied to and from AGPRs around every MFMA batch.
+# Per-file additions.  The block-product and W-tile kernels keep their MFMA
+# accumulators in ordinary VGPRs: with the default heuristic the loop-carried
+# FP64 accumulators are copied to and from AGPRs around every MFMA batch.
 FILE_FLAGS = {
     "rpy_block.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "rpy_grad.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 
