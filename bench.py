@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on 1 GiB device copies in the same process).  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "fa59f88641a546e0b85d5c6ff702951127f2c6d9f978e9e0bc4e56c495892043",
+TRAFFIC = {"src_sha256": "d20501085a8b8da6cd491876b549437c44e6c393ee7b8aa13b1c3ebd89c5ed54",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 409642667}
+           "bytes_per_launch": 409640538}
 TRAFFIC_BLOCK = {"src_sha256": "5abfa89c82dff85286e5a56da84134a6e6101d14931229953277db0b2d79748c",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
                  "bytes_per_launch": {"f32": 312316961 + 48771072, "bf16": 159672889 + 48771072}}
