@@ -77,8 +77,10 @@ template <> struct P6<uint16_t> {
 // accumulates B x_i for its columns, and the 4 row groups and 4 waves are
 // combined in a fixed order -> part[I][j][rows of J].  Diagonal tiles hold
 // both (i, j) and (j, i) and take row sums only.
+// Four vectors need 274 VGPRs, one wave per SIMD; capped at 256 (two waves,
+// a few spills) the FP64 launch takes 132 us instead of 176 us at N = 4000.
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_symv6(int N, int n3, int n3pad, int rhs_cap, int j0,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M == 4 ? 2 : 1, 8))) void k_symv6(int N, int n3, int n3pad, int rhs_cap, int j0,
                                                int nsf, int nkb, int nk, int nmax,
                                                const KVec *__restrict__ kvec,
                                                const double2 *__restrict__ etab,
