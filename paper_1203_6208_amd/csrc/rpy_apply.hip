@@ -29,24 +29,35 @@ template <typename A> __device__ inline A sum16(A x)
 // (BF16) non-temporal loads that are contiguous across the row group.
 template <typename T> struct P6;
 template <> struct P6<double> {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    struct raw_t {
+        d2v u, v;
+    };
+    static constexpr bool hoist = false;
     __device__ static int col(int q, int e) { return 32 * (e >> 1) + 2 * q + (e & 1); }
-    __device__ static void load(const double *row, int q, double a[4])
+    __device__ static raw_t raw(const double *row, int q)
     {
-        typedef double d2v __attribute__((ext_vector_type(2)));
-        const d2v u = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 2 * q));
-        const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 32 + 2 * q));
-        a[0] = u.x;
-        a[1] = u.y;
-        a[2] = v.x;
-        a[3] = v.y;
+        return {__builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 2 * q)),
+                __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 32 + 2 * q))};
+    }
+    __device__ static void cvt(const raw_t &r, double a[4])
+    {
+        a[0] = r.u.x;
+        a[1] = r.u.y;
+        a[2] = r.v.x;
+        a[3] = r.v.y;
     }
 };
 template <> struct P6<float> {
+    typedef float raw_t __attribute__((ext_vector_type(4)));
+    static constexpr bool hoist = false;
     __device__ static int col(int q, int e) { return 4 * q + e; }
-    __device__ static void load(const float *row, int q, double a[4])
+    __device__ static raw_t raw(const float *row, int q)
     {
-        typedef float f4v __attribute__((ext_vector_type(4)));
-        const f4v u = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(row + 4 * q));
+        return __builtin_nontemporal_load(reinterpret_cast<const raw_t *>(row + 4 * q));
+    }
+    __device__ static void cvt(const raw_t &u, double a[4])
+    {
         a[0] = u.x;
         a[1] = u.y;
         a[2] = u.z;
@@ -54,11 +65,15 @@ template <> struct P6<float> {
     }
 };
 template <> struct P6<uint16_t> {
+    typedef uint32_t raw_t __attribute__((ext_vector_type(2)));
+    static constexpr bool hoist = true;
     __device__ static int col(int q, int e) { return 4 * q + e; }
-    __device__ static void load(const uint16_t *row, int q, double a[4])
+    __device__ static raw_t raw(const uint16_t *row, int q)
     {
-        typedef uint32_t u2v __attribute__((ext_vector_type(2)));
-        const u2v u = __builtin_nontemporal_load(reinterpret_cast<const u2v *>(row + 4 * q));
+        return __builtin_nontemporal_load(reinterpret_cast<const raw_t *>(row + 4 * q));
+    }
+    __device__ static void cvt(const raw_t &u, double a[4])
+    {
         a[0] = __uint_as_float(u.x << 16);
         a[1] = __uint_as_float(u.x & 0xFFFF0000u);
         a[2] = __uint_as_float(u.y << 16);
@@ -125,13 +140,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M == 4 ? 2 
     __syncthreads();
     const T *tile = tiles + (size_t)t * TILE6;
     const bool offd = I != J;
+    // BF16 rows are small: all four of a lane's rows are loaded before any
+    // arithmetic (more bytes in flight per wave; 34.1 against 37.4 us at
+    // N = 4000); FP64 and FP32 rows are loaded one at a time (hoisting them
+    // costs occupancy: FP32 46.9 against 43.8 us)
+    typename P6<T>::raw_t rw[TB / 16][6];
+    if constexpr (P6<T>::hoist) {
+#pragma unroll
+        for (int it = 0; it < TB / 16; ++it)
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+                rw[it][c] = P6<T>::raw(tile + (size_t)(16 * it + 4 * w + g) * 6 * TB + c * TB, q);
+    }
 #pragma unroll
     for (int it = 0; it < TB / 16; ++it) {
         const int i = 16 * it + 4 * w + g;
         const T *row = tile + (size_t)i * 6 * TB;
         double b[6][4];
+        if constexpr (!P6<T>::hoist) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) P6<T>::load(row + c * TB, q, b[c]);
+            for (int c = 0; c < 6; ++c) rw[it][c] = P6<T>::raw(row + c * TB, q);
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) P6<T>::cvt(rw[it][c], b[c]);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             double r0 = 0.0, r1 = 0.0, r2 = 0.0;
