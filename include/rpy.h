@@ -72,11 +72,15 @@ typedef struct {
                           chebyshev_sqrt_adaptive and rpy_u_vjp (0 disables
                           that call; at most 512): cheb_keep x max(max_rhs, 2)
                           x 3N doubles */
-    int32_t grad;      /* 1: also hold the buffers of rpy_u_vjp (a second
-                          stored-tile matrix and 2 cheb_keep + 4 vectors of
+    int32_t grad;      /* 1: also hold the buffers of rpy_u_vjp (a W
+                          matrix on the upper tiles, row-major, about
+                          9N^2/2 doubles, and 2 cheb_keep + 4 vectors of
                           3N); needs cheb_keep >= 2 and lma = 0.  0: none */
     int32_t lma;       /* 0: high-memory form, the real-space part of D is
-                          stored (symmetric tiles, 3N(3N+1)/2 doubles).
+                          stored (upper tiles, the 6 distinct entries of
+                          each symmetric 3 x 3 bead-pair block: about
+                          3N(N+1) doubles; the row-major upper tiles of the
+                          block product, when enabled, come on top).
                           1: low-memory form (section "Low memory
                           algorithm"): nothing of size N^2 is stored; every
                           product recomputes the real-space sum over a cell
