@@ -34,17 +34,17 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on 1 GiB device copies in the same process).  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "d20501085a8b8da6cd491876b549437c44e6c393ee7b8aa13b1c3ebd89c5ed54",
+TRAFFIC = {"src_sha256": "18116b5c2b47a16d403fb7753e0cee14a5c0ce993981648af782698808ad8750",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 409640538}
+           "bytes_per_launch": 409641527}
 TRAFFIC_BLOCK = {"src_sha256": "5abfa89c82dff85286e5a56da84134a6e6101d14931229953277db0b2d79748c",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
                  "bytes_per_launch": {"f32": 312316961 + 48771072, "bf16": 159672889 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "5d8414f9a8ba7e8e72e61241008ea028dd69bba96f7614f5cd460e18d6d61798",
+TRAFFIC_BATCH = {"src_sha256": "30e194b06006da89d634e5911ef9eeaa97bf3fbff545e36fbc1b28485bc89b49",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4931225421}
+                 "bytes_per_launch": 4931230847}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 
