@@ -106,7 +106,7 @@ def profile_pass(ctx, rpy, tpos, bp, steps, torch):
     out = {}
     names = {rpy.PROF_SYMV: "tile_product", rpy.PROF_BUILD: "tile_build",
              rpy.PROF_KSPACE: "sf_reduce", rpy.PROF_EPI: "kspace_epilogue",
-             rpy.PROF_OTHER: "forces_wrap"}
+             rpy.PROF_OTHER: "forces_noise_side_stream"}
     for k, nm in names.items():
         n, ms = rpy.rpy_profile_read(ctx.handle, k)
         out[nm] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / max(n, 1)}

@@ -199,7 +199,11 @@ int chebyshev_sqrt_adaptive(rpy_ctx *c, const double *dw, double *out, int m,
  * pos: device [N][3], updated in place.  drift, noise, e_f: optional device
  * outputs ([N][3] D.F, [N][3] dS, [1] E_f).  Bounds follow bounds_rule.
  * prec selects the arithmetic of the Chebyshev products; the drift and the
- * bounds always use FP64. */
+ * bounds always use FP64.  The forces and the device noise run on a second
+ * stream owned by the context, forked from `stream` after the wrap and
+ * joined back before the drift product (event record / wait, no host
+ * synchronisation), so that they overlap the tile build; everything the call
+ * enqueues is ordered before later work on `stream`. */
 typedef struct {
     double dt;
     double ev_zstar;    /* 0 disables excluded volume */
@@ -305,7 +309,8 @@ enum {
     RPY_PROF_BUILD = 1,     /* real-space tile build */
     RPY_PROF_KSPACE = 2,    /* structure-factor reduction */
     RPY_PROF_EPI = 3,       /* reciprocal back-projection + recurrence epilogue */
-    RPY_PROF_OTHER = 4,     /* forces, noise, coefficients, update */
+    RPY_PROF_OTHER = 4,     /* bd_step's forces + noise (on an internal
+                               second stream, beside the tile build) */
     RPY_PROF_KINDS = 5
 };
 int rpy_profile_enable(rpy_ctx *c, int cap);

@@ -32,6 +32,11 @@ struct rpy_ctx {
     double *acc = nullptr;    // [max_rhs][3N] scratch accumulator
     // the phase matrix c.eph is valid for wrap generation eph_gen
     uint64_t wrap_gen = 1, eph_gen = 0;
+    // bd_step runs the forces and the noise on a second stream (default
+    // priority) beside the tile build: fork after the wrap, join before the
+    // drift product
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 static thread_local char g_err[256];
@@ -210,6 +215,9 @@ extern "C" void rpy_destroy(rpy_ctx *x)
                     c.cell_beads};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
+    if (x->fork) (void)hipEventDestroy(x->fork);
+    if (x->join) (void)hipEventDestroy(x->join);
+    if (x->side) (void)hipStreamDestroy(x->side);
     for (int k = 0; k < RPY_PROF_KINDS; ++k) {
         for (int i = 0; i < 2 * x->prof.alloc; ++i) (void)hipEventDestroy(x->prof.ev[k][i]);
         delete[] x->prof.ev[k];
@@ -348,6 +356,13 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
         (te6 && (e = hipMemset(c.d64, 0, te6 * sizeof(double)))) ||
         (c.block && (e = hipMemset(c.tkm, 0, (size_t)c.nk4 * 6 * BLOCK_RHS * sizeof(double))))) {
         rc = hip_fail(e, "rpy_create upload");
+        rpy_destroy(x);
+        return rc;
+    }
+    if ((e = hipStreamCreateWithFlags(&x->side, hipStreamNonBlocking)) ||
+        (e = hipEventCreateWithFlags(&x->fork, hipEventDisableTiming)) ||
+        (e = hipEventCreateWithFlags(&x->join, hipEventDisableTiming))) {
+        rc = hip_fail(e, "rpy_create stream");
         rpy_destroy(x);
         return rc;
     }
@@ -931,16 +946,26 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
     if (rc) return rc;
     hipStream_t s = S(stream);
     const size_t nv = (size_t)c.n3;
+    launch_wrap_tables(c, pos, s);
+    ++x->wrap_gen;
+    // forces and noise on the side stream, beside the build
+    HIP_TRY(hipEventRecord(x->fork, s));
+    HIP_TRY(hipStreamWaitEvent(x->side, x->fork, 0));
+    const double *w = dw;
     {
-        ProfScope ps(x, RPY_PROF_OTHER, s);
-        launch_wrap_tables(c, pos, s);
-        ++x->wrap_gen;
-        forces(x, pos, c.rt, bp->ev_zstar, bp->ev_dstar, bp->ev_rcut, x->F, s);
+        ProfScope ps(x, RPY_PROF_OTHER, x->side);
+        forces(x, pos, c.rt, bp->ev_zstar, bp->ev_dstar, bp->ev_rcut, x->F, x->side);
+        if (!w) {
+            launch_noise(x->dW, (int64_t)nv, seed, step, bp->dt, x->side);
+            w = x->dW;
+        }
     }
+    HIP_TRY(hipEventRecord(x->join, x->side));
     {
         ProfScope ps(x, RPY_PROF_BUILD, s);
         launch_build_tiles(c, s);
     }
+    HIP_TRY(hipStreamWaitEvent(s, x->join, 0));
     EpiArgs f{};
     f.mode = EPI_APPLY;
     f.vout = x->Y;
@@ -953,11 +978,6 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
         product(x, x->F, 1, RPY_PREC_F64, f, s);
         launch_cheb_coeffs(c, bp->n_cheb, RPY_BOUNDS_EXPLICIT, 0, bp->d_min, bp->d_max, nullptr,
                            s);
-    }
-    const double *w = dw;
-    if (!w) {
-        launch_noise(x->dW, (int64_t)nv, seed, step, bp->dt, s);
-        w = x->dW;
     }
     cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s);
     if (e_f) launch_sqrt_error(c, 1, w, x->ddw, x->dS, e_f, s);
