@@ -104,9 +104,9 @@ def profile_pass(ctx, rpy, tpos, bp, steps, torch):
         ctx.step(tpos, bp, seed=3, step=i)
     torch.cuda.synchronize()
     out = {}
-    names = {rpy.PROF_SYMV: "tile_product", rpy.PROF_BUILD: "tile_build",
-             rpy.PROF_KSPACE: "sf_reduce", rpy.PROF_EPI: "kspace_epilogue",
-             rpy.PROF_OTHER: "forces_noise_side_stream"}
+    names = {rpy.PROF_SYMV: "tile_product", rpy.PROF_SYMV_MULTI: "tile_product_2_to_4_vectors",
+             rpy.PROF_BUILD: "tile_build", rpy.PROF_KSPACE: "sf_reduce",
+             rpy.PROF_EPI: "kspace_epilogue", rpy.PROF_OTHER: "forces_noise_side_stream"}
     for k, nm in names.items():
         n, ms = rpy.rpy_profile_read(ctx.handle, k)
         out[nm] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / max(n, 1)}
@@ -174,9 +174,10 @@ def time_block(w, prec, reps, torch, rpy):
     torch.cuda.synchronize()
     nprod = w.nch - 1
     stage = {}
-    for kind, nm in ((rpy.PROF_SYMV, "tile_product"), (rpy.PROF_KSPACE, "structure_factors"),
-                     (rpy.PROF_EPI, "back_projection_epilogue")):
-        n, ms = rpy.rpy_profile_read(ctx.handle, kind)
+    for kinds, nm in (((rpy.PROF_SYMV, rpy.PROF_SYMV_MULTI), "tile_product"),
+                      ((rpy.PROF_KSPACE,), "structure_factors"),
+                      ((rpy.PROF_EPI,), "back_projection_epilogue")):
+        ms = sum(rpy.rpy_profile_read(ctx.handle, k)[1] for k in kinds)
         stage[nm + "_us"] = 1e3 * ms / nprod
     rpy.rpy_profile_enable(ctx.handle, 0)
     gbs = tile_bytes(w.n, prec, packed=prec == "f64") / (stage["tile_product_us"] * 1e-6) / 1e9

@@ -305,13 +305,16 @@ int rpy_host_pair_block(const rpy_params *p, const double *d, int self,
  * `kind` (RPY_PROF_*) and their summed duration in milliseconds (host
  * outputs), and resets that class.  Launches beyond cap are not recorded. */
 enum {
-    RPY_PROF_SYMV = 0,      /* tile product (+ structure-factor partials) */
+    RPY_PROF_SYMV = 0,      /* tile product of one vector (+ structure-factor
+                               partials), matrix-core block product,
+                               matrix-free real space */
     RPY_PROF_BUILD = 1,     /* real-space tile build */
     RPY_PROF_KSPACE = 2,    /* structure-factor reduction */
     RPY_PROF_EPI = 3,       /* reciprocal back-projection + recurrence epilogue */
     RPY_PROF_OTHER = 4,     /* bd_step's forces + noise (on an internal
                                second stream, beside the tile build) */
-    RPY_PROF_KINDS = 5
+    RPY_PROF_SYMV_MULTI = 5, /* packed tile products of 2-4 vectors */
+    RPY_PROF_KINDS = 6
 };
 int rpy_profile_enable(rpy_ctx *c, int cap);
 int rpy_profile_read(rpy_ctx *c, int kind, int64_t *count, double *total_ms);

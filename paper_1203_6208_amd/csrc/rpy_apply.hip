@@ -94,8 +94,9 @@ template <> struct P6<uint16_t> {
 // both (i, j) and (j, i) and take row sums only.
 // Four vectors need 274 VGPRs, one wave per SIMD; capped at 256 (two waves,
 // a few spills) the FP64 launch takes 132 us instead of 176 us at N = 4000.
+// Three and four vectors run at two waves per SIMD.
 template <typename T, int M>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M == 4 ? 2 : 1, 8))) void k_symv6(int N, int n3, int n3pad, int rhs_cap, int j0,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 : 1, 8))) void k_symv6(int N, int n3, int n3pad, int rhs_cap, int j0,
                                                int nsf, int nkb, int nk, int nmax,
                                                const KVec *__restrict__ kvec,
                                                const double2 *__restrict__ etab,
@@ -235,6 +236,7 @@ static void symv_group(const Ctx &c, const T *tiles, const double *v, int j0, in
                        hipStream_t s)
 {
     if (mc == 4) symv_launch<T, 4>(c, tiles, v, j0, s);
+    else if (mc == 3) symv_launch<T, 3>(c, tiles, v, j0, s);
     else if (mc == 2) symv_launch<T, 2>(c, tiles, v, j0, s);
     else symv_launch<T, 1>(c, tiles, v, j0, s);
 }

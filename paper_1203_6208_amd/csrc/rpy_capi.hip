@@ -23,8 +23,8 @@ struct Prof {
 struct rpy_ctx {
     Ctx c;
     Prof prof;
-    double *F = nullptr;      // [2][3N]: forces, then U+ (all ones)
-    double *Y = nullptr;      // [2][3N]: D.F, D.U+
+    double *F = nullptr;      // [3][3N]: forces, U+ (all ones), the step's dW
+    double *Y = nullptr;      // [3][3N]: D.F, D.U+, D.dW
     double *dW = nullptr;     // [3N]
     double *dS = nullptr;     // [3N]
     double *Bv[2] = {nullptr, nullptr};  // [max_rhs][3N] Chebyshev vectors
@@ -253,7 +253,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     c.cheb_keep = p->cheb_keep;
     c.grad = p->grad != 0;
     c.lma = p->lma != 0;
-    c.rhs_cap = c.max_rhs > 2 ? c.max_rhs : 2;
+    c.rhs_cap = c.max_rhs > 3 ? c.max_rhs : 3;   // bd_step's product of [F, U+, dW]
     c.block = !c.lma && c.lowp != RPY_PREC_F64 && c.max_rhs >= BLOCK_MIN_RHS;
     if (c.block) c.rhs_cap = BLOCK_RHS;  // block kernels write all 16 columns
     c.pc = make_pair_const(c.L, c.a, c.alpha, c.rc);
@@ -302,7 +302,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     const size_t lcells = c.lma ? (size_t)c.lma_nc * c.lma_nc * c.lma_nc : 0;
     const size_t nv = (size_t)c.n3;
     const size_t mv = (size_t)c.rhs_cap * nv;
-    c.work_elems = 2 * nv + 2 * nv + nv + nv + 2 * mv + mv + mv;
+    c.work_elems = 3 * nv + 3 * nv + nv + nv + 2 * mv + mv + mv;
     const int ncell_cap = 64;
     const size_t ncells_cap = (size_t)ncell_cap * ncell_cap * ncell_cap;
     if ((rc = dalloc(&c.rt, nv)) || (rc = dalloc(&c.rt_ev, nv)) || (rc = dalloc(&c.etab, nv * (c.nmax + 1))) ||
@@ -340,8 +340,8 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
         return rc;
     }
     double *w = c.work;
-    x->F = w; w += 2 * nv;
-    x->Y = w; w += 2 * nv;
+    x->F = w; w += 3 * nv;
+    x->Y = w; w += 3 * nv;
     x->dW = w; w += nv;
     x->dS = w; w += nv;
     x->Bv[0] = w; w += mv;
@@ -457,8 +457,9 @@ static void product(rpy_ctx *x, const double *v, int m, int prec, const EpiArgs 
         return;
     }
     for (int j0 = 0; j0 < m;) {
-        const int mc = (m - j0) >= 4 ? 4 : (m - j0) >= 2 ? 2 : 1;
-        ProfScope ps(x, RPY_PROF_SYMV, s);
+        const int r = m - j0;
+        const int mc = r >= 4 ? 4 : r;
+        ProfScope ps(x, mc == 1 ? RPY_PROF_SYMV : RPY_PROF_SYMV_MULTI, s);
         launch_symv(c, prec, v, j0, mc, s);
         j0 += mc;
     }
@@ -483,11 +484,13 @@ extern "C" int rpy_apply(rpy_ctx *x, const double *v, double *out, int m, int pr
 }
 
 // Chebyshev recurrence with coefficients already in c.scal.
+// Products p = first .. n_cheb - 1 of the recurrence (first = 2 when V_1,
+// acc and D.dW are already in Bv[1], out and ddw).
 static void cheb_run(rpy_ctx *x, const double *dw, double *out, int m, int n_cheb, int prec,
-                     hipStream_t s)
+                     hipStream_t s, int first = 1)
 {
     const Ctx &c = x->c;
-    for (int p = 1; p < n_cheb; ++p) {
+    for (int p = first; p < n_cheb; ++p) {
         EpiArgs f{};
         f.m = m;
         f.p = p;
@@ -948,17 +951,21 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
     const size_t nv = (size_t)c.n3;
     launch_wrap_tables(c, pos, s);
     ++x->wrap_gen;
+    // The FP64 step folds the first Chebyshev product into the drift
+    // product: one pass over D for [F, U+, dW] (dW at F + 2 nv), then the
+    // coefficients, then V_1 from D.dW.  Lower-precision Chebyshev products
+    // keep their own first product.
+    const bool fold = bp->prec == RPY_PREC_F64;
+    double *w = fold ? x->F + 2 * nv : x->dW;
     // forces and noise on the side stream, beside the build
     HIP_TRY(hipEventRecord(x->fork, s));
     HIP_TRY(hipStreamWaitEvent(x->side, x->fork, 0));
-    const double *w = dw;
     {
         ProfScope ps(x, RPY_PROF_OTHER, x->side);
         forces(x, pos, c.rt, bp->ev_zstar, bp->ev_dstar, bp->ev_rcut, x->F, x->side);
-        if (!w) {
-            launch_noise(x->dW, (int64_t)nv, seed, step, bp->dt, x->side);
-            w = x->dW;
-        }
+        if (!dw) launch_noise(w, (int64_t)nv, seed, step, bp->dt, x->side);
+        else if (fold) launch_copy(w, dw, nv, x->side);
+        else w = const_cast<double *>(dw);
     }
     HIP_TRY(hipEventRecord(x->join, x->side));
     {
@@ -969,17 +976,30 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
     EpiArgs f{};
     f.mode = EPI_APPLY;
     f.vout = x->Y;
-    if (bp->bounds_rule == RPY_BOUNDS_PAPER) {
-        f.m = 2;   // [F, U+] in one pass over D
-        product(x, x->F, 2, RPY_PREC_F64, f, s);
-        launch_cheb_coeffs(c, bp->n_cheb, RPY_BOUNDS_PAPER, bp->bounds_C, 0, 0, x->Y + nv, s);
+    const bool paper = bp->bounds_rule == RPY_BOUNDS_PAPER;
+    // [F, U+] (paper rule) or [F] (explicit bounds), plus dW when folded
+    f.m = (paper ? 2 : 1) + (fold ? 1 : 0);
+    if (fold && !paper) {
+        // no U+ between F and dW: gather [F, dW] in Bv[0] (free until the
+        // recurrence's second product)
+        launch_copy(x->Bv[0], x->F, nv, s);
+        launch_copy(x->Bv[0] + nv, w, nv, s);
+        product(x, x->Bv[0], f.m, RPY_PREC_F64, f, s);
     } else {
-        f.m = 1;
-        product(x, x->F, 1, RPY_PREC_F64, f, s);
+        product(x, x->F, f.m, RPY_PREC_F64, f, s);
+    }
+    if (paper)
+        launch_cheb_coeffs(c, bp->n_cheb, RPY_BOUNDS_PAPER, bp->bounds_C, 0, 0, x->Y + nv, s);
+    else
         launch_cheb_coeffs(c, bp->n_cheb, RPY_BOUNDS_EXPLICIT, 0, bp->d_min, bp->d_max, nullptr,
                            s);
+    if (fold) {
+        const double *ddw = x->Y + (paper ? 2 : 1) * nv;   // D.dW
+        launch_cheb_first(c, ddw, w, x->Bv[1], x->dS, x->ddw, s);
+        cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s, 2);
+    } else {
+        cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s);
     }
-    cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s);
     if (e_f) launch_sqrt_error(c, 1, w, x->ddw, x->dS, e_f, s);
     if (drift) launch_copy(drift, x->Y, nv, s);
     if (noise) launch_copy(noise, x->dS, nv, s);

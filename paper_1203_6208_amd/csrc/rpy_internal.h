@@ -516,6 +516,8 @@ void launch_ev_vjp(const Ctx &c, const double *rt, double zstar, double dstar, d
 void launch_noise(double *out, int64_t count, uint64_t seed, uint64_t step, double dt,
                   hipStream_t s);
 void launch_philox(const uint32_t *ck, uint32_t *out, int64_t n, hipStream_t s);
+void launch_cheb_first(const Ctx &c, const double *y, const double *v0, double *v1, double *acc,
+                       double *dv, hipStream_t s);
 void launch_euler(const Ctx &c, double *pos, double dt, const double *ud,
                   const double *ds, hipStream_t s);
 void launch_observables(const Ctx &c, const double *pos, double *re2, double *rg2,

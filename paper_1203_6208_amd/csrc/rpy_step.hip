@@ -403,6 +403,31 @@ void launch_noise(double *out, int64_t count, uint64_t seed, uint64_t step, doub
 }
 
 // Euler-Maruyama update r += (dt/4) D.F + dS/sqrt(2) (eq. sde, kappa = 0).
+// The first Chebyshev step from a product computed before the coefficients
+// (bd_step folds D.dW into its drift product): with y = D.V_0,
+//   V_1 = ya y - yb V_0,  acc = (c_0/2) V_0 + c_1 V_1,  dv = y
+// (eq. cheb2; the same operations as the EPI_CHEB_FIRST epilogue).
+__global__ void k_cheb_first(int n3, const double *__restrict__ y, const double *__restrict__ v0,
+                             const double *__restrict__ scal, double *__restrict__ v1,
+                             double *__restrict__ acc, double *__restrict__ dv)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    const double ya = scal[2], yb = scal[3];
+    const double yy = y[i], a = v0[i];
+    const double b = ya * yy - yb * a;
+    v1[i] = b;
+    acc[i] = 0.5 * scal[8] * a + scal[9] * b;
+    dv[i] = yy;
+}
+
+void launch_cheb_first(const Ctx &c, const double *y, const double *v0, double *v1, double *acc,
+                       double *dv, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cheb_first, dim3((c.n3 + 255) / 256), dim3(256), 0, s, c.n3, y, v0,
+                       c.scal, v1, acc, dv);
+}
+
 __global__ void k_euler(int n3, double *__restrict__ pos, double dt4,
                         const double *__restrict__ ud, const double *__restrict__ ds)
 {

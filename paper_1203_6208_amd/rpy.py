@@ -272,7 +272,7 @@ def rpy_forces_vjp(ctx, pos, zstar, dstar, rcut, gF, g_pos, stream=None):
     return g_pos
 
 
-PROF_SYMV, PROF_BUILD, PROF_KSPACE, PROF_EPI, PROF_OTHER = range(5)
+PROF_SYMV, PROF_BUILD, PROF_KSPACE, PROF_EPI, PROF_OTHER, PROF_SYMV_MULTI = range(6)
 
 
 def rpy_profile_enable(ctx, cap: int) -> None:
