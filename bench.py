@@ -34,17 +34,17 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on 1 GiB device copies in the same process).  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "18116b5c2b47a16d403fb7753e0cee14a5c0ce993981648af782698808ad8750",
+TRAFFIC = {"src_sha256": "123665518a7641f895c6c4582f6f388854d777796a52330479b3f3d4e2d5e25a",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 409641527}
-TRAFFIC_BLOCK = {"src_sha256": "5abfa89c82dff85286e5a56da84134a6e6101d14931229953277db0b2d79748c",
+           "bytes_per_launch": 409641829}
+TRAFFIC_BLOCK = {"src_sha256": "7941e944961f4527c522d9035d55ed7eb74435a5493804501c1d23013d65ffbf",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f32": 312316961 + 48771072, "bf16": 159672889 + 48771072}}
+                 "bytes_per_launch": {"f32": 312284275 + 48771072, "bf16": 159688360 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "30e194b06006da89d634e5911ef9eeaa97bf3fbff545e36fbc1b28485bc89b49",
+TRAFFIC_BATCH = {"src_sha256": "3f5382cc92993f041ce61303cd60c64600e0e71eafb28db623c31ecdaec6497f",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4931230847}
+                 "bytes_per_launch": 4931232757}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 
