@@ -35,10 +35,12 @@ template <> struct P6<double> {
     };
     static constexpr bool hoist = false;
     __device__ static int col(int q, int e) { return 32 * (e >> 1) + 2 * q + (e & 1); }
-    __device__ static raw_t raw(const double *row, int q)
+    template <bool CACHED> __device__ static raw_t raw(const double *row, int q)
     {
-        return {__builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 2 * q)),
-                __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 32 + 2 * q))};
+        const d2v *a = reinterpret_cast<const d2v *>(row + 2 * q);
+        const d2v *b = reinterpret_cast<const d2v *>(row + 32 + 2 * q);
+        if constexpr (CACHED) return {*a, *b};
+        else return {__builtin_nontemporal_load(a), __builtin_nontemporal_load(b)};
     }
     __device__ static void cvt(const raw_t &r, double a[4])
     {
@@ -52,9 +54,11 @@ template <> struct P6<float> {
     typedef float raw_t __attribute__((ext_vector_type(4)));
     static constexpr bool hoist = false;
     __device__ static int col(int q, int e) { return 4 * q + e; }
-    __device__ static raw_t raw(const float *row, int q)
+    template <bool CACHED> __device__ static raw_t raw(const float *row, int q)
     {
-        return __builtin_nontemporal_load(reinterpret_cast<const raw_t *>(row + 4 * q));
+        const raw_t *a = reinterpret_cast<const raw_t *>(row + 4 * q);
+        if constexpr (CACHED) return *a;
+        else return __builtin_nontemporal_load(a);
     }
     __device__ static void cvt(const raw_t &u, double a[4])
     {
@@ -68,9 +72,11 @@ template <> struct P6<uint16_t> {
     typedef uint32_t raw_t __attribute__((ext_vector_type(2)));
     static constexpr bool hoist = true;
     __device__ static int col(int q, int e) { return 4 * q + e; }
-    __device__ static raw_t raw(const uint16_t *row, int q)
+    template <bool CACHED> __device__ static raw_t raw(const uint16_t *row, int q)
     {
-        return __builtin_nontemporal_load(reinterpret_cast<const raw_t *>(row + 4 * q));
+        const raw_t *a = reinterpret_cast<const raw_t *>(row + 4 * q);
+        if constexpr (CACHED) return *a;
+        else return __builtin_nontemporal_load(a);
     }
     __device__ static void cvt(const raw_t &u, double a[4])
     {
@@ -95,7 +101,7 @@ template <> struct P6<uint16_t> {
 // Four vectors need 274 VGPRs, one wave per SIMD; capped at 256 (two waves,
 // a few spills) the FP64 launch takes 132 us instead of 176 us at N = 4000.
 // Three and four vectors run at two waves per SIMD.
-template <typename T, int M>
+template <typename T, int M, bool CACHED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 : 1, 8))) void k_symv6(int N, int n3, int n3pad, int rhs_cap, int j0,
                                                int nsf, int nkb, int nk, int nmax,
                                                const KVec *__restrict__ kvec,
@@ -151,7 +157,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
         for (int it = 0; it < TB / 16; ++it)
 #pragma unroll
             for (int c = 0; c < 6; ++c)
-                rw[it][c] = P6<T>::raw(tile + (size_t)(16 * it + 4 * w + g) * 6 * TB + c * TB, q);
+                rw[it][c] = P6<T>::template raw<CACHED>(
+                    tile + (size_t)(16 * it + 4 * w + g) * 6 * TB + c * TB, q);
     }
 #pragma unroll
     for (int it = 0; it < TB / 16; ++it) {
@@ -160,7 +167,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
         double b[6][4];
         if constexpr (!P6<T>::hoist) {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) rw[it][c] = P6<T>::raw(row + c * TB, q);
+            for (int c = 0; c < 6; ++c) rw[it][c] = P6<T>::template raw<CACHED>(row + c * TB, q);
         }
 #pragma unroll
         for (int c = 0; c < 6; ++c) P6<T>::cvt(rw[it][c], b[c]);
@@ -226,9 +233,19 @@ static void symv_launch(const Ctx &c, const T *tiles, const double *v, int j0, h
     const int nkb = (c.nk + 255) / 256;
     const int nsf = c.nsfc * nkb;
     const size_t lds = symv_lds<T, M>(c);
-    hipLaunchKernelGGL((k_symv6<T, M>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N, c.n3,
-                       c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab, c.sfpart,
-                       c.tile_ij, tiles, v, c.part);
+    // Tiles that fit the Infinity Cache with room to spare are read with
+    // ordinary (allocating) loads and stay there from one product to the
+    // next; larger ones are streamed with non-temporal loads, which keep
+    // them from evicting the rest.
+    const bool cached = (size_t)c.ntiles * TILE6 * sizeof(T) <= TILE_CACHE_BYTES;
+    if (cached)
+        hipLaunchKernelGGL((k_symv6<T, M, true>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N,
+                           c.n3, c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab,
+                           c.sfpart, c.tile_ij, tiles, v, c.part);
+    else
+        hipLaunchKernelGGL((k_symv6<T, M, false>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N,
+                           c.n3, c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab,
+                           c.sfpart, c.tile_ij, tiles, v, c.part);
 }
 
 template <typename T>

@@ -30,6 +30,10 @@ constexpr int TB = 64;          // beads per tile side
 constexpr int TS = 3 * TB;      // matrix rows per tile side
 constexpr int TILE_ELEMS = TS * TS;
 constexpr int TILE6 = 6 * TB * TB;   // packed FP64 tile: 6 planes per bead row
+// Tile arrays up to this size are read with allocating loads so that they
+// stay in the 256 MB Infinity Cache across products (measured at N = 4000:
+// FP32 tiles, 198 MB, 44.1 -> 39.8 us; BF16, 99 MB, 34.8 -> 31.3 us).
+constexpr size_t TILE_CACHE_BYTES = (size_t)200 << 20;
 constexpr int NSER = 20;        // terms of the small-r series of S(r)
 constexpr double XSER = 0.75;   // use the series for alpha*r below this
 constexpr int MAX_RHS = 16;
