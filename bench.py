@@ -34,17 +34,17 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on 1 GiB device copies in the same process).  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "123665518a7641f895c6c4582f6f388854d777796a52330479b3f3d4e2d5e25a",
+TRAFFIC = {"src_sha256": "24ada6dc29b06987daf292185dab64c152462ca9186113b83876dc94d131bdac",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 409641829}
-TRAFFIC_BLOCK = {"src_sha256": "7941e944961f4527c522d9035d55ed7eb74435a5493804501c1d23013d65ffbf",
+           "bytes_per_launch": 409641915}
+TRAFFIC_BLOCK = {"src_sha256": "e442f5aefbf962a6840170df2eb94873d1d6815aee559558009e1ae60b34e681",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f32": 312284275 + 48771072, "bf16": 159688360 + 48771072}}
+                 "bytes_per_launch": {"f32": 312502476 + 48771072, "bf16": 159700779 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "3f5382cc92993f041ce61303cd60c64600e0e71eafb28db623c31ecdaec6497f",
+TRAFFIC_BATCH = {"src_sha256": "0dafaabd4ddf05e3150462a6e0840539e1ce36149a1bb9ef95b0d31a3602ba48",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4931232757}
+                 "bytes_per_launch": 4931231716}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 
