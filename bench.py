@@ -554,8 +554,8 @@ def measured_traffic(t=TRAFFIC, key=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design note, not implemented.", file=sys.stderr)
+        print(f"bench.py: the library and this benchmark run on one GPU only (asked for --gpus "
+              f"{args.gpus}); sharding across GPUs is designed, not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
 

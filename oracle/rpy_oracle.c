@@ -21,7 +21,7 @@
  * diffusion matrix is 3N x 3N row-major with row index 3*nu + i (the block
  * matrix of the section "Governing equation").
  *
- * Readings of the paper that this file takes (each is repeated in the design doc):
+ * Readings of the paper that this file takes (the GPU library takes the same):
  *  - reciprocal sum uses cos(k.(r_nu - r_mu)) (the printed minus sign in the
  *    Beenakker sum breaks translation invariance);
  *  - the rr coefficient of M* is (3/(2x^3))(x^2/4-1)^2, i.e. M* equals the
