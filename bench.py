@@ -65,6 +65,11 @@ def parse():
                     help="run only the high/low-memory crossover study")
     ap.add_argument("--no-studies", action="store_true",
                     help="skip the eigenvalue, batching, differentiation and crossover studies")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="also time the CPU oracle at N = 100, 1000, 2000, 4000 on one thread "
+                         "and on all threads (about a minute of host time)")
+    ap.add_argument("--oracle-table-seconds", type=float, default=2.5,
+                    help="host seconds per cell of the oracle table")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -529,6 +534,77 @@ def cpu_baseline(w, seconds):
                        f"(O(N))")}
 
 
+def host_description():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def oracle_table(seconds):
+    """The oracle's cost on the host, on one thread and on all of its threads,
+    for the workloads of N = 100, 1000, 2000 and 4000 beads: one build of D
+    (real-space sum, self term and the reciprocal sum over the full +-k set),
+    one product D.v, one sqrt(D).dW (N_Ch - 1 products) for 1 and 16 vectors,
+    and one step (build + 2 + N_Ch - 1 products; forces and update are O(N)
+    and left out).  Rows of D are sampled at evenly spaced beads (all rows
+    where that fits the time per cell) and the times scaled by N / rows; the
+    products are the oracle's plain row loops on the sampled rows, scaled the
+    same way."""
+    import oracle
+    from paper_1203_6208_amd import inputs
+    oracle.build(force=False)
+    allth = oracle.max_threads()
+    out = {"host": host_description(), "threads_all": allth,
+           "seconds_per_cell": seconds, "rows": []}
+    for name in ("n100", "n1000", "n2000", "n4000"):
+        w = inputs.workload(name)
+        pos = w.positions()
+        v = np.random.default_rng(0).standard_normal(3 * w.n)
+
+        def sample(nb):
+            rows = np.linspace(0, w.n - 1, nb).round().astype(int)
+            t0 = time.perf_counter()
+            R = oracle.diffusion_rows(pos, rows, w.L, w.a, w.alpha, w.rc, w.n2max)
+            t1 = time.perf_counter()
+            reps, t2 = 0, t1
+            while reps < 3 or (t2 - t1 < 0.2 and reps < 1000):
+                oracle.rows_matvec(R, v)
+                reps += 1
+                t2 = time.perf_counter()
+            return t1 - t0, (t2 - t1) / reps
+
+        for th in sorted({1, allth}):
+            oracle.use_threads(th)
+            # the loops are parallel over rows: sample whole rounds of th rows
+            p = min(w.n, max(2, th))
+            tb, tm = sample(p)
+            nb = int(seconds / max((tb + tm) / p, 1e-9))
+            nb = min(w.n, max(p, nb // p * p))
+            tb, tm = sample(nb)
+            scale = w.n / nb
+            build, prod = tb * scale, tm * scale
+            row = {"workload": name, "n_beads": w.n, "n_cheb": w.nch, "threads": th,
+                   "rows_sampled": nb, "build_s": build, "product_s": prod,
+                   "sqrt_m1_s": (w.nch - 1) * prod, "sqrt_m16_s": 16 * (w.nch - 1) * prod,
+                   "step_s": build + (2 + w.nch - 1) * prod}
+            out["rows"].append(row)
+            print(f"# oracle table {row}", file=sys.stderr, flush=True)
+    oracle.use_threads(allth)
+    return out
+
+
 def tile_bytes(n, prec, packed=True):
     """Algorithmic bytes one product streams.  Packed tiles (every product of
     up to 4 vectors) keep the 6 distinct entries of each symmetric 3 x 3
@@ -628,6 +704,7 @@ def main():
         forms["differentiation_n2000"] = dstudy
         forms["hma_lma_crossover"] = lma_study(torch, rpy, inputs)
     cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_seconds)
+    otab = oracle_table(args.oracle_table_seconds) if args.oracle_table else None
     line = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -648,6 +725,8 @@ def main():
         "eigen": eigen,
         "cpu_baseline": cpu,
     }
+    if otab is not None:
+        line["oracle_table"] = otab
     print(json.dumps(line))
 
 

@@ -65,6 +65,8 @@ def _L():
             "orc_count_kvectors": (i, [i]),
             "orc_matvec": (None, [i, p, i, p, p]),
             "orc_rows_matvec": (None, [i, i, p, p, p]),
+            "orc_set_threads": (None, [i]),
+            "orc_max_threads": (i, []),
             "orc_cheb_coeffs": (None, [i, d, d, p]),
             "orc_cheb_sqrt": (None, [i, p, i, p, i, d, d, p]),
             "orc_sqrt_error": (d, [i, p, p, p]),
@@ -99,6 +101,17 @@ def _f64(x) -> np.ndarray:
 def set_threads(n: int) -> None:
     """Set the OpenMP thread count the oracle uses (environment-level)."""
     os.environ["OMP_NUM_THREADS"] = str(int(n))
+
+
+def use_threads(n: int) -> None:
+    """Set the OpenMP team size of the oracle's later parallel loops (takes
+    effect in a process whose OpenMP runtime has already started)."""
+    _L().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    """The team size the oracle's parallel loops use now."""
+    return int(_L().orc_max_threads())
 
 
 # ---------------------------------------------------------------- pair terms

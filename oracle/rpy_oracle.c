@@ -35,6 +35,7 @@
  *    N_Ch Chebyshev-Gauss nodes mapped onto [d_min, d_max].
  */
 #include <math.h>
+#include <omp.h>
 #include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -331,6 +332,11 @@ void orc_matvec(int n3, const double *D, int m, const double *V, double *out)
             out[(long)j * n3 + i] = s;
         }
 }
+
+/* Thread control for timing the oracle (no arithmetic): the OpenMP team size
+ * of later parallel loops, and the size they would use now. */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* out = R . v for a block of rows R [nrows][ncols] (same plain loop). */
 void orc_rows_matvec(int nrows, int ncols, const double *R, const double *v, double *out)

@@ -416,3 +416,24 @@ def test_theta_statics_statistical(orc):
         re.append(np.mean(np.sum((x[:, -1] - x[:, 0]) ** 2, axis=1)))
     assert abs(np.mean(q2) / 3.0 - 1) < 0.06
     assert abs(np.mean(re) / 9.0 - 1) < 0.2
+
+
+def test_thread_count_leaves_results_unchanged(orc):
+    """The oracle's loops are parallel over rows and each row is summed by one
+    thread, so its results are the same on one thread and on all of them."""
+    w = inputs.workload("n100")
+    pos = w.positions()
+    rows = [0, 17, 50, 99]
+    v = np.random.default_rng(3).standard_normal(3 * w.n)
+    allth = orc.max_threads()
+    try:
+        orc.use_threads(1)
+        assert orc.max_threads() == 1
+        R1 = orc.diffusion_rows(pos, rows, w.L, w.a, w.alpha, w.rc, w.n2max)
+        y1 = orc.rows_matvec(R1, v)
+    finally:
+        orc.use_threads(allth)
+    assert orc.max_threads() == allth
+    R = orc.diffusion_rows(pos, rows, w.L, w.a, w.alpha, w.rc, w.n2max)
+    assert np.array_equal(R, R1)
+    assert np.array_equal(orc.rows_matvec(R, v), y1)
