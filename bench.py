@@ -29,22 +29,23 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes moved by one tile-product launch at N = 4000, from two rocprofv3
+# Bytes moved by one tile-product launch at N = 4000, from two rocprofv3
 # counter runs (FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000, scale factors
-# calibrated on 1 GiB device copies in the same process).  Valid only for the
+# calibrated on 1 GiB device copies in the same process).  FETCH_SIZE counts
+# what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "24ada6dc29b06987daf292185dab64c152462ca9186113b83876dc94d131bdac",
+TRAFFIC = {"src_sha256": "f53f7fe99e98900a280666e314473f88b001a35925f6d6ac3112339ec852e56d",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 409641915}
-TRAFFIC_BLOCK = {"src_sha256": "e442f5aefbf962a6840170df2eb94873d1d6815aee559558009e1ae60b34e681",
+           "bytes_per_launch": 411396167}
+TRAFFIC_BLOCK = {"src_sha256": "d4c3815a400ec488f6080f2c09bd371ef44323bfb01fb0a1ad3d9978355c70ec",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f32": 312502476 + 48771072, "bf16": 159700779 + 48771072}}
+                 "bytes_per_launch": {"f32": 312420526 + 48771072, "bf16": 159666388 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "0dafaabd4ddf05e3150462a6e0840539e1ce36149a1bb9ef95b0d31a3602ba48",
+TRAFFIC_BATCH = {"src_sha256": "09257c39df6018fd96a5e529cfef173f0b0a3d3b7f19c714802bb9d33bd53f4e",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4931231716}
+                 "bytes_per_launch": 4931231898}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 

@@ -26,7 +26,8 @@ template <typename A> __device__ inline A sum16(A x)
 // Loads of a packed plane row (64 values of one bead row and one entry of
 // the 3 x 3 blocks): lane q (0..15) of a 16-lane row group owns the bead
 // columns col(q, e), e = 0..3, read with 16-byte (FP64, FP32) or 8-byte
-// (BF16) non-temporal loads that are contiguous across the row group.
+// (BF16) loads that are contiguous across the row group: allocating loads
+// when CACHED, else non-temporal ones.
 template <typename T> struct P6;
 template <> struct P6<double> {
     typedef double d2v __attribute__((ext_vector_type(2)));
@@ -90,7 +91,8 @@ template <> struct P6<uint16_t> {
 // Product on the packed tiles (6 planes per bead row, tile[t][i][c][j]),
 // FP64, FP32 or BF16 entries, FP64 arithmetic.  Workgroups [0, nsf) compute
 // structure-factor partials of v; each further workgroup (4 waves) takes one
-// stored tile (I, J).  Wave w, row group g (16 lanes), lane q: bead rows
+// stored tile (I, J), in stored order or, when `flip`, in reverse order (each
+// tile's results go to its own slots, so the order changes no value).  Wave w, row group g (16 lanes), lane q: bead rows
 // i = 16 it + 4 w + g (it = 0..3); lane q owns the bead columns
 // jb(e) = P6<T>::col(q, e), e = 0..3, of every plane.  With B the symmetric
 // 3 x 3 block of (i, j), the row sums of B x_j over the 16 lanes give
@@ -103,7 +105,7 @@ template <> struct P6<uint16_t> {
 // Three and four vectors run at two waves per SIMD.
 template <typename T, int M, bool CACHED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 : 1, 8))) void k_symv6(int N, int n3, int n3pad, int rhs_cap, int j0,
-                                               int nsf, int nkb, int nk, int nmax,
+                                               int nsf, int flip, int nkb, int nk, int nmax,
                                                const KVec *__restrict__ kvec,
                                                const double2 *__restrict__ etab,
                                                double *__restrict__ sfpart,
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
     }
     double(*sx)[TS] = reinterpret_cast<double(*)[TS]>(smem);                    // [M][TS]
     double(*scol)[M][TS] = reinterpret_cast<double(*)[M][TS]>(smem + M * TS);  // [4][M][TS]
-    const int t = blockIdx.x - nsf;
+    const int t = flip ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x - nsf;
     const int2 ij = tile_ij[t];
     const int I = ij.x, J = ij.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -233,18 +235,21 @@ static void symv_launch(const Ctx &c, const T *tiles, const double *v, int j0, h
     const int nkb = (c.nk + 255) / 256;
     const int nsf = c.nsfc * nkb;
     const size_t lds = symv_lds<T, M>(c);
-    // Tiles that fit the Infinity Cache with room to spare are read with
-    // ordinary (allocating) loads and stay there from one product to the
-    // next; larger ones are streamed with non-temporal loads, which keep
-    // them from evicting the rest.
-    const bool cached = (size_t)c.ntiles * TILE6 * sizeof(T) <= TILE_CACHE_BYTES;
+    // Allocating loads, with the tile order reversed on every other launch,
+    // for arrays that fit the Infinity Cache and, in one-vector products, for
+    // arrays up to TILE_ZIGZAG_BYTES (each product then starts on the tiles
+    // the previous one left in the cache); otherwise non-temporal loads in
+    // stored order, which keep the stream from evicting the rest.
+    const size_t bytes = (size_t)c.ntiles * TILE6 * sizeof(T);
+    const bool cached = bytes <= TILE_CACHE_BYTES || (M == 1 && bytes <= TILE_ZIGZAG_BYTES);
+    const int flip = cached ? (int)(c.symv_calls++ & 1u) : 0;
     if (cached)
         hipLaunchKernelGGL((k_symv6<T, M, true>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N,
-                           c.n3, c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab,
+                           c.n3, c.n3pad, c.rhs_cap, j0, nsf, flip, nkb, c.nk, c.nmax, c.kvec, c.etab,
                            c.sfpart, c.tile_ij, tiles, v, c.part);
     else
         hipLaunchKernelGGL((k_symv6<T, M, false>), dim3(nsf + c.ntiles), dim3(256), lds, s, c.N,
-                           c.n3, c.n3pad, c.rhs_cap, j0, nsf, nkb, c.nk, c.nmax, c.kvec, c.etab,
+                           c.n3, c.n3pad, c.rhs_cap, j0, nsf, flip, nkb, c.nk, c.nmax, c.kvec, c.etab,
                            c.sfpart, c.tile_ij, tiles, v, c.part);
 }
 

@@ -30,10 +30,18 @@ constexpr int TB = 64;          // beads per tile side
 constexpr int TS = 3 * TB;      // matrix rows per tile side
 constexpr int TILE_ELEMS = TS * TS;
 constexpr int TILE6 = 6 * TB * TB;   // packed FP64 tile: 6 planes per bead row
-// Tile arrays up to this size are read with allocating loads so that they
-// stay in the 256 MB Infinity Cache across products (measured at N = 4000:
-// FP32 tiles, 198 MB, 44.1 -> 39.8 us; BF16, 99 MB, 34.8 -> 31.3 us).
+// Tile arrays up to TILE_CACHE_BYTES are read with allocating loads and stay
+// in the 256 MB Infinity Cache from one product to the next (measured at
+// N = 4000: FP32 tiles, 192 MB, 44.1 -> 39.2 us; BF16, 96 MB, 33.9 -> 30.6
+// us).  One-vector products also read arrays up to TILE_ZIGZAG_BYTES with
+// allocating loads, walking the tiles in reverse order on every other
+// launch, so that the tiles one product read last (those still in the
+// cache) are the first the next one reads (FP64 tiles at N = 4000, 384 MB:
+// 70.5 -> 67.6 us).  Products of 2-4 vectors on such arrays lose by it (87.5
+// -> 103.4 us for three vectors) and, like every larger array, stream the
+// tiles with non-temporal loads in stored order.
 constexpr size_t TILE_CACHE_BYTES = (size_t)200 << 20;
+constexpr size_t TILE_ZIGZAG_BYTES = (size_t)384 << 20;
 constexpr int NSER = 20;        // terms of the small-r series of S(r)
 constexpr double XSER = 0.75;   // use the series for alpha*r below this
 constexpr int MAX_RHS = 16;
@@ -369,13 +377,14 @@ struct Ctx {
     int n2max, nmax;   // |n|^2 cutoff and max |component|
     int nk;            // half-space wave vectors
     int lowp, max_rhs;
-    int rhs_cap;       // stride of the per-RHS work buffers: max(max_rhs, 2)
+    int rhs_cap;       // stride of the per-RHS work buffers: max(max_rhs, 3)
     PairConst pc;
     // tiling
     int nbt;           // bead tiles per side
     int ntiles;        // stored tiles
     int n3pad;         // nbt * TS
     int nsfc;          // structure-factor bead chunks (SF_BEADS beads each)
+    mutable unsigned symv_calls = 0;   // tile products launched (their parity sets the tile order)
     // device buffers
     double *rt = nullptr;        // wrapped positions [N][3] of the built D
     double *rt_ev = nullptr;     // wrapped positions for stand-alone force calls
