@@ -35,9 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "f53f7fe99e98900a280666e314473f88b001a35925f6d6ac3112339ec852e56d",
+TRAFFIC = {"src_sha256": "a92caad78277e895b567589130eca4b374dc5821a1621522119644662522bb40",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 411396167}
+           "bytes_per_launch": 411394987}
 TRAFFIC_BLOCK = {"src_sha256": "d4c3815a400ec488f6080f2c09bd371ef44323bfb01fb0a1ad3d9978355c70ec",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
                  "bytes_per_launch": {"f32": 312420526 + 48771072, "bf16": 159666388 + 48771072}}

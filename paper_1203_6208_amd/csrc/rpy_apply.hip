@@ -373,9 +373,6 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
     const int nm1 = nmax + 1;
     double2 *tabs = reinterpret_cast<double2 *>(lds);          // [EPI_BEADS][3 nm1]
     double *stage = lds + 2 * EPI_BEADS * 3 * nm1;
-    const KVec *kv_s = staged ? reinterpret_cast<const KVec *>(stage) : kvec;
-    const double *tk_s = staged ? stage + 2 * (nk + 1) : tk_g + (size_t)j0 * 6;
-    const int tk_ld = staged ? 6 * M : 6 * rhs_cap;
     // Loads that do not depend on the staged tables are issued first: the
     // bead's tile-column partials and, for the 3 EPI_BEADS threads that apply
     // the epilogue, the recurrence operands.
@@ -437,28 +434,37 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
     const double2 *tb = tabs + bl * 3 * nm1;
     const double2 ez = nm1 > 1 ? tb[2 * nm1 + 1] : make_double2(1.0, 0.0);   // e^{i 2 pi s_z}
     const double ezr = ez.x, ezi = ez.y;
-    double cs = 1.0, sn = 0.0;
-    int px = -(1 << 30), py = 0, pz = 0;
-    for (int k = klo; k < khi; ++k) {
-        const KVec kv = kv_s[k];
-        if (kv.nx == px && kv.ny == py && kv.nz == pz + 1) {
-            const double c2 = cs * ezr - sn * ezi;
-            sn = cs * ezi + sn * ezr;
-            cs = c2;
-        } else {   // a run start: the phase from the bead's tables
-            const double2 e = kphase(kv, tb, nm1);
-            cs = e.x;
-            sn = e.y;
+    // The loop is written out once per source of the tables, so that each
+    // copy reads through a pointer of known address space (LDS reads when
+    // staged; a pointer that may be either compiles to generic loads).
+    auto kloop = [&](const KVec *kv_s, const double *tk_s, int tk_ld) {
+        double cs = 1.0, sn = 0.0;
+        int px = -(1 << 30), py = 0, pz = 0;
+        for (int k = klo; k < khi; ++k) {
+            const KVec kv = kv_s[k];
+            if (kv.nx == px && kv.ny == py && kv.nz == pz + 1) {
+                const double c2 = cs * ezr - sn * ezi;
+                sn = cs * ezi + sn * ezr;
+                cs = c2;
+            } else {   // a run start: the phase from the bead's tables
+                const double2 e = kphase(kv, tb, nm1);
+                cs = e.x;
+                sn = e.y;
+            }
+            px = kv.nx;
+            py = kv.ny;
+            pz = kv.nz;
+            const double *tt = tk_s + (size_t)k * tk_ld;
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) y[j][c] += cs * tt[6 * j + c] + sn * tt[6 * j + 3 + c];
         }
-        px = kv.nx;
-        py = kv.ny;
-        pz = kv.nz;
-        const double *tt = tk_s + (size_t)k * tk_ld;
-#pragma unroll
-        for (int j = 0; j < M; ++j)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) y[j][c] += cs * tt[6 * j + c] + sn * tt[6 * j + 3 + c];
-    }
+    };
+    if (staged)
+        kloop(reinterpret_cast<const KVec *>(stage), stage + 2 * (nk + 1), 6 * M);
+    else
+        kloop(kvec, tk_g + (size_t)j0 * 6, 6 * rhs_cap);
     const double ya = f.scal ? f.scal[2] : 0.0, yb = f.scal ? f.scal[3] : 0.0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
