@@ -35,17 +35,17 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "a92caad78277e895b567589130eca4b374dc5821a1621522119644662522bb40",
+TRAFFIC = {"src_sha256": "6ec5e0b9b9e49529e9a4442d5db63fdaf781281e38b77027abad810cc73ca31f",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 411394987}
-TRAFFIC_BLOCK = {"src_sha256": "d4c3815a400ec488f6080f2c09bd371ef44323bfb01fb0a1ad3d9978355c70ec",
+           "bytes_per_launch": 411374984}
+TRAFFIC_BLOCK = {"src_sha256": "fdf70b4d9eb56de94a3b3d7182c671a37de09f487260541b2d4f00ac198b995e",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f32": 312420526 + 48771072, "bf16": 159666388 + 48771072}}
+                 "bytes_per_launch": {"f32": 312425130 + 48771072, "bf16": 159588026 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "09257c39df6018fd96a5e529cfef173f0b0a3d3b7f19c714802bb9d33bd53f4e",
+TRAFFIC_BATCH = {"src_sha256": "0dd29d542bb3f1f6605d671f5b959d025b11065892315c74d662928e3cfd9b14",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4931231898}
+                 "bytes_per_launch": 4931230504}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 

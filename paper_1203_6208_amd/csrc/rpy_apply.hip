@@ -8,8 +8,9 @@ namespace rpy {
 
 #define RPY_RHS_GROUPS(m, BODY)                                              \
     for (int j0 = 0; j0 < (m);) {                                            \
-        const int mc = ((m) - j0) >= 4 ? 4 : ((m) - j0) >= 2 ? 2 : 1;        \
+        const int mc = ((m) - j0) >= 4 ? 4 : ((m) - j0);                     \
         if (mc == 4) { constexpr int MC = 4; BODY; }                         \
+        else if (mc == 3) { constexpr int MC = 3; BODY; }                    \
         else if (mc == 2) { constexpr int MC = 2; BODY; }                    \
         else { constexpr int MC = 1; BODY; }                                 \
         j0 += mc;                                                            \

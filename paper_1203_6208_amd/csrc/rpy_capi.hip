@@ -85,6 +85,7 @@ PairConst make_pair_const(double L, double a, double alpha, double rc)
     p.inv_sqrtpi = 1.0 / sqrt(M_PI);
     p.A1 = a * alpha;
     p.A3 = p.A1 * p.A1 * p.A1;
+    p.inv_A1sq = 1.0 / (p.A1 * p.A1);
     p.self_coeff = 1.0 - 6.0 * p.A1 * p.inv_sqrtpi + 40.0 * p.A3 * p.inv_sqrtpi / 3.0;
     double fact = 1.0;  // n!
     for (int n = 0; n < NSER; ++n) {

@@ -61,6 +61,7 @@ struct PairConst {
     double self_coeff;     // 1 - 6 a al/sqrt(pi) + 40 a^3 al^3 / (3 sqrt(pi))
     double A1, A3;         // a*alpha and (a*alpha)^3
     double inv_sqrtpi;
+    double inv_A1sq;       // 1 / (a alpha)^2
     double s1[NSER], s2[NSER];  // series of S1, S2 in (alpha r)^2
 };
 
@@ -75,9 +76,9 @@ RPY_HD inline void m1_coeffs(double r, const PairConst &p, double &c1, double &c
     const double x2 = x * x;
     const double e = erfc(x);
     const double g = exp(-x2) * p.inv_sqrtpi;
-    const double ar = p.a / r;
+    const double ar = p.a * (1.0 / r);
     const double ar3 = ar * ar * ar;
-    const double ix2 = 1.0 / x2;
+    const double ix2 = ar * ar * p.inv_A1sq;   // 1/x^2 = (a/r)^2 / (a alpha)^2
     c1 = e * (0.75 * ar + 0.5 * ar3)
        + g * (p.A1 * (3.0 * x2 - 4.5) + p.A3 * ((4.0 * x2 - 20.0) * x2 + 14.0 + ix2));
     c2 = e * (0.75 * ar - 1.5 * ar3)
