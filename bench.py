@@ -35,9 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "6ec5e0b9b9e49529e9a4442d5db63fdaf781281e38b77027abad810cc73ca31f",
+TRAFFIC = {"src_sha256": "a888d46cf20503e9494a1a4522999fd63e09cb1372f9568b7b2c4a30310c8396",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 411374984}
+           "bytes_per_launch": 411374571}
 TRAFFIC_BLOCK = {"src_sha256": "fdf70b4d9eb56de94a3b3d7182c671a37de09f487260541b2d4f00ac198b995e",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
                  "bytes_per_launch": {"f32": 312425130 + 48771072, "bf16": 159588026 + 48771072}}

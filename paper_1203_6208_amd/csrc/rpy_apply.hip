@@ -291,6 +291,10 @@ __global__ __launch_bounds__(1024) void k_sf_reduce(int nk, int nsfc, int rhs_ca
     const int kk = lane & 15, sub = lane >> 4;
     const int k = blockIdx.x * 16 + kk;
     const int j = blockIdx.y >> 1, half = blockIdx.y & 1;
+    // the projection of the 16 threads that finish, loaded with the
+    // partials (after the barrier it would be a second memory round trip)
+    KCoef kc = {0.0, 0.0, 0.0, 0.0};
+    if (threadIdx.x < 16 && k < nk) kc = kcoef[k];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     if (k < nk) {
         const size_t cstride = (size_t)6 * rhs_cap * nk;
@@ -322,7 +326,6 @@ __global__ __launch_bounds__(1024) void k_sf_reduce(int nk, int nsfc, int rhs_ca
         for (int w = 0; w < 16; ++w) a += red[w][c][kk];
         t[c] = a;
     }
-    const KCoef kc = kcoef[k];
     const double h = kc.hx * t[0] + kc.hy * t[1] + kc.hz * t[2];
     double *o = tk + ((size_t)k * rhs_cap + j0 + j) * 6 + 3 * half;
     o[0] = kc.w * (t[0] - kc.hx * h);
