@@ -522,12 +522,14 @@ def cpu_baseline(w, seconds):
         t2 = time.perf_counter()
         return t1 - t0, t2 - t1
 
-    tb, tm = sample(4)
-    per_bead = (tb + tm) / 4
-    nb = int(max(4, min(w.n, seconds / max(per_bead, 1e-9))))
+    # the oracle's loops are parallel over rows: probe with one row per thread
+    threads = oracle.max_threads()
+    p = min(w.n, max(4, threads))
+    tb, tm = sample(p)
+    per_bead = (tb + tm) / p
+    nb = int(max(p, min(w.n, seconds / max(per_bead, 1e-9))))
     tb, tm = sample(nb)
     t_step = (tb + tm) * w.n / nb
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": threads, "kind": "oracle",
             "sample": (f"D block rows of {nb} of {w.n} beads (real space + self + reciprocal "
                        f"over 1236 k, brute force) plus {2 + w.nch - 1} row-block products; "
