@@ -309,6 +309,11 @@ def test_full_size_n4000_sampled_rows(orc):
     out = ctx.apply(_cuda(v)).cpu().numpy().reshape(w.n, 3)
     ref = (R @ v.reshape(-1)).reshape(len(rows), 3)
     assert _rel(out[rows], ref) < TOL
+    # consecutive one-vector products walk the stored tiles in opposite
+    # orders; every tile writes its own partial slots, so the results are
+    # bit-identical
+    again = [ctx.apply(_cuda(v)).cpu().numpy().reshape(w.n, 3) for _ in range(3)]
+    assert all(np.array_equal(a, out) for a in again)
     # N_Ch = 2: dS = c0/2 dW + c1 Y dW, rows from the oracle's rows of D
     lo, hi = 0.02, 20.0
     dw = w.noise()
