@@ -35,17 +35,17 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "a888d46cf20503e9494a1a4522999fd63e09cb1372f9568b7b2c4a30310c8396",
+TRAFFIC = {"src_sha256": "b3eb01a5de67861dcb391e0f4803f214bf365d2fe8dce41c897a2a62f58d2d93",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 411374571}
-TRAFFIC_BLOCK = {"src_sha256": "fdf70b4d9eb56de94a3b3d7182c671a37de09f487260541b2d4f00ac198b995e",
+           "bytes_per_launch": 411362100}
+TRAFFIC_BLOCK = {"src_sha256": "842b53788719ae2a14959b0f0bb3058b454e8624c341c7aaf19b65d3d8769d56",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f32": 312425130 + 48771072, "bf16": 159588026 + 48771072}}
+                 "bytes_per_launch": {"f32": 312264793 + 48771072, "bf16": 159680915 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "0dd29d542bb3f1f6605d671f5b959d025b11065892315c74d662928e3cfd9b14",
+TRAFFIC_BATCH = {"src_sha256": "049c8ee2989ba340a7a682f8e0ff3480dd425c559feec89a08fae710e4776f2f",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4931230504}
+                 "bytes_per_launch": 4931231300}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 

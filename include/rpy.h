@@ -303,7 +303,11 @@ int rpy_host_pair_block(const rpy_params *p, const double *d, int self,
  * recording; the events are kept until rpy_destroy).  rpy_profile_read
  * synchronises the device, returns the number of recorded launches of class
  * `kind` (RPY_PROF_*) and their summed duration in milliseconds (host
- * outputs), and resets that class.  Launches beyond cap are not recorded. */
+ * outputs), and resets that class.  Launches beyond cap are not recorded.
+ * Packed-tile products (RPY_PROF_SYMV with stored FP64/FP32/BF16 tiles, and
+ * RPY_PROF_SYMV_MULTI) have the pair recorded by their own dispatch, so it
+ * times the kernel alone; the other classes take it from two stream
+ * records around the launches. */
 enum {
     RPY_PROF_SYMV = 0,      /* tile product of one vector (+ structure-factor
                                partials), matrix-core block product,

@@ -388,14 +388,23 @@ struct ProfScope {
     ProfScope(rpy_ctx *x_, int k_, hipStream_t s_) : x(x_), k(k_), s(s_)
     {
         on = x->prof.cap > 0 && x->prof.n[k] < x->prof.cap;
-        if (on) (void)hipEventRecord(x->prof.ev[k][2 * x->prof.n[k]], s);
+        if (!on) return;
+        hipEvent_t *e = &x->prof.ev[k][2 * x->prof.n[k]];
+        (void)hipEventRecord(e[0], s);
+        if (k == RPY_PROF_SYMV || k == RPY_PROF_SYMV_MULTI) {
+            // a packed-tile launch in this scope takes the pair over and
+            // records it from its own dispatch (kernel time only)
+            x->c.prof_ev0 = e[0];
+            x->c.prof_ev1 = e[1];
+        }
     }
     ~ProfScope()
     {
-        if (on) {
-            (void)hipEventRecord(x->prof.ev[k][2 * x->prof.n[k] + 1], s);
-            ++x->prof.n[k];
-        }
+        if (!on) return;
+        const bool taken = (k == RPY_PROF_SYMV || k == RPY_PROF_SYMV_MULTI) && !x->c.prof_ev0;
+        x->c.prof_ev0 = x->c.prof_ev1 = nullptr;
+        if (!taken) (void)hipEventRecord(x->prof.ev[k][2 * x->prof.n[k] + 1], s);
+        ++x->prof.n[k];
     }
 };
 

@@ -386,6 +386,9 @@ struct Ctx {
     int n3pad;         // nbt * TS
     int nsfc;          // structure-factor bead chunks (SF_BEADS beads each)
     mutable unsigned symv_calls = 0;   // tile products launched (their parity sets the tile order)
+    // Set by the profiler around one tile-product launch: that launch records
+    // the pair itself (start and end of the kernel) and clears it.
+    mutable hipEvent_t prof_ev0 = nullptr, prof_ev1 = nullptr;
     // device buffers
     double *rt = nullptr;        // wrapped positions [N][3] of the built D
     double *rt_ev = nullptr;     // wrapped positions for stand-alone force calls
