@@ -35,17 +35,17 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "b3eb01a5de67861dcb391e0f4803f214bf365d2fe8dce41c897a2a62f58d2d93",
+TRAFFIC = {"src_sha256": "7e6ad28e37416205d1b0b7787e01b6f1dd3dcded8f9cdc3730f7f91559c12ff1",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 411362100}
-TRAFFIC_BLOCK = {"src_sha256": "842b53788719ae2a14959b0f0bb3058b454e8624c341c7aaf19b65d3d8769d56",
+           "bytes_per_launch": 411377165}
+TRAFFIC_BLOCK = {"src_sha256": "08c6b9fa089f12a8916ca35b0d01a6eedd435ae7f35f3519950f8b50dc2c6f92",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f32": 312264793 + 48771072, "bf16": 159680915 + 48771072}}
+                 "bytes_per_launch": {"f32": 312428486 + 48771072, "bf16": 159733814 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "049c8ee2989ba340a7a682f8e0ff3480dd425c559feec89a08fae710e4776f2f",
+TRAFFIC_BATCH = {"src_sha256": "733cc46850c2f62d0ad3c3f0ec07554155937491b7b1ee49058b1139a98bf04f",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4931231300}
+                 "bytes_per_launch": 4931232044}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 

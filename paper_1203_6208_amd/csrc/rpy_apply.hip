@@ -366,12 +366,15 @@ void launch_sf_reduce(const Ctx &c, int m, hipStream_t s)
 //                  dv = xs ya mu_p
 constexpr int EPI_BEADS = 16;
 constexpr int EPI_SLICES = 64;
-// When `staged` (nk <= 1024 and at most EPI_STAGE_PER x 1024 values of tk),
-// the wave vectors and this launch's 6 M values of tk per k are copied to LDS
-// once per workgroup -- [nk + 1] KVec then [nk][M][6] + 1 -- with every load
-// issued before the first LDS write (clamped indices; the copies of the
-// clamped loads land in the slack entries, so no write is conditional).
-constexpr int EPI_STAGE_PER = 6;
+// When `staged` (nk <= 1024, at most epi_stage_per<M>() x 1024 values of tk,
+// and the tables fit the workgroup's LDS), the wave vectors and this
+// launch's 6 M values of tk per k are copied to LDS once per workgroup --
+// [nk + 1] KVec then [nk][M][6] + 1 -- with every load issued before the
+// first LDS write (clamped indices; the copies of the clamped loads land in
+// the slack entries, so no write is conditional).  The per-thread counts
+// cover the 618 half-space wave vectors of alpha L = 6 for 1-4 vectors.
+template <int M> constexpr int epi_stage_per() { return M == 1 ? 6 : M == 2 ? 8 : M == 3 ? 11 : 15; }
+constexpr size_t EPI_RED_BYTES = sizeof(double) * 16 * 3 * EPI_BEADS;   // static `red`
 template <int M>
 __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, int nbt, int nk,
                                                      int nmax, int rhs_cap, int j0, int staged,
@@ -430,16 +433,17 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
         double *td = stage + 2 * (nk + 1);
         const int ntk = nk * 6 * M;
         const KVec kv0 = kvec[min((int)threadIdx.x, nk - 1)];
-        double tv[EPI_STAGE_PER];
+        constexpr int SP = epi_stage_per<M>();
+        double tv[SP];
 #pragma unroll
-        for (int i = 0; i < EPI_STAGE_PER; ++i) {
+        for (int i = 0; i < SP; ++i) {
             const int e = min((int)threadIdx.x + 1024 * i, ntk - 1);
             const int k = e / (6 * M), r = e % (6 * M);
             tv[i] = tk_g[((size_t)k * rhs_cap + j0) * 6 + r];
         }
         kd[min((int)threadIdx.x, nk)] = kv0;
 #pragma unroll
-        for (int i = 0; i < EPI_STAGE_PER; ++i) td[min((int)threadIdx.x + 1024 * i, ntk)] = tv[i];
+        for (int i = 0; i < SP; ++i) td[min((int)threadIdx.x + 1024 * i, ntk)] = tv[i];
     }
     __syncthreads();
     const int klo = (int)((long)u * nk / EPI_SLICES), khi = (int)((long)(u + 1) * nk / EPI_SLICES);
@@ -521,8 +525,9 @@ void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
     const size_t tabs = sizeof(double) * 2 * EPI_BEADS * 3 * (size_t)(c.nmax + 1);
     RPY_RHS_GROUPS(f.m, {
         const size_t lds = sizeof(double) * ((size_t)c.nk * (2 + 6 * MC) + 3);
-        const int staged = c.nk <= 1024 && (size_t)c.nk * 6 * MC <= 1024 * EPI_STAGE_PER &&
-                           tabs + lds <= 48 * 1024;
+        const int staged = c.nk <= 1024 &&
+                           (size_t)c.nk * 6 * MC <= (size_t)1024 * epi_stage_per<MC>() &&
+                           tabs + lds + EPI_RED_BYTES <= (size_t)c.lds_max;
         hipLaunchKernelGGL(k_kspace_epi<MC>, g, b, tabs + (staged ? lds : 0), s, c.N, c.n3,
                            c.n3pad, c.nslot, c.nk, c.nmax, c.rhs_cap, j0, staged, c.kvec, c.etab,
                            c.part, c.tk, f);

@@ -257,6 +257,13 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     c.rhs_cap = c.max_rhs > 3 ? c.max_rhs : 3;   // bd_step's product of [F, U+, dW]
     c.block = !c.lma && c.lowp != RPY_PREC_F64 && c.max_rhs >= BLOCK_MIN_RHS;
     if (c.block) c.rhs_cap = BLOCK_RHS;  // block kernels write all 16 columns
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            lds > 0)
+            c.lds_max = lds;
+    }
     c.pc = make_pair_const(c.L, c.a, c.alpha, c.rc);
     c.nbt = (c.N + TB - 1) / TB;
     c.ntiles = c.nbt * (c.nbt + 1) / 2;

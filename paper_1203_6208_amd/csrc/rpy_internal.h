@@ -385,6 +385,7 @@ struct Ctx {
     int ntiles;        // stored tiles
     int n3pad;         // nbt * TS
     int nsfc;          // structure-factor bead chunks (SF_BEADS beads each)
+    int lds_max = 48 * 1024;           // LDS bytes a workgroup may use on this device
     mutable unsigned symv_calls = 0;   // tile products launched (their parity sets the tile order)
     // Set by the profiler around one tile-product launch: that launch records
     // the pair itself (start and end of the kernel) and clears it.
