@@ -71,6 +71,7 @@ def _L():
             "orc_cheb_sqrt": (None, [i, p, i, p, i, d, d, p]),
             "orc_sqrt_error": (d, [i, p, p, p]),
             "orc_bounds_rule": (None, [i, p, d, p, p]),
+            "orc_bounds_dilute": (None, [i, p, p, p]),
             "orc_cheb_adaptive": (i, [i, p, i, p, i, i, d, d, d, p]),
             "orc_lanczos": (None, [i, p, p, i, p, p]),
             "orc_spring_forces": (None, [i, i, p, p]),
@@ -313,6 +314,15 @@ def bounds_rule(D, nbeads: int, C: float):
     D = _f64(D)
     lo, hi = ctypes.c_double(), ctypes.c_double()
     _L().orc_bounds_rule(int(nbeads), _ptr(D), C, ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
+
+
+def bounds_dilute(D, nbeads: int):
+    """Dilute rule (eq. lmax-lmin-dilute): d_max = 2 U+.D.U+/(3N),
+    d_min = U-.D.U-/(2 3N); returns (dmin, dmax)."""
+    D = _f64(D)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _L().orc_bounds_dilute(int(nbeads), _ptr(D), ctypes.byref(lo), ctypes.byref(hi))
     return lo.value, hi.value
 
 

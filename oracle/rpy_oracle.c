@@ -494,6 +494,24 @@ void orc_bounds_rule(int nbeads, const double *D, double C, double *dmin, double
     *dmin = lmax / (C * pow((double)nbeads, 0.6));
 }
 
+/* Dilute bound rule (eq. lmax-lmin-dilute): lmax_F = U+.D.U+/(3N) and
+ * lmin_F = U-.D.U-/(3N), U+ all ones, U- alternating 1, -1 over the
+ * flattened index 3 nu + i starting with +1, and the bounds the paper quotes
+ * with it: d_max = 2 lmax_F, d_min = lmin_F / 2. */
+void orc_bounds_dilute(int nbeads, const double *D, double *dmin, double *dmax)
+{
+    int n3 = 3 * nbeads;
+    double sp = 0.0, sm = 0.0;
+    for (long i = 0; i < n3; ++i)
+        for (long k = 0; k < n3; ++k) {
+            double ui = (i % 2 == 0) ? 1.0 : -1.0, uk = (k % 2 == 0) ? 1.0 : -1.0;
+            sp += D[i * n3 + k];
+            sm += ui * D[i * n3 + k] * uk;
+        }
+    *dmax = 2.0 * sp / n3;
+    *dmin = 0.5 * sm / n3;
+}
+
 /* Hookean spring forces (section "Governing equation"): beads are stored
  * chain after chain, bpc beads each; Q_mu = r_{mu+1} - r_mu (unwrapped);
  * F_mu = Q_mu - Q_{mu-1}.  F is overwritten. */

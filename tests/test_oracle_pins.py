@@ -314,6 +314,26 @@ def test_bounds_rule_isotropic(orc):
     assert abs(lo - hi / (8.0 * n ** 0.6)) < 1e-13
 
 
+def test_bounds_dilute_rule(orc):
+    """Dilute rule (eq. lmax-lmin-dilute, d_max = 2 lmax_F, d_min = lmin_F/2) on
+    D = I + e U+ U+^T with 3N even: U+.D.U+ = 3N + e (3N)^2 and, as U-.U+ = 0,
+    U-.D.U- = 3N; so d_max = 2 (1 + 3N e) and d_min = 1/2.  A sign pattern of
+    U- over beads instead of the flattened index, or swapped factors, fails."""
+    n, e = 6, 0.01
+    up = np.ones(3 * n)
+    lo, hi = orc.bounds_dilute(np.eye(3 * n) + e * np.outer(up, up), n)
+    assert abs(hi - 2 * (1 + 3 * n * e)) < 1e-13
+    assert abs(lo - 0.5) < 1e-13
+    # a D that separates the flattened-index pattern from a per-bead one:
+    # U-.D.U- picks up the x-y coupling inside each bead with a minus sign
+    D = np.eye(3 * n)
+    for b in range(n):
+        D[3 * b, 3 * b + 1] = D[3 * b + 1, 3 * b] = 0.25
+    lo, hi = orc.bounds_dilute(D, n)
+    assert abs(lo - 0.5 * (3 * n - 2 * 0.25 * n) / (3 * n)) < 1e-13
+    assert abs(hi - 2 * (3 * n + 2 * 0.25 * n) / (3 * n)) < 1e-13
+
+
 # ------------------------------------------------------------- forces etc.
 def test_spring_forces_are_minus_gradient(orc):
     """Hookean F = -grad U, U = sum_bonds |Q|^2 / 2 (section "Governing
@@ -437,3 +457,33 @@ def test_thread_count_leaves_results_unchanged(orc):
     R = orc.diffusion_rows(pos, rows, w.L, w.a, w.alpha, w.rc, w.n2max)
     assert np.array_equal(R, R1)
     assert np.array_equal(orc.rows_matvec(R, v), y1)
+
+
+def test_row_helpers_on_a_shuffled_row_list(orc):
+    """The row helpers that check the GPU at sizes where the dense oracle is
+    too costly (block rows of D for a list of beads, and the row-block
+    product) equal the dense matrices restricted to those rows, for a row
+    list that is shuffled, repeats a bead and skips others.  A helper that
+    took the position in the list for the bead index would agree only on the
+    list 0..N-1 that the dense routines use."""
+    w = inputs.workload("n100")
+    pos = w.positions()
+    rng = np.random.default_rng(20120328)
+    rows = list(rng.permutation(w.n)[:37]) + [5, 5, 99, 0]
+    assert rows != sorted(rows)
+    idx = np.concatenate([[3 * r, 3 * r + 1, 3 * r + 2] for r in rows])
+    D = orc.diffusion_matrix(pos, w.L, w.a, w.alpha, w.rc, w.n2max)
+    Drs = orc.real_space_matrix(pos, w.L, w.a, w.alpha, w.rc)
+    R = orc.diffusion_rows(pos, rows, w.L, w.a, w.alpha, w.rc, w.n2max)
+    Rrs = orc.real_space_rows(pos, rows, w.L, w.a, w.alpha, w.rc)
+    assert R.shape == (3 * len(rows), 3 * w.n)
+    # the real-space rows are summed by the same loop as the dense routine;
+    # the full rows add the reciprocal sum into the same array, where the
+    # dense routine adds two matrices, so they agree to rounding
+    assert np.array_equal(Rrs, Drs[idx])
+    assert np.max(np.abs(R - D[idx])) <= 1e-14 * np.max(np.abs(D))
+    v = rng.standard_normal(3 * w.n)
+    assert np.array_equal(orc.rows_matvec(D[idx], v), orc.matvec(D, v)[idx])
+    assert np.max(np.abs(orc.rows_matvec(R, v) - orc.matvec(D, v)[idx])) <= 1e-13
+    # and the restriction is not trivially satisfied: the rows differ
+    assert np.max(np.abs(D[idx] - D[:len(idx)])) > 1e-3
