@@ -107,12 +107,18 @@ NG_EV = {"zstar": 1.0, "dstar": 0.5, "rcut": 4.0}
 def workload(name: str) -> Workload:
     """The workloads: plain FP64 N=100 and N=1000, the precision form at
     N=4000, the differentiation form at N=2000, the theta-statics check
-    (batching boxes: batch_boxes)."""
+    (batching boxes: batch_boxes).
+
+    N=1000 takes M = alpha r_c = 4.6 so that both truncations of the Ewald
+    sum (section "Choice of Ewald parameters", eq. rparameter, kparameter)
+    leave less than 1e-6: erfc(M) = 8e-11 for the real-space cut, and for the
+    reciprocal cut the factor of eq. M2 at k = K = 2 alpha M,
+    (1 + M^2 + 2 M^4) e^{-M^2} = 5.9e-7 (at M = 3.5 it is 1.5e-3)."""
     base = POSITION_SEED_BASE
     if name == "n100":
         return Workload("n100", 10, 10, 1.0, nch=20, seed=base + 0)
     if name == "n1000":
-        return Workload("n1000", 40, 25, 1.0, nch=30, seed=base + 1)
+        return Workload("n1000", 40, 25, 1.0, M=4.6, nch=30, seed=base + 1)
     if name == "n4000":
         return Workload("n4000", 80, 50, 2.0, nch=30, ev=dict(NG_EV), seed=base + 2)
     if name == "n2000":
