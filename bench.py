@@ -2,16 +2,23 @@
 
 One step = the whole hot path of the semidilute Ewald-RPY Brownian-dynamics
 method (arXiv:1203.6208): wrap + cell list + spring and excluded-volume
-forces, real-space tile build of D, one FP64 product with [F, U+] (drift and
-the paper's bound rule), N_Ch - 1 = 29 Chebyshev products (each the stored
-real-space tiles plus the reciprocal sum), device noise and the Euler update.
-Inputs are resident in HBM before the timed region starts.
+forces, real-space tile build of D, the FP64 drift product D.F, the
+Chebyshev interval, the Fixman-Chebyshev products for sqrt(D).dW (each the
+stored real-space tiles plus the reciprocal sum), device noise and the Euler
+update.  Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line.  The headline `value` is the plain FP64 form; the FP32
-and BF16 product forms are reported under `forms` with their errors against
-the FP64 path.  `roofline` is for the dominant kernel (the symmetric tile
-product), timed live with HIP events on the stream the library launches on.
-`cpu_baseline` times the CPU oracle on a bounded sample of the same step.
+The headline `value` is the plain FP64 step at a stated accuracy of the
+square root: N_Ch from eq. nint, raised one term at a time until E_f < 1e-2
+(the paper's procedure, run on the device with no host synchronisation),
+on the interval of an FP64 Lanczos estimate of the extreme eigenvalues
+(5% margin) that is refreshed every 50 steps inside the timed region.  The
+fixed-order steps (N_Ch = 30 on the paper's bound rule, the configuration
+of the previous headline, and the paper's rule with the adaptive order) are
+reported beside it with their E_f; the FP32 and BF16 product forms under
+`forms`, with their errors against the FP64 oracle.  `roofline` is for the
+dominant kernel (the one-vector packed tile product), timed live with HIP
+events on the stream the library launches on.  `cpu_baseline` times the CPU
+oracle on a bounded sample of the same step.
 """
 from __future__ import annotations
 
@@ -48,6 +55,13 @@ TRAFFIC_BATCH = {"src_sha256": "733cc46850c2f62d0ad3c3f0ec07554155937491b7b1ee49
                  "bytes_per_launch": 4931232044}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
+TOL_EF = 1e-2     # E_f tolerance of the headline's adaptive order
+N_MAX = 160       # N_Ch the context keeps (the adaptive order's largest possible)
+SLACK = 12        # the adaptive search runs to eq. nint + SLACK at most
+LANCZOS_STEPS = 60
+LANCZOS_MARGIN = 0.05
+REFRESH = 50      # steps between Lanczos refreshes of the interval
+ORACLE_REF = os.path.join(ROOT, "tests", "golden", "n4000_oracle.npz")
 
 
 def parse():
@@ -76,38 +90,87 @@ def parse():
     return ap.parse_args()
 
 
-def run_steps(ctx, rpy, tpos, bp, k, seed0, torch):
-    for i in range(k):
-        ctx.step(tpos, bp, seed=seed0, step=i)
+class Stepper:
+    """bd_step on one context in one of the step configurations:
+      "adaptive"        Lanczos interval (refreshed every REFRESH steps, the
+                        refresh counted in the step that does it) + adaptive
+                        order to E_f < tol (the headline);
+      "paper_fixed"     paper's rule at C = BOUNDS_C, N_Ch = w.nch;
+      "paper_adaptive"  paper's rule at C = BOUNDS_C + adaptive order."""
+
+    def __init__(self, w, prec, kind, torch, rpy, tol=TOL_EF):
+        self.w, self.kind, self.rpy = w, kind, rpy
+        adapt = kind != "paper_fixed"
+        self.ctx = rpy.context_for(w, lowp=prec, cheb_keep=N_MAX if adapt else 0)
+        self.tpos = torch.from_numpy(w.positions()).cuda()
+        if kind == "paper_fixed":
+            self.bp = rpy.make_bd_params(dt=w.dt, n_cheb=w.nch, bounds_rule=rpy.BOUNDS_PAPER,
+                                         bounds_C=BOUNDS_C, prec=prec, ev=w.ev)
+        elif kind == "paper_adaptive":
+            # the rule fixes d_max / d_min = C N^0.6, hence eq. nint
+            n0 = math.floor(math.sqrt(BOUNDS_C * w.n ** 0.6) + 0.5) + 1
+            self.bp = rpy.make_bd_params(dt=w.dt, n_cheb=0, bounds_rule=rpy.BOUNDS_PAPER,
+                                         bounds_C=BOUNDS_C, prec=prec, ev=w.ev, tol=tol,
+                                         n_max=min(N_MAX, n0 + SLACK))
+        else:
+            self.bp = rpy.make_bd_params(dt=w.dt, n_cheb=0, bounds_rule=rpy.BOUNDS_EXPLICIT,
+                                         prec=prec, ev=w.ev, tol=tol, n_max=N_MAX)
+        self.i = 0
+
+    def refresh(self):
+        self.ctx.build(self.tpos)
+        lo, hi, _, _ = self.ctx.lanczos_bounds(LANCZOS_STEPS, seed=1000 + self.i,
+                                               margin=LANCZOS_MARGIN)
+        self.bp.d_min, self.bp.d_max = lo, hi
+        n0 = math.floor(math.sqrt(hi / lo) + 0.5) + 1   # eq. nint
+        self.bp.n_max = min(N_MAX, n0 + SLACK)
+
+    def step(self, seed, e_f=None):
+        if self.kind == "adaptive" and self.i % REFRESH == 0:
+            self.refresh()
+        self.ctx.step(self.tpos, self.bp, seed=seed, step=self.i, e_f=e_f)
+        self.i += 1
 
 
-def time_form(w, prec, steps, warmup, torch, rpy):
-    """Steps/s of bd_step with Chebyshev products in `prec`."""
-    ctx = rpy.context_for(w, lowp=prec, max_rhs=16)
-    tpos = torch.from_numpy(w.positions()).cuda()
-    bp = rpy.make_bd_params(dt=w.dt, n_cheb=w.nch, bounds_rule=rpy.BOUNDS_PAPER,
-                            bounds_C=BOUNDS_C, prec=prec, ev=w.ev)
-    run_steps(ctx, rpy, tpos, bp, warmup, 1, torch)
+def time_form(w, prec, steps, warmup, torch, rpy, kind="adaptive"):
+    """Steps/s of bd_step with Chebyshev products in `prec` in the step
+    configuration `kind`; E_f of every timed step is kept on the device."""
+    st = Stepper(w, prec, kind, torch, rpy)
+    for _ in range(warmup):
+        st.step(seed=1)
+    if kind != "paper_fixed":
+        st.ctx.order_stats()   # forget the warm-up orders
+    st.i = 0                    # the timed region starts with a refresh
+    efs = torch.empty(steps, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record()
     for i in range(steps):
-        ctx.step(tpos, bp, seed=2, step=i)
-    ev1.record()
+        st.step(seed=2, e_f=efs[i:i + 1])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    st = ctx.status()
-    return ctx, tpos, bp, wall, gpu_ms, st
+    status = st.ctx.status()
+    res = {"steps_per_s": steps / wall, "ms_per_step": 1e3 * wall / steps, "status": status,
+           "E_f_max": float(efs.max()), "E_f_mean": float(efs.mean())}
+    if kind == "paper_fixed":
+        res["n_cheb"] = w.nch
+    else:
+        calls, mean_n, max_n, missed = st.ctx.order_stats()
+        res.update({"n_cheb_mean": mean_n, "n_cheb_max": max_n, "tol": st.bp.tol,
+                    "missed_tol": missed, "adaptive_calls": calls})
+    if kind == "adaptive":
+        res.update({"interval": [st.bp.d_min, st.bp.d_max], "lanczos_steps": LANCZOS_STEPS,
+                    "refresh_every": REFRESH})
+    return st, wall, res
 
 
-def profile_pass(ctx, rpy, tpos, bp, steps, torch):
-    """Same loop with HIP event pairs around every launch, per kernel class."""
-    rpy.rpy_profile_enable(ctx.handle, 64 * steps + 64)
+def profile_pass(st, rpy, steps, torch):
+    """The same steps with HIP event pairs around every launch, per kernel
+    class (a Lanczos refresh falls outside: the pass starts mid-interval)."""
+    ctx = st.ctx
+    st.i = 1
+    rpy.rpy_profile_enable(ctx.handle, (N_MAX + 8) * steps + 64)
     for i in range(steps):
-        ctx.step(tpos, bp, seed=3, step=i)
+        st.step(seed=3)
     torch.cuda.synchronize()
     out = {}
     names = {rpy.PROF_SYMV: "tile_product", rpy.PROF_SYMV_MULTI: "tile_product_2_to_4_vectors",
@@ -121,38 +184,42 @@ def profile_pass(ctx, rpy, tpos, bp, steps, torch):
 
 
 def form_errors(w, torch, rpy):
-    """Errors of the FP32/BF16 product forms against the FP64 path on the same
-    state: drift D.F (always FP64), one bd_step's dS, and a 16-vector block of
-    sqrt(D) dW (m = 16)."""
+    """Error of each product precision against the FP64 oracle, at the
+    workload's initial state: D.F with the precision's stored tiles, and the
+    N_Ch = 30 Chebyshev sum p(D) dW on the paper's interval (C = 60) for one
+    dW and for the 16-vector block (the matrix-core block product in FP32 and
+    BF16).  The oracle's values are read from tests/golden/n4000_oracle.npz,
+    written by the oracle alone; they cover the block rows of every 8th bead,
+    over which the norm-wise relative errors ||y - y_oracle|| / ||y_oracle||
+    are taken.  (bd_step always takes its drift in FP64.)"""
+    ref = np.load(ORACLE_REF)
+    rows = torch.from_numpy(ref["rows"]).cuda()
+    lo, hi, nch = float(ref["dmin"]), float(ref["dmax"]), int(ref["n_cheb"])
     pos = torch.from_numpy(w.positions()).cuda()
     dw1 = torch.from_numpy(w.noise()[0]).cuda()
     dw16 = torch.from_numpy(w.noise(m=16)).cuda()
-    res = {}
-    ref = {}
+    cuda = {k: torch.from_numpy(ref[k]).cuda() for k in ("drift", "ds1", "ds16")}
+
+    def rel(a, b):
+        return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+    out = {"reference": "tests/golden/n4000_oracle.npz (CPU oracle, rows of every 8th bead)",
+           "interval": [lo, hi], "n_cheb": nch, "E_f_oracle_m1": float(ref["ef1"])}
     for prec in ("f64", "f32", "bf16"):
         ctx = rpy.context_for(w, lowp=prec, max_rhs=16)
-        p = pos.clone()
-        bp = rpy.make_bd_params(dt=w.dt, n_cheb=w.nch, bounds_rule=rpy.BOUNDS_PAPER,
-                                bounds_C=BOUNDS_C, prec=prec, ev=w.ev)
-        drift, noise, ef = ctx.step(p, bp, dw=dw1, want=True)
+        F = torch.empty_like(pos)
+        rpy.rpy_forces(ctx.handle, pos, w.ev["zstar"], w.ev["dstar"], w.ev["rcut"], F)
         ctx.build(pos)
-        lo, hi = ctx.bounds(BOUNDS_C)
-        blk = ctx.sqrt_apply(dw16, w.nch, lo, hi, prec=prec)
+        y = ctx.apply(F, prec=prec).reshape(w.n, 3)
+        ds1, ef1 = ctx.sqrt_apply(dw1, nch, lo, hi, prec=prec, want_ef=True)
+        ds16 = ctx.sqrt_apply(dw16, nch, lo, hi, prec=prec)
         torch.cuda.synchronize()
-        if prec == "f64":
-            ref = {"drift": drift, "dS": noise, "block": blk}
-            res[prec] = {"E_f": ef.item(), "d_min": lo, "d_max": hi}
-            continue
-
-        def rel(a, b):
-            return (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
-
-        res[prec] = {"rel_err_drift": rel(drift, ref["drift"]),
-                     "rel_err_dS": rel(noise, ref["dS"]),
-                     "rel_err_sqrtD_dW_m16": rel(blk, ref["block"]),
-                     "E_f": ef.item()}
+        out[prec] = {"rel_err_DF": rel(y[rows], cuda["drift"]),
+                     "rel_err_sqrtD_dW_m1": rel(ds1.reshape(w.n, 3)[rows], cuda["ds1"]),
+                     "rel_err_sqrtD_dW_m16": rel(ds16.reshape(16, w.n, 3)[:, rows], cuda["ds16"]),
+                     "E_f_m1": float(ef1[0])}
         del ctx
-    return res
+    return out
 
 
 def time_block(w, prec, reps, torch, rpy):
@@ -198,47 +265,75 @@ def time_block(w, prec, reps, torch, rpy):
 def eigen_study(w, torch, rpy):
     """Chebyshev interval and order at the bench state (section
     "Decomposition of the diffusion tensor"): FP64 Lanczos bounds (60 steps)
-    against the paper's rule at C = 8 and at the bench's C, the order of
-    eq. nint for each, and the order the adaptive procedure needs for
-    E_f < 1e-3 on one dW with the Lanczos interval."""
+    against the paper's rule at C = 8 and at the bench's C and against the
+    oracle's exact extreme eigenvalues (tests/golden/n4000_oracle.npz), the
+    order of eq. nint for each, and the order the adaptive procedure needs
+    for E_f < 1e-2 and 1e-3 on one dW with the Lanczos interval."""
+    ref = np.load(ORACLE_REF)
     ctx = rpy.context_for(w, max_rhs=1, cheb_keep=256)
     pos = torch.from_numpy(w.positions()).cuda()
     ctx.build(pos)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lo, hi, _, _ = ctx.lanczos_bounds(60, seed=1, margin=0.05)
+    lo, hi, _, _ = ctx.lanczos_bounds(LANCZOS_STEPS, seed=1, margin=LANCZOS_MARGIN)
     t_lz = time.perf_counter() - t0
-    out = {"lanczos_60": {"d_min": lo, "d_max": hi, "seconds": t_lz,
-                          "n_cheb_rule": math.floor(math.sqrt(hi / lo) + 0.5) + 1}}
+    out = {"exact_oracle": {"lambda_min": float(ref["lam_min"]), "lambda_max": float(ref["lam_max"]),
+                            "n_cheb_rule": math.floor(math.sqrt(ref["lam_max"] / ref["lam_min"])
+                                                      + 0.5) + 1},
+           f"lanczos_{LANCZOS_STEPS}": {"d_min": lo, "d_max": hi, "seconds": t_lz,
+                                        "margin": LANCZOS_MARGIN,
+                                        "n_cheb_rule": math.floor(math.sqrt(hi / lo) + 0.5) + 1}}
     for C in (8.0, BOUNDS_C):
         a, b = ctx.bounds(C)
         out[f"paper_rule_C{C:g}"] = {"d_min": a, "d_max": b,
                                      "n_cheb_rule": math.floor(math.sqrt(b / a) + 0.5) + 1}
+    a, b = ctx.bounds(0.0, rule=rpy.BOUNDS_DILUTE)
+    out["dilute_rule"] = {"d_min": a, "d_max": b,
+                          "n_cheb_rule": math.floor(math.sqrt(b / a) + 0.5) + 1}
     dw = torch.from_numpy(w.noise()[0]).cuda()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, ef, n = ctx.sqrt_adaptive(dw, lo, hi, 1e-3, 256, allow_etol=True)
-    t_ad = time.perf_counter() - t0
-    out["adaptive_tol_1e-3"] = {"n_cheb": n, "E_f": float(ef[0]), "seconds": t_ad}
-    # the FP64 step at stated accuracy: the Lanczos interval (computed once,
-    # held for the timed steps) with the order of eq. nint and with the
-    # adaptive order above
-    for tag, nch in (("step_lanczos_nint", out["lanczos_60"]["n_cheb_rule"]),
-                     ("step_lanczos_adaptive", n)):
-        bp = rpy.make_bd_params(dt=w.dt, n_cheb=nch, bounds_rule=rpy.BOUNDS_EXPLICIT,
-                                d_min=lo, d_max=hi, ev=w.ev)
-        p = pos.clone()
-        _, _, e_f = ctx.step(p, bp, seed=7, step=0, want=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(10):
-            ctx.step(p, bp, seed=7, step=1 + i)
-        torch.cuda.synchronize()
-        dt_s = (time.perf_counter() - t0) / 10
-        out[tag] = {"n_cheb": nch, "E_f": float(e_f[0]), "steps_per_s": 1.0 / dt_s,
-                    "ms_per_step": 1e3 * dt_s}
+    for tol in (1e-2, 1e-3):
+        _, ef, n = ctx.sqrt_apply(dw, 256, lo, hi, tol=tol, want_ef=True, want_n=True,
+                                  allow_etol=True)
+        out[f"adaptive_tol_{tol:g}"] = {"n_cheb": n, "E_f": float(ef[0])}
     del ctx
     return out
+
+
+def trajectory_n1000(torch, rpy, inputs, steps=1000, refresh=100):
+    """The N = 1000 workload (40 chains x 25 beads, c/c* = 1, alpha r_c =
+    4.6): `steps` FP64 steps with D rebuilt every step, N_Ch = 30 on a
+    Lanczos interval (60 steps, 5% margin) refreshed every `refresh` steps,
+    device noise.  Steps/s, the E_f of every step, the status, and the chain
+    averages of R_e^2 and R_g^2 (section "Testing and verification") at the
+    start and at the end.  Its first five steps are compared with the oracle
+    trajectory in tests/test_gpu_fullsize.py."""
+    w = inputs.workload("n1000")
+    ctx = rpy.context_for(w)
+    tpos = torch.from_numpy(w.positions()).cuda()
+    bp = rpy.make_bd_params(dt=w.dt, n_cheb=w.nch, bounds_rule=rpy.BOUNDS_EXPLICIT)
+    re0, rg0 = ctx.observables(tpos)
+    efs = torch.empty(steps, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        if i % refresh == 0:
+            ctx.build(tpos)
+            lo, hi, _, _ = ctx.lanczos_bounds(LANCZOS_STEPS, seed=2000 + i, margin=LANCZOS_MARGIN)
+            bp.d_min, bp.d_max = lo, hi
+        ctx.step(tpos, bp, seed=11, step=i, e_f=efs[i:i + 1])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    re2, rg2 = ctx.observables(tpos)
+    st = ctx.status()
+    del ctx
+    return {"workload": "n1000: 40 x 25 beads, c/c*=1, h*=0.28, theta (no EV), alpha L=6, "
+                        "alpha r_c=4.6, N_Ch=30, dt=1e-3",
+            "steps": steps, "seconds": wall, "steps_per_s": steps / wall, "status": st,
+            "lanczos_refresh_every": refresh, "E_f_max": float(efs.max()),
+            "E_f_mean": float(efs.mean()),
+            "Re2_mean": [float(re0.mean()), float(re2.mean())],
+            "Rg2_mean": [float(rg0.mean()), float(rg2.mean())],
+            "Re2_theta": 3.0 * (w.bpc - 1), "Rg2_theta": inputs.theta_rg2(w.bpc)}
 
 
 def batch_study(torch, rpy, inputs, steps=5, per_box=True):
@@ -662,43 +757,53 @@ def main():
     w = inputs.workload("n4000")
     print(f"# workload n4000 N={w.n} L={w.L:.4f} alpha={w.alpha:.5f} rc={w.rc:.4f} "
           f"n2max={w.n2max}", file=sys.stderr, flush=True)
-    ctx, tpos, bp, wall, gpu_ms, st = time_form(w, "f64", args.steps, args.warmup, torch, rpy)
+    st, wall, head = time_form(w, "f64", args.steps, args.warmup, torch, rpy, kind="adaptive")
     ms_step = 1e3 * wall / args.steps
     value = args.steps / wall
-    print(f"# f64: {ms_step:.3f} ms/step (events {gpu_ms / args.steps:.3f}) status={st}",
-          file=sys.stderr, flush=True)
-    prof = profile_pass(ctx, rpy, tpos, bp, args.steps, torch)
+    print(f"# f64 headline: {json.dumps(head)}", file=sys.stderr, flush=True)
+    prof = profile_pass(st, rpy, min(args.steps, 20), torch)
+    del st
     alg_bytes = tile_bytes(w.n, "f64")
     sym = prof["tile_product"]
     achieved = alg_bytes / (sym["avg_us"] * 1e-6) / 1e9
     print(f"# profile {json.dumps(prof)}", file=sys.stderr, flush=True)
+    configs = {"adaptive_lanczos": head}
     forms = {}
     if not args.no_forms:
+        for kind in ("paper_fixed", "paper_adaptive"):
+            s2, _, r2 = time_form(w, "f64", args.steps, args.warmup, torch, rpy, kind=kind)
+            del s2
+            configs[kind] = r2
+            print(f"# f64 {kind}: {json.dumps(r2)}", file=sys.stderr, flush=True)
         for prec in ("f32", "bf16"):
-            c2, tp2, bp2, wl2, g2, st2 = time_form(w, prec, args.steps, args.warmup, torch, rpy)
-            pr2 = profile_pass(c2, rpy, tp2, bp2, max(4, args.steps // 5), torch)
-            forms[prec] = {"steps_per_s": args.steps / wl2, "ms_per_step": 1e3 * wl2 / args.steps,
-                           "speedup_vs_f64": (args.steps / wl2) / value,
-                           "tile_product_avg_us": pr2["tile_product"]["avg_us"],
-                           "tile_product_GBs": tile_bytes(w.n, prec)
-                           / (pr2["tile_product"]["avg_us"] * 1e-6) / 1e9}
-            del c2
-            print(f"# {prec}: {forms[prec]}", file=sys.stderr, flush=True)
+            forms[prec] = {}
+            for kind in ("adaptive", "paper_fixed"):
+                s2, _, r2 = time_form(w, prec, args.steps, args.warmup, torch, rpy, kind=kind)
+                pr2 = profile_pass(s2, rpy, max(4, min(args.steps, 20) // 2), torch)
+                del s2
+                r2["speedup_vs_f64_same_configuration"] = (
+                    r2["steps_per_s"] / configs["adaptive_lanczos" if kind == "adaptive"
+                                                else kind]["steps_per_s"])
+                r2["tile_product_avg_us"] = pr2["tile_product"]["avg_us"]
+                r2["tile_product_GBs"] = (tile_bytes(w.n, prec)
+                                          / (pr2["tile_product"]["avg_us"] * 1e-6) / 1e9)
+                forms[prec][kind] = r2
+                print(f"# {prec} {kind}: {json.dumps(r2)}", file=sys.stderr, flush=True)
         for prec in ("f64", "f32", "bf16"):
             forms.setdefault(prec, {})["block_m16"] = time_block(w, prec, 5, torch, rpy)
             print(f"# block m16 {prec}: {forms[prec]['block_m16']}", file=sys.stderr, flush=True)
         errs = form_errors(w, torch, rpy)
-        for k, v in errs.items():
-            forms.setdefault(k, {}).update(v)
-        forms["f64"].update({"steps_per_s": value, "ms_per_step": ms_step})
+        print(f"# errors vs oracle {json.dumps(errs)}", file=sys.stderr, flush=True)
+        forms["errors_vs_oracle"] = errs
     studies = not (args.no_forms or args.no_studies)
     eigen = eigen_study(w, torch, rpy) if studies else None
     if eigen:
         print(f"# eigen {eigen}", file=sys.stderr, flush=True)
-    batch = None
     if studies:
-        del ctx, tpos
         torch.cuda.empty_cache()
+        traj = trajectory_n1000(torch, rpy, inputs)
+        print(f"# trajectory n1000 {traj}", file=sys.stderr, flush=True)
+        forms["trajectory_n1000"] = traj
         batch = batch_study(torch, rpy, inputs)
         print(f"# batch {batch}", file=sys.stderr, flush=True)
         forms["batched_256_boxes"] = batch
@@ -715,14 +820,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": "n4000: 80 chains x 50 beads, c/c*=2, h*=0.28, narrow-Gaussian "
                                "excluded volume z*=1 d*=0.5, alpha L=6, alpha r_c=3.5, "
-                               "k_c=2 alpha M (618 half-space k), N_Ch=30, dt=1e-3, paper "
-                               f"bound rule C={BOUNDS_C:g}, device Philox noise",
-                   "n_beads": w.n, "n_cheb": w.nch, "box_l": w.L, "parallelism": "single GPU"},
+                               "k_c=2 alpha M (618 half-space k), dt=1e-3, device Philox noise; "
+                               f"N_Ch by eq. nint raised until E_f < {TOL_EF:g} on an FP64 "
+                               f"Lanczos interval ({LANCZOS_STEPS} steps, "
+                               f"{LANCZOS_MARGIN:g} margin) refreshed every {REFRESH} steps",
+                   "n_beads": w.n, "n_cheb_mean": head["n_cheb_mean"],
+                   "E_f_tol": TOL_EF, "box_l": w.L, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_symv6<1> (packed symmetric tile product, FP64, m=1)",
+                     "kernel": "k_symv6<double,1> (packed symmetric tile product, FP64, m=1)",
+                     "memory": "effective bandwidth: the 384 MB tile array is read with "
+                               "allocating loads, the tile order reversed on every other launch, "
+                               "so part of it comes from the 256 MB Infinity Cache",
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_us": sym["avg_us"], "launches": sym["launches"]},
+        "step_configurations": configs,
         "kernels": prof,
         "forms": forms,
         "eigen": eigen,

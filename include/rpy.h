@@ -45,11 +45,17 @@ enum {
  * Chebyshev recurrence and all accumulation across tiles stay FP64). */
 enum { RPY_PREC_F64 = 0, RPY_PREC_F32 = 1, RPY_PREC_BF16 = 2 };
 
-/* Chebyshev interval: explicit [d_min, d_max], or the paper's semidilute
- * rule (section "Decomposition of the diffusion tensor", eq. lmax-lmin-dilute,
- * fmax, fmin): lmax = 0.35 N^0.6 U+.D.U+/(3N), d_max = lmax,
- * d_min = lmax / (C N^0.6). */
-enum { RPY_BOUNDS_EXPLICIT = 0, RPY_BOUNDS_PAPER = 1 };
+/* Chebyshev interval (section "Decomposition of the diffusion tensor"):
+ *  RPY_BOUNDS_EXPLICIT  the caller's [d_min, d_max];
+ *  RPY_BOUNDS_PAPER     the paper's semidilute rule (eq. lmax-lmin-dilute,
+ *                       fmax, fmin): lmax = 0.35 N^0.6 U+.D.U+/(3N),
+ *                       d_max = lmax, d_min = lmax / (C N^0.6);
+ *  RPY_BOUNDS_DILUTE    the dilute rule of eq. lmax-lmin-dilute with the
+ *                       factors the paper quotes for it: d_max = 2 U+.D.U+/(3N),
+ *                       d_min = U-.D.U-/(2 3N), U+ all ones, U- alternating
+ *                       +1, -1 over the flattened index 3 nu + i.
+ * The rules cost one FP64 product with U+ (and U-). */
+enum { RPY_BOUNDS_EXPLICIT = 0, RPY_BOUNDS_PAPER = 1, RPY_BOUNDS_DILUTE = 2 };
 
 /* Problem statement (sections "Governing equation" and "Implementation of
  * the Ewald sum"): N beads in a cubic periodic box of side box_l; bead radius
@@ -68,10 +74,11 @@ typedef struct {
                           (1..16); with lowp FP32/BF16 and max_rhs >= 5 the
                           context also holds the buffers of the matrix-core
                           block product (about 100 MB at N = 4000) */
-    int32_t cheb_keep; /* Chebyshev vectors V_p kept for
-                          chebyshev_sqrt_adaptive and rpy_u_vjp (0 disables
-                          that call; at most 512): cheb_keep x max(max_rhs, 2)
-                          x 3N doubles */
+    int32_t cheb_keep; /* Chebyshev vectors V_p kept for the adaptive order
+                          (bd_step and chebyshev_sqrt_apply with tol > 0,
+                          chebyshev_sqrt_adaptive) and rpy_u_vjp: the largest
+                          order those calls may use (0 disables them; at most
+                          512); cheb_keep x max(max_rhs, 4) x 3N doubles */
     int32_t grad;      /* 1: also hold the buffers of rpy_u_vjp (a W
                           matrix on the upper tiles, row-major, about
                           9N^2/2 doubles, and 2 cheb_keep + 4 vectors of
@@ -132,26 +139,41 @@ int rpy_ewald_build(rpy_ctx *c, const double *pos, void *stream);
 int rpy_apply(rpy_ctx *c, const double *v, double *out, int m, int prec,
               void *stream);
 
-/* Chebyshev interval by the paper's rule from the last build (one FP64
- * product with U+).  d_min, d_max: HOST outputs.  Synchronises the stream;
- * returns RPY_ENONFINITE if the last build saw a non-finite position. */
-int rpy_bounds(rpy_ctx *c, double C, double *d_min, double *d_max,
+/* Chebyshev interval by rule (RPY_BOUNDS_PAPER with constant C, or
+ * RPY_BOUNDS_DILUTE, C unused) from the last build: one FP64 product with U+
+ * (and U-).  d_min, d_max: HOST outputs.  Synchronises the stream; returns
+ * RPY_EINVAL for another rule or C <= 0 with the paper's rule, and
+ * RPY_ENONFINITE if the last build saw a non-finite position. */
+int rpy_bounds(rpy_ctx *c, int rule, double C, double *d_min, double *d_max,
                void *stream);
 
 /* Fixman-Chebyshev Brownian term (section "Decomposition of the diffusion
- * tensor", eq. cheb1-cheb3): out = sum_{p<n_cheb} c_p V_p - (c_0/2) dW with
+ * tensor", eq. cheb1-cheb3): out = sum_{p<N_Ch} c_p V_p - (c_0/2) dW with
  * V_0 = dW, V_1 = Y V_0, V_p = 2 Y V_{p-1} - V_{p-2},
  * Y = (2 D - (d_max + d_min) I) / (d_max - d_min), c_p the coefficients of
- * the interpolant of sqrt at the n_cheb Chebyshev-Gauss nodes of
- * [d_min, d_max].  dw, out: device [m][N][3], not aliased.  The n_cheb - 1
- * products use `prec` for the stored real-space part.  e_f: optional device
- * [m] output of the error estimate
+ * the interpolant of sqrt at the N_Ch Chebyshev-Gauss nodes of
+ * [d_min, d_max].  dw, out: device [m][N][3], not aliased.  The N_Ch - 1
+ * products use `prec` for the stored real-space part.
+ *  tol <= 0: N_Ch = n_cheb.
+ *  tol > 0: the paper's adaptive order (eq. nint, then the E_f criterion):
+ *    N_Ch starts at nint(sqrt(d_max/d_min)) + 1 (rounded half away from zero,
+ *    at least 2) and grows by one term -- one more product and a new sum of
+ *    the kept V_p with the coefficients of the new order -- until
+ *    E_f < tol for every right-hand side, or N_Ch = n_cheb, the largest order
+ *    tried (needs cheb_keep >= n_cheb).  The whole search is enqueued at once;
+ *    on the device the products and sums past the settled order return at
+ *    once, so the call does not synchronise unless n_used is requested.  A
+ *    tolerance still missed at n_cheb is reported as RPY_ETOL by this call
+ *    when n_used is given, else by the next rpy_status (outputs written).
+ * n_used: optional HOST output, the N_Ch used (synchronises the stream when
+ * tol > 0).  e_f: optional device [m] output of the error estimate
  * E_f = sqrt(|dS.dS - dW.D.dW| / dW.D.dW) per right-hand side.
  * Errors: RPY_EINVAL for n_cheb < 2, d_min <= 0, d_min >= d_max, m outside
- * 1..max_rhs, prec not built. */
+ * 1..max_rhs, prec not built, a non-finite tol, or tol > 0 with
+ * n_cheb > cheb_keep. */
 int chebyshev_sqrt_apply(rpy_ctx *c, const double *dw, double *out, int m,
-                         int n_cheb, double d_min, double d_max, int prec,
-                         double *e_f, void *stream);
+                         int n_cheb, double d_min, double d_max, double tol,
+                         int prec, int *n_used, double *e_f, void *stream);
 
 /* Eigenvalue bounds of D of the last build by the Lanczos recurrence in FP64
  * (the interval of eq. cheb3 must satisfy d_max >= lambda_max and
@@ -171,16 +193,13 @@ int rpy_lanczos_bounds(rpy_ctx *c, int n_iter, uint64_t seed, const double *star
                        double margin, double *d_min, double *d_max, double *alpha,
                        double *beta, void *stream);
 
-/* Fixman-Chebyshev Brownian term with the paper's adaptive order (eq. nint,
- * then the E_f criterion): N_Ch starts at n_start (or, if n_start < 2, at
- * nint(sqrt(d_max/d_min)) + 1, rounding half away from zero), and grows by one
- * term at a time -- each step one more product and a re-summation of the kept
- * V_p with the coefficients of the new order -- until
- * E_f < tol for every right-hand side or N_Ch = n_max.  n_used: HOST output,
- * the final N_Ch; e_f: optional device [m] output.  Synchronises the stream
- * once per trial order.  Needs cheb_keep >= n_max.  Returns RPY_ETOL (outputs
- * written) if E_f >= tol at n_max; RPY_EINVAL as chebyshev_sqrt_apply, for
- * tol <= 0, or n_max outside 2..cheb_keep. */
+/* The adaptive order of chebyshev_sqrt_apply with an explicit first order:
+ * N_Ch starts at n_start (or, if n_start < 2, at eq. nint) and grows by one
+ * term until E_f < tol for every right-hand side or N_Ch = n_max.  n_used:
+ * HOST output, the final N_Ch; e_f: optional device [m] output.  Synchronises
+ * the stream once, at the end.  Needs cheb_keep >= n_max.  Returns RPY_ETOL
+ * (outputs written) if E_f >= tol at n_max; RPY_EINVAL as
+ * chebyshev_sqrt_apply, for tol <= 0, or n_max outside 2..cheb_keep. */
 int chebyshev_sqrt_adaptive(rpy_ctx *c, const double *dw, double *out, int m,
                             int n_start, int n_max, double d_min, double d_max,
                             double tol, int prec, int *n_used, double *e_f,
@@ -197,13 +216,25 @@ int chebyshev_sqrt_adaptive(rpy_ctx *c, const double *dw, double *out, int m,
  * from (seed, step) with Philox4x32-10 and Box-Muller (the mapping of
  * rpy_gaussian_noise with count 3N).
  * pos: device [N][3], updated in place.  drift, noise, e_f: optional device
- * outputs ([N][3] D.F, [N][3] dS, [1] E_f).  Bounds follow bounds_rule.
+ * outputs ([N][3] D.F, [N][3] dS, [1] E_f).  The interval follows
+ * bounds_rule, computed on the device from this step's D.
+ * Order: tol <= 0 takes N_Ch = n_cheb.  tol > 0 takes the paper's adaptive
+ * order as chebyshev_sqrt_apply does -- N_Ch starts at n_cheb if >= 2, else at
+ * eq. nint on this step's interval, and grows by one term until E_f < tol or
+ * N_Ch = n_max (needs 2 <= n_max <= cheb_keep) -- with no host
+ * synchronisation; a missed tolerance is counted and reported as RPY_ETOL by
+ * rpy_status, and rpy_order_stats reports the orders used.
  * prec selects the arithmetic of the Chebyshev products; the drift and the
  * bounds always use FP64.  The forces and the device noise run on a second
  * stream owned by the context, forked from `stream` after the wrap and
  * joined back before the drift product (event record / wait, no host
  * synchronisation), so that they overlap the tile build; everything the call
- * enqueues is ordered before later work on `stream`. */
+ * enqueues is ordered before later work on `stream`.
+ * Errors: RPY_EINVAL for dt <= 0, an unknown rule, C <= 0 with the paper's
+ * rule, an invalid explicit interval, n_cheb outside 2..512 with tol <= 0,
+ * n_max outside 2..cheb_keep with tol > 0, prec not built, or invalid
+ * excluded-volume parameters (ev_zstar > 0 needs ev_dstar > 0 and
+ * 0 < ev_rcut < L/2). */
 typedef struct {
     double dt;
     double ev_zstar;    /* 0 disables excluded volume */
@@ -212,10 +243,11 @@ typedef struct {
     double bounds_C;    /* C of the paper's rule */
     double d_min;       /* explicit bounds (RPY_BOUNDS_EXPLICIT) */
     double d_max;
-    int32_t n_cheb;
+    double tol;         /* E_f tolerance of the adaptive order; <= 0: fixed order */
+    int32_t n_cheb;     /* fixed N_Ch; with tol > 0 the first order (< 2: eq. nint) */
     int32_t bounds_rule;
     int32_t prec;
-    int32_t reserved;
+    int32_t n_max;      /* with tol > 0: the largest N_Ch tried */
 } bd_params;
 
 int bd_step(rpy_ctx *c, double *pos, const bd_params *bp, const double *dw,
@@ -260,8 +292,18 @@ int rpy_forces_vjp(rpy_ctx *c, const double *pos, double zstar, double dstar,
                    double rcut, const double *gF, double *g_pos, void *stream);
 
 /* Synchronise the stream and report a non-finite position seen by an
- * earlier build (RPY_ENONFINITE, flag then cleared) or RPY_OK. */
+ * earlier build (RPY_ENONFINITE, flag then cleared), else an adaptive order
+ * that missed its tolerance at its largest order since the last call
+ * (RPY_ETOL, count then cleared), else RPY_OK. */
 int rpy_status(rpy_ctx *c, void *stream);
+
+/* Orders used by the adaptive calls (bd_step, chebyshev_sqrt_apply and
+ * chebyshev_sqrt_adaptive with tol > 0) settled since the last read: their
+ * number, mean and largest N_Ch, and how many stopped at their largest order
+ * with E_f >= tol (HOST outputs).  Synchronises the stream and resets the
+ * counts. */
+int rpy_order_stats(rpy_ctx *c, int64_t *calls, double *mean_order,
+                    int *max_order, int64_t *missed, void *stream);
 
 /* Copy the stored real-space part of D (FP64) into a dense row-major
  * device buffer out[3N][3N]. */
@@ -390,7 +432,8 @@ int rpy_batch_chebyshev(rpy_batch *b, const double *dw, double *out,
  * interval + coefficients per box, noise from Philox4x32-10 with the mapping
  * of rpy_gaussian_noise over all 3G padded entries (padding entries zero),
  * Chebyshev products in bp->prec, Euler update of the real beads.
- * bp->ev_zstar must be 0.  drift, noise: optional device [G][3]; e_f:
+ * bp->ev_zstar must be 0, bp->tol <= 0 (a fixed order n_cheb) and the rule
+ * RPY_BOUNDS_EXPLICIT or RPY_BOUNDS_PAPER.  drift, noise: optional device [G][3]; e_f:
  * optional device [nbox]. */
 int rpy_batch_step(rpy_batch *b, double *pos, const bd_params *bp,
                    uint64_t seed, uint64_t step, double *drift, double *noise,

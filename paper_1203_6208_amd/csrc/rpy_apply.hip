@@ -115,9 +115,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
                                                const int2 *__restrict__ tile_ij,
                                                const T *__restrict__ tiles,
                                                const double *__restrict__ v,
-                                               double *__restrict__ part)
+                                               double *__restrict__ part,
+                                               const int *__restrict__ gate)
 {
     extern __shared__ double smem[];
+    if (gate && *gate) return;   // a product past the settled adaptive order
     if ((int)blockIdx.x < nsf) {
         sf_partial_block<M>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
                             sfpart, smem);
@@ -254,12 +256,12 @@ static void symv_launch(const Ctx &c, const T *tiles, const double *v, int j0, h
         hipExtLaunchKernelGGL((k_symv6<T, M, true>), dim3(nsf + c.ntiles), dim3(256),
                               (uint32_t)lds, s, e0, e1, 0u, c.N, c.n3, c.n3pad, c.rhs_cap, j0, nsf,
                               flip, nkb, c.nk, c.nmax, c.kvec, c.etab, c.sfpart, c.tile_ij, tiles, v,
-                              c.part);
+                              c.part, c.gate);
     else
         hipExtLaunchKernelGGL((k_symv6<T, M, false>), dim3(nsf + c.ntiles), dim3(256),
                               (uint32_t)lds, s, e0, e1, 0u, c.N, c.n3, c.n3pad, c.rhs_cap, j0, nsf,
                               flip, nkb, c.nk, c.nmax, c.kvec, c.etab, c.sfpart, c.tile_ij, tiles, v,
-                              c.part);
+                              c.part, c.gate);
 }
 
 template <typename T>
@@ -292,9 +294,11 @@ void launch_symv(const Ctx &c, int prec, const double *v, int j0, int mc, hipStr
 __global__ __launch_bounds__(1024) void k_sf_reduce(int nk, int nsfc, int rhs_cap, int j0,
                                                     const KCoef *__restrict__ kcoef,
                                                     const double *__restrict__ sfpart,
-                                                    double *__restrict__ tk)
+                                                    double *__restrict__ tk,
+                                                    const int *__restrict__ gate)
 {
     __shared__ double red[16][3][16];
+    if (gate && *gate) return;
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int kk = lane & 15, sub = lane >> 4;
     const int k = blockIdx.x * 16 + kk;
@@ -345,7 +349,7 @@ void launch_sf_reduce(const Ctx &c, int m, hipStream_t s)
 {
     RPY_RHS_GROUPS(m, hipLaunchKernelGGL(k_sf_reduce, dim3((c.nk + 15) / 16, 2 * MC), dim3(1024),
                                          0, s, c.nk, c.nsfc, c.rhs_cap, j0, c.kcoef, c.sfpart,
-                                         c.tk));
+                                         c.tk, c.gate));
 }
 
 // ------------------------------------- reciprocal back-projection + epilogue
@@ -381,10 +385,12 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
                                                      const KVec *kvec,
                                                      const double2 *__restrict__ etab,
                                                      const double *__restrict__ part,
-                                                     const double *tk_g, EpiArgs f)
+                                                     const double *tk_g, EpiArgs f,
+                                                     const int *__restrict__ gate)
 {
     __shared__ double red[16][3][EPI_BEADS];
     extern __shared__ double lds[];
+    if (gate && *gate) return;
     const int nm1 = nmax + 1;
     double2 *tabs = reinterpret_cast<double2 *>(lds);          // [EPI_BEADS][3 nm1]
     double *stage = lds + 2 * EPI_BEADS * 3 * nm1;
@@ -530,7 +536,7 @@ void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
                            tabs + lds + EPI_RED_BYTES <= (size_t)c.lds_max;
         hipLaunchKernelGGL(k_kspace_epi<MC>, g, b, tabs + (staged ? lds : 0), s, c.N, c.n3,
                            c.n3pad, c.nslot, c.nk, c.nmax, c.rhs_cap, j0, staged, c.kvec, c.etab,
-                           c.part, c.tk, f);
+                           c.part, c.tk, f, c.gate);
     });
 }
 
@@ -539,49 +545,12 @@ void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
 // scal[3] = (d_max + d_min)/(d_max - d_min), scal[8 + p] = c_p with
 //   c_p = (2/n) sum_{j=1..n} sqrt(h x_j + m) cos(p theta_j),
 //   theta_j = pi (j - 1/2)/n, x_j = cos theta_j, h = (d_max-d_min)/2, m = (d_max+d_min)/2.
-// rule = RPY_BOUNDS_PAPER derives the interval from du = D.U+ first.  One
-// workgroup: a fixed-order tree reduction, then wave w sums the nodes of
-// coefficients p = w, w+16, ... with a lane-parallel sum.
-__global__ __launch_bounds__(1024) void k_cheb_coeffs(int nbeads, int n, int rule, double C,
-                                                      double dmin, double dmax,
-                                                      const double *__restrict__ du,
-                                                      double *__restrict__ scal)
+// One 1024-thread workgroup: wave w sums the nodes of coefficients
+// p = w, w+16, ... with a lane-parallel sum in a fixed order.
+__device__ void cheb_coeffs_block(int n, double lo, double hi, double *__restrict__ scal)
 {
-    __shared__ double red[1024];
-    __shared__ double bounds[2];
-    const int tid = threadIdx.x;
-    if (rule == RPY_BOUNDS_PAPER) {
-        const int n3 = 3 * nbeads;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int i = tid;
-        for (; i + 3 * 1024 < n3; i += 4 * 1024) {
-            s0 += du[i];
-            s1 += du[i + 1024];
-            s2 += du[i + 2048];
-            s3 += du[i + 3072];
-        }
-        for (; i < n3; i += 1024) s0 += du[i];
-        red[tid] = (s0 + s1) + (s2 + s3);
-        __syncthreads();
-        for (int h = 512; h > 0; h >>= 1) {
-            if (tid < h) red[tid] += red[tid + h];
-            __syncthreads();
-        }
-        if (tid == 0) {
-            const double lf = red[0] / n3;
-            const double np6 = pow((double)nbeads, 0.6);
-            const double lmax = 0.35 * np6 * lf;
-            bounds[0] = lmax / (C * np6);
-            bounds[1] = lmax;
-        }
-    } else if (tid == 0) {
-        bounds[0] = dmin;
-        bounds[1] = dmax;
-    }
-    __syncthreads();
-    const double lo = bounds[0], hi = bounds[1];
     const double h = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
-    const int lane = tid & 63, w = tid >> 6;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int p = w; p < n; p += 16) {
         double s = 0.0;
         for (int j = 1 + lane; j <= n; j += 64) {
@@ -592,6 +561,82 @@ __global__ __launch_bounds__(1024) void k_cheb_coeffs(int nbeads, int n, int rul
         for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
         if (lane == 0) scal[8 + p] = 2.0 * s / n;
     }
+}
+
+// The interval and the coefficients.  rule = RPY_BOUNDS_PAPER derives the
+// interval from du = D.U+ first, RPY_BOUNDS_DILUTE from du = [D.U+, D.U-]
+// (fixed-order tree reductions).  With st
+// (an adaptive call) the order is the call's first one, adapt_floor if >= 2
+// or else eq. nint, nint(sqrt(d_max/d_min)) + 1 rounded half away from zero,
+// clamped to [2, adapt_max]; the call's state is reset.
+__global__ __launch_bounds__(1024) void k_cheb_coeffs(int nbeads, int n, int rule, double C,
+                                                      double dmin, double dmax,
+                                                      const double *__restrict__ du,
+                                                      double *__restrict__ scal,
+                                                      int adapt_floor, int adapt_max,
+                                                      AdaptState *__restrict__ st)
+{
+    __shared__ double red[1024];
+    __shared__ double bounds[2];
+    __shared__ int order;
+    const int tid = threadIdx.x;
+    if (rule == RPY_BOUNDS_PAPER || rule == RPY_BOUNDS_DILUTE) {
+        // U.D.U / 3N for U+ (du[0 .. 3N)) and, for the dilute rule, U-
+        // (du[3N .. 6N) = D.U-, signs (-1)^i)
+        const int n3 = 3 * nbeads;
+        double uf[2];
+        for (int q = 0; q < (rule == RPY_BOUNDS_DILUTE ? 2 : 1); ++q) {
+            const double *d = du + (size_t)q * n3;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int i = tid;
+            for (; i + 3 * 1024 < n3; i += 4 * 1024) {
+                s0 += q && (i & 1) ? -d[i] : d[i];   // 1024 is even: the four share a sign
+                s1 += q && (i & 1) ? -d[i + 1024] : d[i + 1024];
+                s2 += q && (i & 1) ? -d[i + 2048] : d[i + 2048];
+                s3 += q && (i & 1) ? -d[i + 3072] : d[i + 3072];
+            }
+            for (; i < n3; i += 1024) s0 += q && (i & 1) ? -d[i] : d[i];
+            red[tid] = (s0 + s1) + (s2 + s3);
+            __syncthreads();
+            for (int h = 512; h > 0; h >>= 1) {
+                if (tid < h) red[tid] += red[tid + h];
+                __syncthreads();
+            }
+            uf[q] = red[0] / n3;
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (rule == RPY_BOUNDS_PAPER) {   // eq. fmax, fmin
+                const double np6 = pow((double)nbeads, 0.6);
+                const double lmax = 0.35 * np6 * uf[0];
+                bounds[0] = lmax / (C * np6);
+                bounds[1] = lmax;
+            } else {   // eq. lmax-lmin-dilute with d_max = 2 lmax, d_min = lmin / 2
+                bounds[0] = 0.5 * uf[1];
+                bounds[1] = 2.0 * uf[0];
+            }
+        }
+    } else if (tid == 0) {
+        bounds[0] = dmin;
+        bounds[1] = dmax;
+    }
+    __syncthreads();
+    const double lo = bounds[0], hi = bounds[1];
+    if (tid == 0) {
+        int k = n;
+        if (st) {
+            const double r = round(sqrt(hi / lo)) + 1.0;   // compared in FP64: no overflow
+            k = adapt_floor >= 2 ? adapt_floor : (r < (double)adapt_max ? (int)r : adapt_max);
+            k = k < 2 ? 2 : (k > adapt_max ? adapt_max : k);
+            st->done = 0;
+            st->n_used = 0;
+            st->n_start = k;
+            st->last_etol = 0;
+        }
+        order = k;
+    }
+    __syncthreads();
+    cheb_coeffs_block(order, lo, hi, scal);
     if (tid == 0) {
         scal[0] = lo;
         scal[1] = hi;
@@ -601,10 +646,123 @@ __global__ __launch_bounds__(1024) void k_cheb_coeffs(int nbeads, int n, int rul
 }
 
 void launch_cheb_coeffs(const Ctx &c, int n_cheb, int rule, double C, double dmin, double dmax,
-                        const double *du, hipStream_t s)
+                        const double *du, hipStream_t s, int adapt_floor, int adapt_max)
 {
     hipLaunchKernelGGL(k_cheb_coeffs, dim3(1), dim3(1024), 0, s, c.N, n_cheb, rule, C, dmin,
-                       dmax, du, c.scal);
+                       dmax, du, c.scal, adapt_floor, adapt_max,
+                       adapt_floor >= 0 ? c.adapt : nullptr);
+}
+
+// ------------------------------------------------------ adaptive order
+// Trial order n of an adaptive call (eq. nint, then the E_f criterion).
+// Both kernels return at once when the call's order is settled or n is below
+// its first order.  k_trial_sum: grid (chunks of 256 entries, m);
+//   dS = sum_{q<n} c_q V_q - (c_0/2) V_0      (eq. cheb1, c_q in scal[8..])
+// and the chunk's dS.dS and dW.(D dW) by a fixed-order tree.
+__global__ __launch_bounds__(256) void k_trial_sum(int n3, int n, size_t ps,
+                                                   const AdaptState *__restrict__ st,
+                                                   const double *__restrict__ scal,
+                                                   const double *__restrict__ vh,
+                                                   const double *__restrict__ ddw,
+                                                   double *__restrict__ ds,
+                                                   double *__restrict__ part)
+{
+    __shared__ double ra[256], rb[256];
+    if (st->done || n < st->n_start) return;
+    const int j = blockIdx.y, i = blockIdx.x * 256 + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (i < n3) {
+        const size_t o = (size_t)j * n3 + i;
+        const double v0 = vh[o];
+        double d = -0.5 * scal[8] * v0;
+        for (int q = 0; q < n; ++q) d += scal[8 + q] * vh[(size_t)q * ps + o];
+        ds[o] = d;
+        a = d * d;
+        b = v0 * ddw[o];
+    }
+    ra[threadIdx.x] = a;
+    rb[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            ra[threadIdx.x] += ra[threadIdx.x + h];
+            rb[threadIdx.x] += rb[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *o = part + ((size_t)j * gridDim.x + blockIdx.x) * 2;
+        o[0] = ra[0];
+        o[1] = rb[0];
+    }
+}
+
+// k_trial_check (one workgroup): the chunks summed in order per right-hand
+// side, E_f = sqrt(|dS.dS - dW.D.dW| / dW.D.dW); the order is settled when
+// every E_f < tol or n = nmax (e_f written, statistics updated, the ETOL
+// count raised when the tolerance was missed), else the coefficients of
+// order n + 1 replace those of order n.
+__global__ __launch_bounds__(1024) void k_trial_check(int m, int nchunk, int n, int nmax,
+                                                      double tol, AdaptState *__restrict__ st,
+                                                      const double *__restrict__ part,
+                                                      double *__restrict__ scal,
+                                                      double *__restrict__ e_f)
+{
+    __shared__ double ra[1024], rb[1024];
+    __shared__ double ef[MAX_RHS];
+    __shared__ int settle;
+    if (st->done || n < st->n_start) return;
+    const int tid = threadIdx.x;
+    for (int j = 0; j < m; ++j) {
+        double a = 0.0, b = 0.0;
+        for (int c = tid; c < nchunk; c += 1024) {
+            a += part[((size_t)j * nchunk + c) * 2];
+            b += part[((size_t)j * nchunk + c) * 2 + 1];
+        }
+        ra[tid] = a;
+        rb[tid] = b;
+        __syncthreads();
+        for (int h = 512; h > 0; h >>= 1) {
+            if (tid < h) {
+                ra[tid] += ra[tid + h];
+                rb[tid] += rb[tid + h];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) ef[j] = sqrt(fabs(ra[0] - rb[0]) / rb[0]);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double worst = 0.0;
+        for (int j = 0; j < m; ++j) worst = ef[j] > worst ? ef[j] : worst;
+        const bool ok = worst < tol;
+        settle = ok || n >= nmax;
+        if (settle) {
+            for (int j = 0; j < m; ++j) e_f[j] = ef[j];
+            st->done = 1;
+            st->n_used = n;
+            st->last_etol = ok ? 0 : 1;
+            if (!ok) {
+                st->etol += 1;
+                st->missed += 1;
+            }
+            st->calls += 1;
+            st->sum_orders += n;
+            if (n > st->max_order) st->max_order = n;
+        }
+    }
+    __syncthreads();
+    if (!settle) cheb_coeffs_block(n + 1, scal[0], scal[1], scal);
+}
+
+void launch_trial(const Ctx &c, int m, int n, int nmax, double tol, size_t ps,
+                  const double *ddw, double *ds, double *e_f, hipStream_t s)
+{
+    const int nchunk = (c.n3 + 255) / 256;
+    hipLaunchKernelGGL(k_trial_sum, dim3(nchunk, m), dim3(256), 0, s, c.n3, n, ps, c.adapt,
+                       c.scal, c.vhist, ddw, ds, c.tpart);
+    hipLaunchKernelGGL(k_trial_check, dim3(1), dim3(1024), 0, s, m, nchunk, n, nmax, tol,
+                       c.adapt, c.tpart, c.scal, e_f);
 }
 
 // E_f = sqrt(|dS.dS - dW.(D dW)| / dW.(D dW)), one workgroup per RHS.

@@ -1146,6 +1146,10 @@ static int bcheck_bd(const rpy_batch *b, const bd_params *bp)
         set_error("batched boxes run without excluded volume (ev_zstar must be 0)");
         return RPY_EINVAL;
     }
+    if (bp->tol > 0) {
+        set_error("batched boxes take a fixed Chebyshev order (tol must be <= 0)");
+        return RPY_EINVAL;
+    }
     if (bp->bounds_rule == RPY_BOUNDS_EXPLICIT)
         return (bp->d_min > 0 && bp->d_max > bp->d_min && isfinite(bp->d_max)) ? RPY_OK
                                                                              : RPY_EINVAL;

@@ -58,8 +58,10 @@ __device__ inline uint16_t bf16_rne(float f)
 // so that a lane's operand for 4 (8) consecutive rows of one vector is a
 // single 16-byte load, and 16 lanes read 16 vectors of one row together.
 __global__ void k_pack_block(int n3, int n3pad, int m, int bf16, const double *__restrict__ v,
-                             void *__restrict__ xpk, double *__restrict__ vpk)
+                             void *__restrict__ xpk, double *__restrict__ vpk,
+                             const int *__restrict__ gate)
 {
+    if (gate && *gate) return;   // a product past the settled adaptive order
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= n3pad * BLOCK_RHS) return;
     {
@@ -227,9 +229,11 @@ __global__ __launch_bounds__(256) void k_block_tiles(int n3pad, int m, int ntile
                                                      const int2 *__restrict__ tile_ij,
                                                      const void *__restrict__ tiles,
                                                      const void *__restrict__ xpk,
-                                                     float *__restrict__ part)
+                                                     float *__restrict__ part,
+                                                     const int *__restrict__ gate)
 {
     __shared__ float tbuf[4 * 16 * (BF16 ? TLD16 / 2 : TLD32)];
+    if (gate && *gate) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 15, g = lane >> 4;
     const int t = (int)blockIdx.x * 4 + w;
@@ -309,14 +313,14 @@ void launch_block_tiles(const Ctx &c, int prec, const double *v, int m, hipStrea
     const int bf16 = prec == RPY_PREC_BF16;
     const int np = c.n3pad * BLOCK_RHS;
     hipLaunchKernelGGL(k_pack_block, dim3((np + 255) / 256), dim3(256), 0, s, c.n3, c.n3pad, m,
-                       bf16, v, c.xpk, c.vpk);
+                       bf16, v, c.xpk, c.vpk, c.gate);
     const dim3 grid((c.ntiles + 3) / 4);
     if (bf16)
         hipLaunchKernelGGL(k_block_tiles<1>, grid, dim3(256), 0, s, c.n3pad, m, c.ntiles,
-                           c.tile_ij, (const void *)c.d16, (const void *)c.xpk, c.part32);
+                           c.tile_ij, (const void *)c.d16, (const void *)c.xpk, c.part32, c.gate);
     else
         hipLaunchKernelGGL(k_block_tiles<0>, grid, dim3(256), 0, s, c.n3pad, m, c.ntiles,
-                           c.tile_ij, (const void *)c.d32, (const void *)c.xpk, c.part32);
+                           c.tile_ij, (const void *)c.d32, (const void *)c.xpk, c.part32, c.gate);
 }
 
 // ------------------------------------------------- structure factors (FP64)
@@ -411,9 +415,11 @@ __global__ __launch_bounds__(256) void k_block_sf(int nk, int nk16, int nq, int 
                                                   const double2 *eph, const double *vpk,
                                                   double *sfpart,
                                                   const float *__restrict__ part,
-                                                  double *__restrict__ ypart)
+                                                  double *__restrict__ ypart,
+                                                  const int *__restrict__ gate)
 {
     __shared__ d4v red[SF_WAVES - 1][6][64];
+    if (gate && *gate) return;
     if ((int)blockIdx.x >= nkb) {
         const int b = (blockIdx.x - nkb) + blockIdx.y * (gridDim.x - nkb);
         if (16 * b < N) block_part_sum(b, N, n3, n3pad, m, nslot, part, ypart);
@@ -498,8 +504,10 @@ __global__ __launch_bounds__(256) void k_block_sf(int nk, int nk16, int nq, int 
 // Thread (k block, 2 j + half, k % 16); the chunks of one k block lie
 // together, 16 x 96 doubles apart.
 __global__ void k_block_sf_reduce(int nk, int nch, const KCoef *__restrict__ kcoef,
-                                  const double *__restrict__ sfpart, double *__restrict__ tkm)
+                                  const double *__restrict__ sfpart, double *__restrict__ tkm,
+                                  const int *__restrict__ gate)
 {
+    if (gate && *gate) return;
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     const int kb = o / (2 * BLOCK_RHS * 16), r = o % (2 * BLOCK_RHS * 16);
     const int q2 = r >> 4, kk = r & 15;           // q2 = 2 j + half
@@ -534,10 +542,10 @@ void launch_block_sf(const Ctx &c, int m, hipStream_t s)
     const int px = (npg + c.nchb - 1) / c.nchb;
     hipLaunchKernelGGL(k_block_sf, dim3(nkb + px, c.nchb), dim3(64 * SF_WAVES), 0, s, c.nk,
                        (c.nk + 15) / 16 * 16, nq, cq, nkb, c.N, c.n3, c.n3pad, m, c.nbt, c.eph,
-                       c.vpk, c.sfpart, c.part32, c.ypart);
+                       c.vpk, c.sfpart, c.part32, c.ypart, c.gate);
     const int nt = (c.nk + 15) / 16 * 2 * BLOCK_RHS * 16;
     hipLaunchKernelGGL(k_block_sf_reduce, dim3((nt + 255) / 256), dim3(256), 0, s, c.nk, c.nchb,
-                       c.kcoef, c.sfpart, c.tkm);
+                       c.kcoef, c.sfpart, c.tkm, c.gate);
 }
 
 // ------------------------------ back-projection + partial sum + epilogue
@@ -558,9 +566,10 @@ struct EpiLd {
 __global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int nk4, int nk16,
                                                           const double2 *eph, const double *tkm,
                                                           const double *__restrict__ ypart,
-                                                          EpiArgs f)
+                                                          EpiArgs f, const int *__restrict__ gate)
 {
     __shared__ double red[EPI_W][3][16][17];
+    if (gate && *gate) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 15, g = lane >> 4;
     const int nu0 = blockIdx.x * 16;
@@ -646,7 +655,7 @@ __global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int nk4
 void launch_block_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
 {
     hipLaunchKernelGGL(k_block_epi, dim3((c.N + 15) / 16), dim3(64 * EPI_W), 0, s, c.N, c.n3,
-                       c.nk4, (c.nk + 15) / 16 * 16, c.eph, c.tkm, c.ypart, f);
+                       c.nk4, (c.nk + 15) / 16 * 16, c.eph, c.tkm, c.ypart, f, c.gate);
 }
 
 }  // namespace rpy

@@ -24,7 +24,8 @@ struct rpy_ctx {
     Ctx c;
     Prof prof;
     double *F = nullptr;      // [3][3N]: forces, U+ (all ones), the step's dW
-    double *Y = nullptr;      // [3][3N]: D.F, D.U+, D.dW
+    double *Um = nullptr;     // [3N]: U- (alternating +1, -1 over the flattened index)
+    double *Y = nullptr;      // [4][3N]: D.F, then D.U+, D.U-, D.dW as the step needs them
     double *dW = nullptr;     // [3N]
     double *dS = nullptr;     // [3N]
     double *Bv[2] = {nullptr, nullptr};  // [max_rhs][3N] Chebyshev vectors
@@ -211,6 +212,7 @@ extern "C" void rpy_destroy(rpy_ctx *x)
                     c.d16, c.p32, c.p16, c.part, c.xpk, c.ypart,
                     c.vpk, c.part32, c.tkm,
                     c.sfpart, c.tk, c.sfr, c.work, c.scal, c.red, c.flags, c.cell_start, c.lanc,
+                    c.adapt, c.tpart,
                     c.vhist, c.wgrad, c.xy, c.gpart, c.gk, c.mur,
                     c.lma_start, c.lma_beads, c.rt_sorted, c.v_sorted,
                     c.cell_beads};
@@ -254,7 +256,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     c.cheb_keep = p->cheb_keep;
     c.grad = p->grad != 0;
     c.lma = p->lma != 0;
-    c.rhs_cap = c.max_rhs > 3 ? c.max_rhs : 3;   // bd_step's product of [F, U+, dW]
+    c.rhs_cap = c.max_rhs > 4 ? c.max_rhs : 4;   // bd_step's product of [F, U+, U-, dW]
     c.block = !c.lma && c.lowp != RPY_PREC_F64 && c.max_rhs >= BLOCK_MIN_RHS;
     if (c.block) c.rhs_cap = BLOCK_RHS;  // block kernels write all 16 columns
     {
@@ -310,7 +312,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     const size_t lcells = c.lma ? (size_t)c.lma_nc * c.lma_nc * c.lma_nc : 0;
     const size_t nv = (size_t)c.n3;
     const size_t mv = (size_t)c.rhs_cap * nv;
-    c.work_elems = 3 * nv + 3 * nv + nv + nv + 2 * mv + mv + mv;
+    c.work_elems = 3 * nv + nv + 4 * nv + nv + nv + 2 * mv + mv + mv;
     const int ncell_cap = 64;
     const size_t ncells_cap = (size_t)ncell_cap * ncell_cap * ncell_cap;
     if ((rc = dalloc(&c.rt, nv)) || (rc = dalloc(&c.rt_ev, nv)) || (rc = dalloc(&c.etab, nv * (c.nmax + 1))) ||
@@ -338,6 +340,8 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
         (rc = dalloc(&c.work, c.work_elems)) || (rc = dalloc(&c.scal, 8 + MAX_NCHEB)) ||
         (rc = dalloc(&c.red, 64)) || (rc = dalloc(&c.flags, 4)) ||
         (rc = dalloc(&c.lanc, 2 * MAX_LANCZOS)) ||
+        (rc = dalloc(&c.adapt, 1)) ||
+        (rc = dalloc(&c.tpart, (size_t)c.rhs_cap * ((c.n3 + 255) / 256) * 2)) ||
         (c.cheb_keep > 0 && (rc = dalloc(&c.vhist, (size_t)c.cheb_keep * c.rhs_cap * nv))) ||
         (c.grad && ((rc = dalloc(&c.wgrad, te)) ||
                     (rc = dalloc(&c.xy, (size_t)c.cheb_keep * 2 * nv)) ||
@@ -349,18 +353,23 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     }
     double *w = c.work;
     x->F = w; w += 3 * nv;
-    x->Y = w; w += 3 * nv;
+    x->Um = w; w += nv;
+    x->Y = w; w += 4 * nv;
     x->dW = w; w += nv;
     x->dS = w; w += nv;
     x->Bv[0] = w; w += mv;
     x->Bv[1] = w; w += mv;
     x->ddw = w; w += mv;
     x->acc = w; w += mv;
+    std::vector<double> um(nv);
+    for (size_t i = 0; i < nv; ++i) um[i] = (i & 1) ? -1.0 : 1.0;
     hipError_t e;
     if ((e = hipMemcpy(c.kvec, kv.data(), kv.size() * sizeof(KVec), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(x->Um, um.data(), nv * sizeof(double), hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(c.kcoef, kc.data(), kc.size() * sizeof(KCoef), hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(c.tile_ij, tij.data(), tij.size() * sizeof(int2), hipMemcpyHostToDevice)) ||
         (e = hipMemset(c.flags, 0, 4 * sizeof(int))) ||
+        (e = hipMemset(c.adapt, 0, sizeof(AdaptState))) ||
         (te6 && (e = hipMemset(c.d64, 0, te6 * sizeof(double)))) ||
         (c.block && (e = hipMemset(c.tkm, 0, (size_t)c.nk4 * 6 * BLOCK_RHS * sizeof(double))))) {
         rc = hip_fail(e, "rpy_create upload");
@@ -394,7 +403,9 @@ struct ProfScope {
     bool on;
     ProfScope(rpy_ctx *x_, int k_, hipStream_t s_) : x(x_), k(k_), s(s_)
     {
-        on = x->prof.cap > 0 && x->prof.n[k] < x->prof.cap;
+        // products an adaptive call enqueues past its first trial run under
+        // the gate and may return at once: they are not recorded
+        on = x->prof.cap > 0 && x->prof.n[k] < x->prof.cap && !x->c.gate;
         if (!on) return;
         hipEvent_t *e = &x->prof.ev[k][2 * x->prof.n[k]];
         (void)hipEventRecord(e[0], s);
@@ -528,17 +539,99 @@ static void cheb_run(rpy_ctx *x, const double *dw, double *out, int m, int n_che
     }
 }
 
+// First order of an adaptive call as the device computes it from the
+// interval (eq. nint, rounded half away from zero) or the caller's start.
+static int adapt_first(int floor_n, double d_min, double d_max, int nmax)
+{
+    int k = floor_n;
+    if (floor_n < 2) {
+        const double r = round(sqrt(d_max / d_min)) + 1.0;
+        k = r < (double)nmax ? (int)r : nmax;
+    }
+    return k < 2 ? 2 : (k > nmax ? nmax : k);
+}
+
+// The adaptive order (eq. nint, then one more term at a time until E_f < tol
+// for every right-hand side, section "Decomposition of the diffusion
+// tensor").  On entry V_0 is in the history (c.vhist, stride ps per term)
+// and launch_cheb_coeffs has reset the adaptive state and written the
+// coefficients of the first order; with first = 2 V_1 and D.V_0 are in place
+// as well.  Every product up to the largest order nmax is enqueued, each
+// followed by a trial of the order it completes; the products after the first
+// trial run under the gate, so that the kernels of everything past the
+// settled order return at once.  host_first is the first order the device
+// can start from (no trial is enqueued below it).  dS of the settled order
+// ends in out, its E_f in e_f.
+static void cheb_adapt_run(rpy_ctx *x, int m, int prec, int first, int host_first, int nmax,
+                           double tol, double *out, double *e_f, hipStream_t s)
+{
+    Ctx &c = x->c;
+    const size_t ps = (size_t)c.rhs_cap * c.n3;
+    double *vh = c.vhist;
+    const int *done = &c.adapt->done;
+    auto trial = [&](int n) {
+        if (n >= host_first) launch_trial(c, m, n, nmax, tol, ps, x->ddw, out, e_f, s);
+    };
+    if (first == 2) trial(2);
+    for (int p = first; p < nmax; ++p) {
+        EpiArgs f{};
+        f.m = m;
+        f.p = p;
+        f.scal = c.scal;
+        f.acc = x->acc;   // the fixed-order running sum: not used by the trials
+        f.vout = vh + p * ps;
+        f.vprev = vh + (p - 1) * ps;
+        if (p == 1) {
+            f.mode = EPI_CHEB_FIRST;
+            f.dv = x->ddw;
+        } else {
+            f.mode = EPI_CHEB_NEXT;
+            f.vprev2 = vh + (p - 2) * ps;
+        }
+        c.gate = p >= host_first ? done : nullptr;   // a trial may have settled the order
+        product(x, f.vprev, m, prec, f, s);
+        c.gate = nullptr;
+        trial(p + 1);
+    }
+}
+
+// Reads the adaptive state after the stream has drained.
+static int adapt_result(rpy_ctx *x, int *n_used, hipStream_t s)
+{
+    AdaptState st;
+    HIP_TRY(hipMemcpyAsync(&st, x->c.adapt, sizeof st, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (n_used) *n_used = st.n_used;
+    return st.last_etol ? RPY_ETOL : RPY_OK;
+}
+
 extern "C" int chebyshev_sqrt_apply(rpy_ctx *x, const double *dw, double *out, int m,
-                                    int n_cheb, double d_min, double d_max, int prec,
-                                    double *e_f, void *stream)
+                                    int n_cheb, double d_min, double d_max, double tol, int prec,
+                                    int *n_used, double *e_f, void *stream)
 {
     if (!x || !dw || !out || m < 1 || m > x->c.max_rhs || n_cheb < 2 || n_cheb > MAX_NCHEB ||
-        !(d_min > 0) || !(d_max > d_min) || !isfinite(d_max) || !prec_ok(x->c, prec))
+        !(d_min > 0) || !(d_max > d_min) || !isfinite(d_max) || !prec_ok(x->c, prec) ||
+        !(tol == tol) || tol == INFINITY)
         return RPY_EINVAL;
     hipStream_t s = S(stream);
-    launch_cheb_coeffs(x->c, n_cheb, RPY_BOUNDS_EXPLICIT, 0.0, d_min, d_max, nullptr, s);
+    Ctx &c = x->c;
+    if (tol > 0) {
+        if (n_cheb > c.cheb_keep) {
+            snprintf(g_err, sizeof g_err, "the adaptive order needs cheb_keep >= n_cheb");
+            return RPY_EINVAL;
+        }
+        launch_copy(c.vhist, dw, (size_t)m * c.n3, s);   // V_0
+        launch_cheb_coeffs(c, 0, RPY_BOUNDS_EXPLICIT, 0.0, d_min, d_max, nullptr, s, 0, n_cheb);
+        cheb_adapt_run(x, m, prec, 1, adapt_first(0, d_min, d_max, n_cheb), n_cheb, tol, out,
+                       e_f ? e_f : c.red, s);
+        int rc = check_launch("chebyshev_sqrt_apply");
+        if (rc || !n_used) return rc;
+        return adapt_result(x, n_used, s);
+    }
+    launch_cheb_coeffs(c, n_cheb, RPY_BOUNDS_EXPLICIT, 0.0, d_min, d_max, nullptr, s);
     cheb_run(x, dw, out, m, n_cheb, prec, s);
-    if (e_f) launch_sqrt_error(x->c, m, dw, x->ddw, out, e_f, s);
+    if (e_f) launch_sqrt_error(c, m, dw, x->ddw, out, e_f, s);
+    if (n_used) *n_used = n_cheb;
     return check_launch("chebyshev_sqrt_apply");
 }
 
@@ -693,49 +786,15 @@ extern "C" int chebyshev_sqrt_adaptive(rpy_ctx *x, const double *dw, double *out
         !isfinite(d_max) || !prec_ok(x->c, prec))
         return RPY_EINVAL;
     hipStream_t s = S(stream);
-    const Ctx &c = x->c;
-    const size_t ps = (size_t)c.rhs_cap * c.n3;   // stride between kept V_p
-    double *vh = c.vhist;
-    double *ef = e_f ? e_f : c.red;
-    int n = n_start >= 2 ? n_start : (int)lround(sqrt(d_max / d_min)) + 1;
-    n = n < 2 ? 2 : (n > n_max ? n_max : n);
-    launch_copy(vh, dw, (size_t)m * c.n3, s);   // V_0 = dW
-    int have = 1;                                // V_0 .. V_{have-1} computed
-    std::vector<double> eh(m);
-    double worst = 0.0;
-    for (;;) {
-        launch_cheb_coeffs(c, n, RPY_BOUNDS_EXPLICIT, 0.0, d_min, d_max, nullptr, s);
-        for (int p = have; p < n; ++p) {
-            EpiArgs f{};
-            f.m = m;
-            f.p = p;
-            f.scal = c.scal;
-            f.acc = out;   // running sum of this order; re-summed below
-            f.vout = vh + p * ps;
-            f.vprev = vh + (p - 1) * ps;
-            if (p == 1) {
-                f.mode = EPI_CHEB_FIRST;
-                f.dv = x->ddw;
-            } else {
-                f.mode = EPI_CHEB_NEXT;
-                f.vprev2 = vh + (p - 2) * ps;
-            }
-            product(x, f.vprev, m, prec, f, s);
-        }
-        have = n;
-        launch_cheb_resum(c.n3, m, n, ps, c.scal, vh, out, s);
-        launch_sqrt_error(c, m, dw, x->ddw, out, ef, s);
-        int rc = check_launch("chebyshev_sqrt_adaptive");
-        if (rc) return rc;
-        HIP_TRY(hipMemcpyAsync(eh.data(), ef, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        worst = 0.0;
-        for (int j = 0; j < m; ++j) worst = eh[j] > worst ? eh[j] : worst;
-        if (worst < tol || n >= n_max) break;
-        ++n;
-    }
-    *n_used = n;
-    return worst < tol ? RPY_OK : RPY_ETOL;
+    Ctx &c = x->c;
+    const int floor_n = n_start >= 2 ? n_start : 0;
+    launch_copy(c.vhist, dw, (size_t)m * c.n3, s);   // V_0
+    launch_cheb_coeffs(c, 0, RPY_BOUNDS_EXPLICIT, 0.0, d_min, d_max, nullptr, s, floor_n, n_max);
+    cheb_adapt_run(x, m, prec, 1, adapt_first(floor_n, d_min, d_max, n_max), n_max, tol, out,
+                   e_f ? e_f : c.red, s);
+    int rc = check_launch("chebyshev_sqrt_adaptive");
+    if (rc) return rc;
+    return adapt_result(x, n_used, s);
 }
 
 // Chebyshev recurrence on dw keeping every V_p (V_p at vh + p * ps), out =
@@ -865,17 +924,32 @@ extern "C" int rpy_u_vjp(rpy_ctx *x, const double *pos, const double *F, const d
     return check_launch("rpy_u_vjp");
 }
 
-extern "C" int rpy_bounds(rpy_ctx *x, double C, double *d_min, double *d_max, void *stream)
+extern "C" int rpy_bounds(rpy_ctx *x, int rule, double C, double *d_min, double *d_max,
+                          void *stream)
 {
-    if (!x || !d_min || !d_max || !(C > 0)) return RPY_EINVAL;
+    if (!x || !d_min || !d_max) return RPY_EINVAL;
+    if (rule == RPY_BOUNDS_PAPER) {
+        if (!(C > 0) || !isfinite(C)) return RPY_EINVAL;
+    } else if (rule != RPY_BOUNDS_DILUTE) {
+        return RPY_EINVAL;
+    }
     hipStream_t s = S(stream);
     const Ctx &c = x->c;
+    const size_t nv = (size_t)c.n3;
+    // [U+] for the paper's rule; [U+, U-] side by side for the dilute rule
+    const int m = rule == RPY_BOUNDS_DILUTE ? 2 : 1;
+    const double *v = x->F + nv;
+    if (m == 2) {
+        launch_copy(x->Bv[0], x->F + nv, nv, s);
+        launch_copy(x->Bv[0] + nv, x->Um, nv, s);
+        v = x->Bv[0];
+    }
     EpiArgs f{};
     f.mode = EPI_APPLY;
-    f.m = 1;
-    f.vout = x->Y + c.n3;
-    product(x, x->F + c.n3, 1, RPY_PREC_F64, f, s);
-    launch_cheb_coeffs(c, 2, RPY_BOUNDS_PAPER, C, 0, 0, x->Y + c.n3, s);
+    f.m = m;
+    f.vout = x->Y + nv;
+    product(x, v, m, RPY_PREC_F64, f, s);
+    launch_cheb_coeffs(c, 2, rule, C, 0, 0, x->Y + nv, s);
     int rc = check_launch("rpy_bounds");
     if (rc) return rc;
     double h[2];
@@ -951,15 +1025,25 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
 {
     if (!x || !pos || !bp) return RPY_EINVAL;
     Ctx &c = x->c;
-    if (!(bp->dt > 0) || !isfinite(bp->dt) || bp->n_cheb < 2 || bp->n_cheb > MAX_NCHEB ||
-        !prec_ok(c, bp->prec))
+    const bool adapt = bp->tol > 0;
+    if (!(bp->dt > 0) || !isfinite(bp->dt) || !prec_ok(c, bp->prec) || !(bp->tol == bp->tol) ||
+        bp->tol == INFINITY)
         return RPY_EINVAL;
-    if (bp->bounds_rule == RPY_BOUNDS_EXPLICIT) {
+    if (adapt) {
+        if (bp->n_max < 2 || bp->n_max > MAX_NCHEB || bp->n_max > c.cheb_keep) {
+            snprintf(g_err, sizeof g_err, "the adaptive order needs 2 <= n_max <= cheb_keep");
+            return RPY_EINVAL;
+        }
+    } else if (bp->n_cheb < 2 || bp->n_cheb > MAX_NCHEB) {
+        return RPY_EINVAL;
+    }
+    const int rule = bp->bounds_rule;
+    if (rule == RPY_BOUNDS_EXPLICIT) {
         if (!(bp->d_min > 0) || !(bp->d_max > bp->d_min) || !isfinite(bp->d_max))
             return RPY_EINVAL;
-    } else if (bp->bounds_rule == RPY_BOUNDS_PAPER) {
-        if (!(bp->bounds_C > 0)) return RPY_EINVAL;
-    } else {
+    } else if (rule == RPY_BOUNDS_PAPER) {
+        if (!(bp->bounds_C > 0) || !isfinite(bp->bounds_C)) return RPY_EINVAL;
+    } else if (rule != RPY_BOUNDS_DILUTE) {
         return RPY_EINVAL;
     }
     int rc = check_ev(c, bp->ev_zstar, bp->ev_dstar, bp->ev_rcut);
@@ -969,9 +1053,9 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
     launch_wrap_tables(c, pos, s);
     ++x->wrap_gen;
     // The FP64 step folds the first Chebyshev product into the drift
-    // product: one pass over D for [F, U+, dW] (dW at F + 2 nv), then the
-    // coefficients, then V_1 from D.dW.  Lower-precision Chebyshev products
-    // keep their own first product.
+    // product: one pass over D for [F, U+, (U-,) dW], then the coefficients,
+    // then V_1 from D.dW.  Lower-precision Chebyshev products keep their own
+    // first product.
     const bool fold = bp->prec == RPY_PREC_F64;
     double *w = fold ? x->F + 2 * nv : x->dW;
     // forces and noise on the side stream, beside the build
@@ -990,34 +1074,61 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
         launch_build_tiles(c, s);
     }
     HIP_TRY(hipStreamWaitEvent(s, x->join, 0));
+    // the drift product: F, then U+ (paper and dilute rules) and U- (dilute),
+    // then dW when folded; D.F lands in Y, D.U+ in Y + nv, D.dW last
+    const int nb = rule == RPY_BOUNDS_PAPER ? 1 : rule == RPY_BOUNDS_DILUTE ? 2 : 0;
     EpiArgs f{};
     f.mode = EPI_APPLY;
     f.vout = x->Y;
-    const bool paper = bp->bounds_rule == RPY_BOUNDS_PAPER;
-    // [F, U+] (paper rule) or [F] (explicit bounds), plus dW when folded
-    f.m = (paper ? 2 : 1) + (fold ? 1 : 0);
-    if (fold && !paper) {
-        // no U+ between F and dW: gather [F, dW] in Bv[0] (free until the
-        // recurrence's second product)
-        launch_copy(x->Bv[0], x->F, nv, s);
-        launch_copy(x->Bv[0] + nv, w, nv, s);
-        product(x, x->Bv[0], f.m, RPY_PREC_F64, f, s);
+    f.m = 1 + nb + (fold ? 1 : 0);
+    if (nb == 1 || f.m == 1) {
+        product(x, x->F, f.m, RPY_PREC_F64, f, s);   // [F], or [F, U+, dW] contiguous
     } else {
-        product(x, x->F, f.m, RPY_PREC_F64, f, s);
+        double *g = x->Bv[0];   // free until the recurrence's second product
+        launch_copy(g, x->F, nv, s);
+        if (nb == 2) {
+            launch_copy(g + nv, x->F + nv, nv, s);
+            launch_copy(g + 2 * nv, x->Um, nv, s);
+        }
+        if (fold) launch_copy(g + (1 + nb) * nv, w, nv, s);
+        product(x, g, f.m, RPY_PREC_F64, f, s);
     }
-    if (paper)
-        launch_cheb_coeffs(c, bp->n_cheb, RPY_BOUNDS_PAPER, bp->bounds_C, 0, 0, x->Y + nv, s);
-    else
-        launch_cheb_coeffs(c, bp->n_cheb, RPY_BOUNDS_EXPLICIT, 0, bp->d_min, bp->d_max, nullptr,
-                           s);
-    if (fold) {
-        const double *ddw = x->Y + (paper ? 2 : 1) * nv;   // D.dW
-        launch_cheb_first(c, ddw, w, x->Bv[1], x->dS, x->ddw, s);
-        cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s, 2);
+    const double *du = x->Y + nv;
+    const int floor_n = adapt ? (bp->n_cheb >= 2 ? bp->n_cheb : 0) : -1;
+    const int nmax = adapt ? bp->n_max : bp->n_cheb;
+    launch_cheb_coeffs(c, bp->n_cheb, rule, bp->bounds_C, bp->d_min, bp->d_max,
+                       nb ? du : nullptr, s, floor_n, nmax);
+    if (adapt) {
+        const size_t ps = (size_t)c.rhs_cap * nv;
+        launch_copy(c.vhist, w, nv, s);   // V_0
+        // The first order the device can start from.  Explicit interval: the
+        // device's own value.  The paper's rule fixes d_max / d_min = C N^0.6
+        // whatever D is, so eq. nint is known up to the rounding of that
+        // ratio: one order below it is safe (a trial below the device's first
+        // order returns at once).  The dilute rule: from the lowest order.
+        int host_first = floor_n >= 2 ? (floor_n < nmax ? floor_n : nmax) : 2;
+        if (rule == RPY_BOUNDS_EXPLICIT) {
+            host_first = adapt_first(floor_n, bp->d_min, bp->d_max, nmax);
+        } else if (rule == RPY_BOUNDS_PAPER && floor_n < 2) {
+            const int k = adapt_first(0, 1.0, bp->bounds_C * pow((double)c.N, 0.6), nmax) - 1;
+            host_first = k < 2 ? 2 : k;
+        }
+        if (fold) {
+            const double *ddw = x->Y + (1 + nb) * nv;   // D.dW
+            launch_cheb_first(c, ddw, w, c.vhist + ps, x->acc, x->ddw, s);
+        }
+        cheb_adapt_run(x, 1, bp->prec, fold ? 2 : 1, host_first, nmax, bp->tol, x->dS,
+                       e_f ? e_f : c.red, s);
     } else {
-        cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s);
+        if (fold) {
+            const double *ddw = x->Y + (1 + nb) * nv;   // D.dW
+            launch_cheb_first(c, ddw, w, x->Bv[1], x->dS, x->ddw, s);
+            cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s, 2);
+        } else {
+            cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s);
+        }
+        if (e_f) launch_sqrt_error(c, 1, w, x->ddw, x->dS, e_f, s);
     }
-    if (e_f) launch_sqrt_error(c, 1, w, x->ddw, x->dS, e_f, s);
     if (drift) launch_copy(drift, x->Y, nv, s);
     if (noise) launch_copy(noise, x->dS, nv, s);
     launch_euler(c, pos, bp->dt, x->Y, x->dS, s);
@@ -1035,6 +1146,30 @@ extern "C" int rpy_status(rpy_ctx *x, void *stream)
         snprintf(g_err, sizeof g_err, "non-finite position");
         return RPY_ENONFINITE;
     }
+    long long etol = 0;
+    HIP_TRY(hipMemcpy(&etol, &x->c.adapt->etol, sizeof etol, hipMemcpyDeviceToHost));
+    if (etol) {
+        HIP_TRY(hipMemset(&x->c.adapt->etol, 0, sizeof etol));
+        return RPY_ETOL;
+    }
+    return RPY_OK;
+}
+
+extern "C" int rpy_order_stats(rpy_ctx *x, int64_t *calls, double *mean_order, int *max_order,
+                               int64_t *missed, void *stream)
+{
+    if (!x || !calls || !mean_order || !max_order || !missed) return RPY_EINVAL;
+    AdaptState st;
+    HIP_TRY(hipMemcpyAsync(&st, x->c.adapt, sizeof st, hipMemcpyDeviceToHost, S(stream)));
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    *calls = st.calls;
+    *mean_order = st.calls ? (double)st.sum_orders / (double)st.calls : 0.0;
+    *max_order = st.max_order;
+    *missed = st.missed;
+    AdaptState z = st;
+    z.calls = z.sum_orders = z.missed = 0;
+    z.max_order = 0;
+    HIP_TRY(hipMemcpy(x->c.adapt, &z, sizeof z, hipMemcpyHostToDevice));
     return RPY_OK;
 }
 

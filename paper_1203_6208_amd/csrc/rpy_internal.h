@@ -370,6 +370,25 @@ __device__ inline uint4 philox10(uint4 c, uint2 k)
     return c;
 }
 
+// ------------------------------------------------- adaptive Chebyshev order
+// Device state of the adaptive order (eq. nint, then one more term until
+// E_f < tol).  The host enqueues every product and trial an adaptive call may
+// need up to its largest order; once a trial settles the order, `done` is set
+// and the kernels of the later products and trials return at once, so no
+// host synchronisation is needed.
+struct AdaptState {
+    int done;             // the order of the current call is settled
+    int n_used;           // the settled order
+    int n_start;          // first order tried by the current call
+    int last_etol;        // the current call settled at its largest order with E_f >= tol
+    long long etol;       // calls settled above the tolerance since the last status read
+    long long calls;      // settled calls since the last order-statistics read
+    long long sum_orders; // sum of their orders
+    long long missed;     // those of them settled above the tolerance
+    int max_order;        // largest of their orders
+    int pad;
+};
+
 // -------------------------------------------------------------- context
 struct Ctx {
     // problem
@@ -422,6 +441,12 @@ struct Ctx {
     double *lanc = nullptr;      // [2 MAX_LANCZOS] Lanczos alpha, beta
     int cheb_keep = 0;           // Chebyshev vectors kept for the adaptive order
     double *vhist = nullptr;     // [cheb_keep][rhs_cap][3N]
+    AdaptState *adapt = nullptr; // adaptive-order state
+    double *tpart = nullptr;     // [rhs_cap][ceil(3N/256)][2] partial dot products of a trial
+    // While set, every product kernel first reads *gate and returns at once
+    // if it is non-zero (the products an adaptive call enqueues past the
+    // order it may settle at).
+    mutable const int *gate = nullptr;
     int *flags = nullptr;        // [0] nonfinite
     // low-memory (matrix-free) form: no stored tiles; the real-space part is
     // recomputed per product over a cell list of side >= max(r_c, 2a)
@@ -494,8 +519,19 @@ constexpr int BLOCK_MIN_RHS = 5;   // products with at least this many vectors u
 constexpr int BLOCK_RHS = 16;
 void launch_sf_reduce(const Ctx &c, int m, hipStream_t s);
 void launch_kspace_epi(const Ctx &c, const EpiArgs &f, hipStream_t s);
+// Interval (explicit, or the paper's rule from du = D.U+), the scalars of Y
+// and the coefficients of order n_cheb.  With adapt_floor >= 0 the order is
+// the adaptive call's first one instead: adapt_floor if >= 2, else eq. nint
+// on the interval, clamped to [2, adapt_max]; the adaptive state is reset.
 void launch_cheb_coeffs(const Ctx &c, int n_cheb, int rule, double C, double dmin,
-                        double dmax, const double *du, hipStream_t s);
+                        double dmax, const double *du, hipStream_t s, int adapt_floor = -1,
+                        int adapt_max = 0);
+// One trial order n of an adaptive call over m right-hand sides whose V_p are
+// kept at c.vhist (stride ps per p) and D.V_0 at ddw: dS of order n into ds,
+// E_f; settles the order when every E_f < tol or n = nmax (then e_f is
+// written), else puts the coefficients of order n + 1 in place.
+void launch_trial(const Ctx &c, int m, int n, int nmax, double tol, size_t ps,
+                  const double *ddw, double *ds, double *e_f, hipStream_t s);
 void launch_sqrt_error(const Ctx &c, int m, const double *dw, const double *ddw,
                        const double *ds, double *e_f, hipStream_t s);
 void launch_fill(double *p, double v, size_t n, hipStream_t s);

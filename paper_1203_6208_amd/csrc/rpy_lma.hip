@@ -15,8 +15,10 @@ namespace rpy {
 // out[j][k] = in[j][beads[k]] (3 components), j < m: positions or vectors in
 // cell order.
 __global__ void k_lma_gather(int N, int m, int n3, const int *__restrict__ beads,
-                             const double *__restrict__ in, double *__restrict__ out)
+                             const double *__restrict__ in, double *__restrict__ out,
+                             const int *__restrict__ gate)
 {
+    if (gate && *gate) return;   // a product past the settled adaptive order
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m * N) return;
     const int j = e / N, k = e % N;
@@ -32,7 +34,7 @@ void launch_lma_build(const Ctx &c, hipStream_t s)
 {
     launch_cell_list_into(c.N, c.L, c.lma_nc, c.rt, c.lma_start, c.lma_beads, s);
     hipLaunchKernelGGL(k_lma_gather, dim3((c.N + 255) / 256), dim3(256), 0, s, c.N, 1, c.n3,
-                       c.lma_beads, c.rt, c.rt_sorted);
+                       c.lma_beads, c.rt, c.rt_sorted, nullptr);
 }
 
 // Real-space product, matrix-free.  Workgroup: 16 consecutive beads in cell
@@ -98,9 +100,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                                                   const int *__restrict__ beads,
                                                   const double *__restrict__ rt_s,
                                                   const double *__restrict__ vs,
-                                                  double *__restrict__ part)
+                                                  double *__restrict__ part,
+                                                  const int *__restrict__ gate)
 {
     __shared__ int queue[4][LMA_QCAP];
+    if (gate && *gate) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int *q = queue[w];
     const double invL = 1.0 / L;
@@ -169,12 +173,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 void launch_lma_real(const Ctx &c, const double *v, int m, hipStream_t s)
 {
     hipLaunchKernelGGL(k_lma_gather, dim3((m * c.N + 255) / 256), dim3(256), 0, s, c.N, m, c.n3,
-                       c.lma_beads, v, c.v_sorted);
+                       c.lma_beads, v, c.v_sorted, c.gate);
     const dim3 g((c.N + LMA_HOMES - 1) / LMA_HOMES);
 #define RPY_LMA_REAL(MC)                                                                        \
     hipLaunchKernelGGL(k_lma_real<MC>, g, dim3(256), 0, s, c.N, c.n3, c.n3pad, c.rhs_cap, j0, \
                        c.L, c.lma_nc, c.pc, c.lma_start, c.lma_beads, c.rt_sorted, c.v_sorted, \
-                       c.part)
+                       c.part, c.gate)
     for (int j0 = 0; j0 < m;) {   // groups of 4, 2, 1 vectors
         const int mc = (m - j0) >= 4 ? 4 : (m - j0) >= 2 ? 2 : 1;
         if (mc == 4) RPY_LMA_REAL(4);
@@ -190,9 +194,11 @@ __global__ __launch_bounds__(256) void k_lma_sf(int N, int n3, int nk, int nmax,
                                                 int nkb, int m, const KVec *__restrict__ kvec,
                                                 const double2 *__restrict__ etab,
                                                 const double *__restrict__ v,
-                                                double *__restrict__ sfpart)
+                                                double *__restrict__ sfpart,
+                                                const int *__restrict__ gate)
 {
     extern __shared__ double smem[];
+    if (gate && *gate) return;
     for (int j0 = 0; j0 < m; j0 += 2) {
         if (j0 > 0) __syncthreads();   // the vector slots are rewritten
         if (m - j0 >= 2)
@@ -209,7 +215,7 @@ void launch_lma_sf(const Ctx &c, const double *v, int m, hipStream_t s)
     const int nkb = (c.nk + 255) / 256;
     const size_t lds = sizeof(double) * (size_t)(2 * SF_BEADS * 3 * (c.nmax + 1) + SF_BEADS * 2 * 3);
     hipLaunchKernelGGL(k_lma_sf, dim3(c.nsfc * nkb), dim3(256), lds, s, c.N, c.n3, c.nk, c.nmax,
-                       c.rhs_cap, nkb, m, c.kvec, c.etab, v, c.sfpart);
+                       c.rhs_cap, nkb, m, c.kvec, c.etab, v, c.sfpart, c.gate);
 }
 
 }  // namespace rpy

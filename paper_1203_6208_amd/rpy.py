@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "librpy.so")
 
 RPY_OK, RPY_EINVAL, RPY_EGEOM, RPY_ENONFINITE, RPY_ETOL, RPY_ENOMEM, RPY_EHIP = 0, -1, -2, -3, -4, -5, -6
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
-BOUNDS_EXPLICIT, BOUNDS_PAPER = 0, 1
+BOUNDS_EXPLICIT, BOUNDS_PAPER, BOUNDS_DILUTE = 0, 1, 2
 
 
 class RpyError(RuntimeError):
@@ -40,9 +40,9 @@ class BdParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("ev_zstar", ctypes.c_double),
                 ("ev_dstar", ctypes.c_double), ("ev_rcut", ctypes.c_double),
                 ("bounds_C", ctypes.c_double), ("d_min", ctypes.c_double),
-                ("d_max", ctypes.c_double), ("n_cheb", ctypes.c_int32),
-                ("bounds_rule", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("d_max", ctypes.c_double), ("tol", ctypes.c_double),
+                ("n_cheb", ctypes.c_int32), ("bounds_rule", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("n_max", ctypes.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -58,8 +58,9 @@ _SIG = {
     "rpy_destroy": (None, [_v]),
     "rpy_ewald_build": (_i, [_v, _v, _v]),
     "rpy_apply": (_i, [_v, _v, _v, _i, _i, _v]),
-    "rpy_bounds": (_i, [_v, _d, _P(_d), _P(_d), _v]),
-    "chebyshev_sqrt_apply": (_i, [_v, _v, _v, _i, _i, _d, _d, _i, _v, _v]),
+    "rpy_bounds": (_i, [_v, _i, _d, _P(_d), _P(_d), _v]),
+    "chebyshev_sqrt_apply": (_i, [_v, _v, _v, _i, _i, _d, _d, _d, _i, _P(_i), _v, _v]),
+    "rpy_order_stats": (_i, [_v, _P(ctypes.c_int64), _P(_d), _P(_i), _P(ctypes.c_int64), _v]),
     "bd_step": (_i, [_v, _v, _P(BdParams), _v, ctypes.c_uint64, ctypes.c_uint64, _v, _v, _v, _v]),
     "rpy_status": (_i, [_v, _v]),
     "rpy_real_space_dense": (_i, [_v, _v, _v]),
@@ -146,20 +147,38 @@ def rpy_apply(ctx, v: torch.Tensor, out: torch.Tensor, m: int, prec="f64", strea
     return out
 
 
-def rpy_bounds(ctx, C: float, stream=None):
+def rpy_bounds(ctx, C: float, rule=BOUNDS_PAPER, stream=None):
     lo, hi = ctypes.c_double(), ctypes.c_double()
-    _check(_lib.rpy_bounds(ctx, float(C), ctypes.byref(lo), ctypes.byref(hi), _stream(stream)),
-           "rpy_bounds")
+    _check(_lib.rpy_bounds(ctx, int(rule), float(C), ctypes.byref(lo), ctypes.byref(hi),
+                           _stream(stream)), "rpy_bounds")
     return lo.value, hi.value
 
 
 def chebyshev_sqrt_apply(ctx, dw: torch.Tensor, out: torch.Tensor, m: int, n_cheb: int,
                          d_min: float, d_max: float, prec="f64", e_f: torch.Tensor = None,
-                         stream=None):
-    _check(_lib.chebyshev_sqrt_apply(ctx, _dev(dw, "dw"), _dev(out, "out"), int(m), int(n_cheb),
-                                     float(d_min), float(d_max), PREC[prec], _dev(e_f, "e_f"),
-                                     _stream(stream)), "chebyshev_sqrt_apply")
-    return out
+                         tol: float = 0.0, want_n: bool = False, stream=None,
+                         allow_etol=False):
+    """Fixed order (tol <= 0) or adaptive order up to n_cheb (tol > 0).
+    Returns the order used when want_n (that synchronises), else None.
+    RPY_ETOL raises unless allow_etol."""
+    n = ctypes.c_int()
+    code = _lib.chebyshev_sqrt_apply(ctx, _dev(dw, "dw"), _dev(out, "out"), int(m), int(n_cheb),
+                                     float(d_min), float(d_max), float(tol), PREC[prec],
+                                     ctypes.byref(n) if want_n else None, _dev(e_f, "e_f"),
+                                     _stream(stream))
+    if not (code == RPY_OK or (allow_etol and code == RPY_ETOL)):
+        _check(code, "chebyshev_sqrt_apply")
+    return n.value if want_n else None
+
+
+def rpy_order_stats(ctx, stream=None):
+    """(calls, mean N_Ch, max N_Ch, calls that missed the tolerance) of the
+    adaptive calls since the last read; resets them."""
+    calls, mx, missed = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int64()
+    mean = ctypes.c_double()
+    _check(_lib.rpy_order_stats(ctx, ctypes.byref(calls), ctypes.byref(mean), ctypes.byref(mx),
+                                ctypes.byref(missed), _stream(stream)), "rpy_order_stats")
+    return calls.value, mean.value, mx.value, missed.value
 
 
 def rpy_lanczos_bounds(ctx, n_iter: int, seed: int = 0, start: torch.Tensor = None,
@@ -191,11 +210,11 @@ def chebyshev_sqrt_adaptive(ctx, dw: torch.Tensor, out: torch.Tensor, m: int, n_
 
 
 def make_bd_params(*, dt, n_cheb, bounds_rule=BOUNDS_EXPLICIT, d_min=0.0, d_max=0.0,
-                   bounds_C=8.0, prec="f64", ev=None) -> BdParams:
+                   bounds_C=8.0, prec="f64", ev=None, tol=0.0, n_max=0) -> BdParams:
     ev = ev or {}
     return BdParams(float(dt), float(ev.get("zstar", 0.0)), float(ev.get("dstar", 0.0)),
                     float(ev.get("rcut", 0.0)), float(bounds_C), float(d_min), float(d_max),
-                    int(n_cheb), int(bounds_rule), PREC[prec], 0)
+                    float(tol), int(n_cheb), int(bounds_rule), PREC[prec], int(n_max))
 
 
 def bd_step(ctx, pos: torch.Tensor, bp: BdParams, dw: torch.Tensor = None, seed: int = 0,
@@ -318,16 +337,22 @@ class Context:
         rpy_apply(self.handle, v, out, v.shape[0], prec, stream)
         return out
 
-    def sqrt_apply(self, dw, n_cheb, d_min, d_max, prec="f64", want_ef=False, stream=None):
+    def sqrt_apply(self, dw, n_cheb, d_min, d_max, prec="f64", want_ef=False, tol=0.0,
+                   want_n=False, stream=None, allow_etol=False):
+        """dS (and E_f when want_ef, the order used when want_n)."""
         dw = dw.reshape(-1, self.n, 3).contiguous()
         out = torch.empty_like(dw)
         ef = torch.empty(dw.shape[0], dtype=torch.float64, device=dw.device) if want_ef else None
-        chebyshev_sqrt_apply(self.handle, dw, out, dw.shape[0], n_cheb, d_min, d_max, prec, ef,
-                             stream)
-        return (out, ef) if want_ef else out
+        n = chebyshev_sqrt_apply(self.handle, dw, out, dw.shape[0], n_cheb, d_min, d_max, prec,
+                                 ef, tol, want_n, stream, allow_etol)
+        res = (out,) + ((ef,) if want_ef else ()) + ((n,) if want_n else ())
+        return res if len(res) > 1 else out
 
-    def bounds(self, C, stream=None):
-        return rpy_bounds(self.handle, C, stream)
+    def bounds(self, C, rule=BOUNDS_PAPER, stream=None):
+        return rpy_bounds(self.handle, C, rule, stream)
+
+    def order_stats(self, stream=None):
+        return rpy_order_stats(self.handle, stream)
 
     def lanczos_bounds(self, n_iter, seed=0, start=None, margin=0.05, stream=None):
         if start is not None:

@@ -1,0 +1,180 @@
+"""GPU parity of the paper's per-step accuracy control through the C ABI
+(arXiv:1203.6208, section "Decomposition of the diffusion tensor": N_Ch from
+eq. nint, then one more term until E_f < tol) and of the dilute bound rule
+(eq. lmax-lmin-dilute), against the CPU oracle.
+
+The adaptive order runs entirely on the device: every product and trial up to
+the largest order is enqueued, and the kernels past the settled order return
+at once.  Compared with the oracle's procedure (orc_cheb_adaptive, which
+recomputes the whole recurrence for every trial order): the order used, dS to
+rel 1e-12, E_f, and the positions after each step.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1203_6208_amd import inputs  # noqa: E402
+from paper_1203_6208_amd import rpy  # noqa: E402
+
+TOL = 1e-12
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _cuda(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("rule,prec", [("explicit", "f64"), ("paper", "f64"),
+                                       ("explicit", "f32")])
+def test_bd_step_adaptive_order_n100(orc, rule, prec):
+    """Five steps with tol = 1e-3 and the order from eq. nint on the step's
+    interval (explicit, or the paper's rule at C = 30 computed on the device),
+    host noise.  Each step is compared on its own (the oracle starts from the
+    GPU's positions): the order used equals the oracle's, and dS, the drift
+    and the new positions agree to 1e-12 (FP64).  With FP32 products the
+    order may differ by one and dS agrees to the product rounding."""
+    _say(f"adaptive bd_step n100 {rule} {prec}")
+    w = inputs.workload("n100")
+    tol, nmax = 1e-3, 96
+    ctx = rpy.context_for(w, lowp=prec, cheb_keep=nmax)
+    tpos = _cuda(w.positions())
+    for step in range(5):
+        p0 = tpos.cpu().numpy()
+        D = orc.diffusion_matrix(p0, w.L, w.a, w.alpha, w.rc, w.n2max)
+        if rule == "explicit":
+            lam = np.linalg.eigvalsh(D)
+            lo, hi = 0.9 * lam[0], 1.1 * lam[-1]
+            bp = rpy.make_bd_params(dt=w.dt, n_cheb=0, d_min=lo, d_max=hi, tol=tol, n_max=nmax,
+                                    prec=prec)
+        else:
+            lo, hi = orc.bounds_rule(D, w.n, 30.0)
+            bp = rpy.make_bd_params(dt=w.dt, n_cheb=0, bounds_rule=rpy.BOUNDS_PAPER,
+                                    bounds_C=30.0, tol=tol, n_max=nmax, prec=prec)
+        dw = w.noise(seed=8100 + step)[0]
+        drift, noise, ef = ctx.step(tpos, bp, dw=_cuda(dw), want=True)
+        calls, mean_n, max_n, missed = ctx.order_stats()
+        assert calls == 1 and missed == 0 and mean_n == max_n
+        F = orc.spring_forces(p0, w.nchains, w.bpc)
+        ud = orc.matvec(D, F.reshape(1, -1)).reshape(w.n, 3)
+        n_o, ds_o = orc.cheb_adaptive(D, dw.reshape(1, -1), lo, hi, tol, nmax)
+        ds_o = ds_o.reshape(w.n, 3)
+        new = orc.euler(p0, w.dt, ud, ds_o)
+        assert _rel(drift.cpu().numpy(), ud) < TOL
+        assert float(ef.item()) < tol
+        if prec == "f64":
+            assert max_n == n_o, (step, max_n, n_o)
+            assert _rel(noise.cpu().numpy(), ds_o) < TOL
+            assert _rel(tpos.cpu().numpy(), new) < TOL
+            e_o = orc.sqrt_error(D, dw, ds_o)
+            assert abs(ef.item() ** 2 - e_o ** 2) < 1e-12
+        else:
+            assert abs(max_n - n_o) <= 1
+            if max_n == n_o:
+                assert _rel(noise.cpu().numpy(), ds_o) < 1e-5
+        _say(f"  step {step}: N_Ch {max_n} (oracle {n_o}), E_f {ef.item():.2e}")
+    assert ctx.status() == 0
+
+
+def test_sqrt_apply_adaptive_block_of_three(orc):
+    """chebyshev_sqrt_apply with tol > 0 and three right-hand sides: the order
+    is settled when every E_f is below tol; n_used, dS and E_f as the
+    oracle's procedure.  Called twice in a row (the second call starts from a
+    settled state of the first)."""
+    _say("sqrt_apply adaptive m=3")
+    w = inputs.workload("n100")
+    pos = w.positions()
+    D = orc.diffusion_matrix(pos, w.L, w.a, w.alpha, w.rc, w.n2max)
+    lam = np.linalg.eigvalsh(D)
+    lo, hi = 0.8 * lam[0], 1.2 * lam[-1]
+    ctx = rpy.context_for(w, max_rhs=3, cheb_keep=128)
+    ctx.build(_cuda(pos))
+    dw = w.noise(m=3)
+    for tol in (1e-4, 1e-2):
+        ds, ef, n = ctx.sqrt_apply(_cuda(dw), 128, lo, hi, tol=tol, want_ef=True, want_n=True)
+        n_o, ds_o = orc.cheb_adaptive(D, dw.reshape(3, -1), lo, hi, tol, 128)
+        assert n == n_o
+        assert _rel(ds.cpu().numpy().reshape(3, -1), ds_o) < TOL
+        for j in range(3):
+            e_o = orc.sqrt_error(D, dw[j].ravel(), ds_o[j])
+            assert abs(ef[j].item() ** 2 - e_o ** 2) < 1e-12
+        assert float(ef.max()) < tol
+
+
+def test_adaptive_missed_tolerance_is_reported(orc):
+    """A tolerance no order up to n_max reaches: the outputs of order n_max
+    are written, the step is counted as missed, and rpy_status reports
+    RPY_ETOL once."""
+    w = inputs.workload("n100")
+    pos = w.positions()
+    ctx = rpy.context_for(w, cheb_keep=6)
+    tpos = _cuda(pos)
+    bp = rpy.make_bd_params(dt=w.dt, n_cheb=0, d_min=0.02, d_max=8.0, tol=1e-12, n_max=6)
+    dw = w.noise()[0]
+    _, noise, _ = ctx.step(tpos, bp, dw=_cuda(dw), want=True)
+    D = orc.diffusion_matrix(pos, w.L, w.a, w.alpha, w.rc, w.n2max)
+    ds_o = orc.cheb_sqrt(D, dw.reshape(1, -1), 6, 0.02, 8.0).reshape(w.n, 3)
+    assert _rel(noise.cpu().numpy(), ds_o) < TOL
+    calls, mean_n, max_n, missed = ctx.order_stats()
+    assert (calls, max_n, missed) == (1, 6, 1)
+    ctx.step(tpos, bp, dw=_cuda(dw))
+    assert ctx.status() == rpy.RPY_ETOL
+    assert ctx.status() == 0
+
+
+def test_adaptive_refusals():
+    """Invalid adaptive requests fail on the host before any launch."""
+    w = inputs.workload("n100")
+    ctx = rpy.context_for(w, cheb_keep=10)
+    tpos = _cuda(w.positions())
+    for kw in (dict(n_max=11), dict(n_max=1)):
+        bp = rpy.make_bd_params(dt=w.dt, n_cheb=0, d_min=0.05, d_max=6.0, tol=1e-3, **kw)
+        with pytest.raises(rpy.RpyError) as e:
+            ctx.step(tpos, bp)
+        assert e.value.code == rpy.RPY_EINVAL
+    dw = _cuda(w.noise())
+    with pytest.raises(rpy.RpyError):
+        ctx.sqrt_apply(dw, 11, 0.05, 6.0, tol=1e-3)   # n_cheb beyond cheb_keep
+    with pytest.raises(rpy.RpyError):
+        ctx.sqrt_apply(dw, 8, 0.05, 6.0, tol=float("nan"))
+
+
+def test_dilute_bound_rule_n100(orc):
+    """The dilute rule (eq. lmax-lmin-dilute; d_max = 2 U+.D.U+/3N, d_min =
+    U-.D.U-/(2 3N)) through rpy_bounds and inside bd_step (FP64, fixed
+    N_Ch = 20, host noise) against the oracle."""
+    w = inputs.workload("n100")
+    pos = w.positions()
+    D = orc.diffusion_matrix(pos, w.L, w.a, w.alpha, w.rc, w.n2max)
+    ctx = rpy.context_for(w)
+    ctx.build(_cuda(pos))
+    lo, hi = ctx.bounds(0.0, rule=rpy.BOUNDS_DILUTE)
+    rlo, rhi = orc.bounds_dilute(D, w.n)
+    assert abs(lo - rlo) < TOL * rlo and abs(hi - rhi) < TOL * rhi
+    with pytest.raises(rpy.RpyError):
+        ctx.bounds(8.0, rule=7)
+    tpos = _cuda(pos)
+    bp = rpy.make_bd_params(dt=w.dt, n_cheb=w.nch, bounds_rule=rpy.BOUNDS_DILUTE)
+    dw = w.noise()[0]
+    drift, noise, _ = ctx.step(tpos, bp, dw=_cuda(dw), want=True)
+    F = orc.spring_forces(pos, w.nchains, w.bpc)
+    ud = orc.matvec(D, F.reshape(1, -1)).reshape(w.n, 3)
+    ds = orc.cheb_sqrt(D, dw.reshape(1, -1), w.nch, rlo, rhi).reshape(w.n, 3)
+    assert _rel(drift.cpu().numpy(), ud) < TOL
+    assert _rel(noise.cpu().numpy(), ds) < TOL
+    assert _rel(tpos.cpu().numpy(), orc.euler(pos, w.dt, ud, ds)) < TOL
