@@ -156,8 +156,12 @@ def test_adaptive_refusals():
 
 def test_dilute_bound_rule_n100(orc):
     """The dilute rule (eq. lmax-lmin-dilute; d_max = 2 U+.D.U+/3N, d_min =
-    U-.D.U-/(2 3N)) through rpy_bounds and inside bd_step (FP64, fixed
-    N_Ch = 20, host noise) against the oracle."""
+    U-.D.U-/(2 3N)) through rpy_bounds and inside bd_step (FP64, host noise)
+    against the oracle.  On this semidilute D the rule's interval [0.32, 3.38]
+    misses the spectrum [0.080, 5.30] (as the paper finds for semidilute
+    systems), so T_p(Y) grows outside [-1, 1] and with it any rounding
+    difference (T_19 reaches about 1e11 there); the step is compared at
+    N_Ch = 4, where the growth stays below 100."""
     w = inputs.workload("n100")
     pos = w.positions()
     D = orc.diffusion_matrix(pos, w.L, w.a, w.alpha, w.rc, w.n2max)
@@ -169,12 +173,13 @@ def test_dilute_bound_rule_n100(orc):
     with pytest.raises(rpy.RpyError):
         ctx.bounds(8.0, rule=7)
     tpos = _cuda(pos)
-    bp = rpy.make_bd_params(dt=w.dt, n_cheb=w.nch, bounds_rule=rpy.BOUNDS_DILUTE)
+    nch = 4
+    bp = rpy.make_bd_params(dt=w.dt, n_cheb=nch, bounds_rule=rpy.BOUNDS_DILUTE)
     dw = w.noise()[0]
     drift, noise, _ = ctx.step(tpos, bp, dw=_cuda(dw), want=True)
     F = orc.spring_forces(pos, w.nchains, w.bpc)
     ud = orc.matvec(D, F.reshape(1, -1)).reshape(w.n, 3)
-    ds = orc.cheb_sqrt(D, dw.reshape(1, -1), w.nch, rlo, rhi).reshape(w.n, 3)
+    ds = orc.cheb_sqrt(D, dw.reshape(1, -1), nch, rlo, rhi).reshape(w.n, 3)
     assert _rel(drift.cpu().numpy(), ud) < TOL
     assert _rel(noise.cpu().numpy(), ds) < TOL
     assert _rel(tpos.cpu().numpy(), orc.euler(pos, w.dt, ud, ds)) < TOL
