@@ -291,6 +291,23 @@ int rpy_u_vjp(rpy_ctx *c, const double *pos, const double *F,
 int rpy_forces_vjp(rpy_ctx *c, const double *pos, double zstar, double dstar,
                    double rcut, const double *gF, double *g_pos, void *stream);
 
+/* rpy_forces without a context, for callers that cannot allocate device
+ * memory (code under stream capture, tight stepping loops, harnesses that
+ * forbid allocation): the same springs and narrow-Gaussian excluded volume
+ * into out[N][3] (device), for N = n_chains x beads_per_chain beads in a box
+ * of side box_l.  It allocates nothing: its scratch (wrapped positions, the
+ * cell list, about 3.9 MB) is a static device array of the library, one per
+ * GPU, looked up on the first call on that GPU and kept until the process
+ * ends.  Every call on a GPU uses that GPU's one array, so calls that overlap
+ * on one GPU (different streams or host threads) race; calls ordered on one
+ * stream do not.  A non-finite position is not reported (the forces of its
+ * chain come out non-finite).  Errors: RPY_EINVAL for n_beads > 65536 (the
+ * scratch limit), sizes that do not match, a non-positive box, null pointers
+ * or invalid excluded-volume parameters (as rpy_forces); RPY_EHIP. */
+int rpy_forces_noalloc(int n_beads, int n_chains, int beads_per_chain,
+                       double box_l, const double *pos, double zstar,
+                       double dstar, double rcut, double *out, void *stream);
+
 /* Synchronise the stream and report a non-finite position seen by an
  * earlier build (RPY_ENONFINITE, flag then cleared), else an adaptive order
  * that missed its tolerance at its largest order since the last call

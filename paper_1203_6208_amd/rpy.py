@@ -78,6 +78,7 @@ _SIG = {
     "rpy_u_forward": (_i, [_v, _v, _v, _v, _i, _d, _d, _v, _v, _v]),
     "rpy_u_vjp": (_i, [_v, _v, _v, _v, _v, _v, _i, _d, _d, _v, _v, _v]),
     "rpy_forces_vjp": (_i, [_v, _v, _d, _d, _d, _v, _v, _v]),
+    "rpy_forces_noalloc": (_i, [_i, _i, _i, _d, _v, _d, _d, _d, _v, _v]),
     "rpy_batch_create": (_i, [_P(_v), _P(RpyParams), _i, _i, _i]),
     "rpy_batch_destroy": (None, [_v]),
     "rpy_batch_padded_beads": (ctypes.c_int64, [_v]),
@@ -243,6 +244,15 @@ def rpy_observables(ctx, pos, re2, rg2, stream=None):
 def rpy_forces(ctx, pos, zstar, dstar, rcut, out, stream=None):
     _check(_lib.rpy_forces(ctx, _dev(pos, "pos"), float(zstar), float(dstar), float(rcut),
                            _dev(out, "out"), _stream(stream)), "rpy_forces")
+    return out
+
+
+def rpy_forces_noalloc(n_beads, n_chains, beads_per_chain, box_l, pos, zstar, dstar, rcut, out,
+                       stream=None):
+    _check(_lib.rpy_forces_noalloc(int(n_beads), int(n_chains), int(beads_per_chain),
+                                   float(box_l), _dev(pos, "pos"), float(zstar), float(dstar),
+                                   float(rcut), _dev(out, "out"), _stream(stream)),
+           "rpy_forces_noalloc")
     return out
 
 
