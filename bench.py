@@ -42,12 +42,16 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "7e6ad28e37416205d1b0b7787e01b6f1dd3dcded8f9cdc3730f7f91559c12ff1",
+TRAFFIC = {"src_sha256": "c4c06c4aed797dc739456cbe5678da63a92a4f9829682d79982186d1b4eec8e7",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 411377165}
-TRAFFIC_BLOCK = {"src_sha256": "08c6b9fa089f12a8916ca35b0d01a6eedd435ae7f35f3519950f8b50dc2c6f92",
+           "bytes_per_launch": 411336252}
+# The matrix-core tile kernel (k_block_tiles) of a 16-vector product: tile and
+# vector reads plus the per-tile FP64/FP32 partial sums it writes.
+TRAFFIC_BLOCK = {"src_sha256": "5ebf909f27e9dcbc3ef4b553eb98fb58c3745f8038d56eb74c78f584c7e10900",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f32": 312428486 + 48771072, "bf16": 159733814 + 48771072}}
+                 "bytes_per_launch": {"f64": 420293966 + 97542144,
+                                      "f32": 215921135 + 48771788,
+                                      "bf16": 111240949 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
 TRAFFIC_BATCH = {"src_sha256": "733cc46850c2f62d0ad3c3f0ec07554155937491b7b1ee49058b1139a98bf04f",
@@ -224,11 +228,11 @@ def form_errors(w, torch, rpy):
 
 def time_block(w, prec, reps, torch, rpy):
     """sqrt(D) dW for a block of 16 dW vectors (N_Ch - 1 = 29 products of D
-    with 16 vectors) on the step's D and bounds.  FP32/BF16 tiles go through
-    the matrix-core block product (tile kernel with the vector packing, FP64
-    structure factors and their reduction, FP64 back-projection + epilogue);
-    FP64 through the vector-unit kernels 4 vectors at a time.  Per-stage times
-    come from HIP event pairs on the library's stream."""
+    with 16 vectors) on the step's D and bounds, each product one pass of the
+    matrix-core block product over the packed tiles of the given precision
+    (tile kernel with the vector packing, FP64 structure factors and their
+    reduction, FP64 back-projection + epilogue).  Per-stage times come from
+    HIP event pairs on the library's stream."""
     ctx = rpy.context_for(w, lowp=prec, max_rhs=16)
     pos = torch.from_numpy(w.positions()).cuda()
     dw16 = torch.from_numpy(w.noise(m=16)).cuda()
@@ -253,12 +257,11 @@ def time_block(w, prec, reps, torch, rpy):
         ms = sum(rpy.rpy_profile_read(ctx.handle, k)[1] for k in kinds)
         stage[nm + "_us"] = 1e3 * ms / nprod
     rpy.rpy_profile_enable(ctx.handle, 0)
-    gbs = tile_bytes(w.n, prec, packed=prec == "f64") / (stage["tile_product_us"] * 1e-6) / 1e9
+    gbs = tile_bytes(w.n, prec) / (stage["tile_product_us"] * 1e-6) / 1e9
     del ctx
     return {"ms_per_block": 1e3 * wall, "us_per_product": 1e6 * wall / nprod,
             **stage, "tile_product_GBs": gbs, "tile_product_hbm_frac": gbs / HBM_PEAK_GBS,
-            "tile_product_traffic": (measured_traffic(TRAFFIC_BLOCK, prec)
-                                     if prec in ("f32", "bf16") else None),
+            "tile_product_traffic": measured_traffic(TRAFFIC_BLOCK, prec),
             "vector_products_per_s": 16 * nprod / wall}
 
 
@@ -703,17 +706,12 @@ def oracle_table(seconds):
     return out
 
 
-def tile_bytes(n, prec, packed=True):
-    """Algorithmic bytes one product streams.  Packed tiles (every product of
-    up to 4 vectors) keep the 6 distinct entries of each symmetric 3 x 3
-    bead-pair block for the N(N+1)/2 pairs i <= j; the matrix-core block
-    product (FP32 / BF16, 5-16 vectors) reads the symmetric half of the
-    3N x 3N matrix."""
+def tile_bytes(n, prec):
+    """Algorithmic bytes one product streams, whatever the number of vectors:
+    the packed tiles keep the 6 distinct entries of each symmetric 3 x 3
+    bead-pair block for the N(N+1)/2 pairs i <= j."""
     esize = {"f64": 8, "f32": 4, "bf16": 2}[prec]
-    if packed:
-        return 3 * n * (n + 1) * esize
-    n3 = 3 * n
-    return n3 * (n3 + 1) // 2 * esize
+    return 3 * n * (n + 1) * esize
 
 
 def measured_traffic(t=TRAFFIC, key=None):

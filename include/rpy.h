@@ -71,9 +71,10 @@ typedef struct {
     int32_t lowp;      /* low-precision copy of D kept by rpy_ewald_build:
                           RPY_PREC_F64 (none), RPY_PREC_F32 or RPY_PREC_BF16 */
     int32_t max_rhs;   /* largest m accepted by rpy_apply/chebyshev_sqrt_apply
-                          (1..16); with lowp FP32/BF16 and max_rhs >= 5 the
+                          (1..16); with max_rhs >= 5 (and lma = 0) the
                           context also holds the buffers of the matrix-core
-                          block product (about 100 MB at N = 4000) */
+                          block product (per-tile FP64 partial sums and the
+                          structure-factor phases: about 150 MB at N = 4000) */
     int32_t cheb_keep; /* Chebyshev vectors V_p kept for the adaptive order
                           (bd_step and chebyshev_sqrt_apply with tol > 0,
                           chebyshev_sqrt_adaptive) and rpy_u_vjp: the largest
@@ -86,8 +87,8 @@ typedef struct {
     int32_t lma;       /* 0: high-memory form, the real-space part of D is
                           stored (upper tiles, the 6 distinct entries of
                           each symmetric 3 x 3 bead-pair block: about
-                          3N(N+1) doubles; the row-major upper tiles of the
-                          block product, when enabled, come on top).
+                          3N(N+1) doubles, read by every product of any
+                          number of vectors).
                           1: low-memory form (section "Low memory
                           algorithm"): nothing of size N^2 is stored; every
                           product recomputes the real-space sum over a cell
@@ -130,10 +131,12 @@ int rpy_ewald_build(rpy_ctx *c, const double *pos, void *stream);
  * aliased), D being the full periodic diffusion tensor of the last build:
  * the stored real-space part in arithmetic `prec` (RPY_PREC_*; FP32/BF16 need
  * the matching lowp copy) plus the reciprocal-space sum in FP64 (eq.
- * DFmodified).  With FP32/BF16 and 5 <= m <= 16 the real-space part runs on
- * the matrix cores with FP32 accumulation inside each 64-bead tile (BF16:
- * the vectors enter as a hi + lo BF16 pair, so only D is rounded to BF16);
- * the reciprocal sum and the sums over tiles stay FP64.  Results are
+ * DFmodified).  With 5 <= m <= 16 (max_rhs >= 5) the real-space part runs on
+ * the matrix cores straight from the packed tile planes: FP64 tiles on the
+ * FP64 matrix cores with FP64 accumulation, FP32 tiles with FP32
+ * accumulation inside each 64-bead tile, BF16 tiles likewise (the vectors
+ * enter as a hi + lo BF16 pair, so only D is rounded to BF16); the
+ * reciprocal sum and the sums over tiles stay FP64.  Results are
  * deterministic run to run.  Errors: RPY_EINVAL (m outside 1..max_rhs, prec
  * not built, null pointers). */
 int rpy_apply(rpy_ctx *c, const double *v, double *out, int m, int prec,

@@ -1,46 +1,48 @@
-// rpy_block.hip -- the block product Y = D.V for up to 16 vectors at once, as
+// rpy_block.hip -- the block product Y = D.V for 5 to 16 vectors at once, as
 // used by the Chebyshev recurrence (arXiv:1203.6208, eq. cheb1-cheb3: every
-// term is one product of D with the current vectors) when the stored
-// real-space tiles are FP32 or BF16.
+// term is one product of D with the current vectors), on the matrix cores.
 //
-//   1. k_pack_block: the vectors in the operand layouts below (low precision
-//      for the tiles, FP64 for the reciprocal sum).
-//   2. k_block_tiles: real-space tiles on the matrix cores, FP32 accumulation
-//      inside a tile, FP32 partial per tile and tile column, stored in blocks
-//      of 16 rows: part32[K][row / 16][j][row % 16].
+//   1. k_pack_block: the vectors in the operand layouts below (the tile
+//      product's element type, component-major; FP64 for the reciprocal sum).
+//   2. k_block_tiles: the stored packed tiles (FP64, FP32 or BF16, the same
+//      6 planes per bead row that every other product reads) times the
+//      vectors on the matrix cores, accumulation in FP64 (FP64 tiles) or FP32
+//      inside a tile, one partial per tile and tile column:
+//      bpart[K][row][j].
 //   3. k_block_sf + k_block_sf_reduce: structure factors S_k = sum_mu e^{i k.r_mu}
 //      v_mu as an FP64 matrix-core product of the phase matrix (computed once
 //      per set of positions by k_block_phases) with V, then the fixed-order
 //      chunk sum and 2 m(k) (I - khat khat) (eq. DF, third term, evaluated
-//      per product).
+//      per product).  Extra workgroups of the same launch sum the tile
+//      partials in slot order.
 //   4. k_block_epi: the back-projection sum_k (cos, sin)(k.r_nu) T_k as an
-//      FP64 matrix-core product, plus the tile partials (summed in a fixed
-//      order by extra workgroups of the k_block_sf launch), plus the
+//      FP64 matrix-core product, plus the summed tile partials, plus the
 //      recurrence step.
 // The reciprocal sum and the recurrence are FP64 throughout.
 //
-// Tile product: each wave owns one stored tile A = A_IJ (192 x 192, I <= J):
-//   row product    A   X_J  -> slot J, rows of I
-//   column product A^T X_I  -> slot I, rows of J   (I < J only)
-// as 16 x 16 MFMA output blocks (16 rows or columns x 16 vectors).  The tile
-// is read once, 16 rows (a strip) at a time, with 16-byte loads.  A lane's
-// loaded values lie along one tile row, the A-operand layout of the row
-// product (operand row = lane % 16).  The column product needs the operand
-// row to be a tile column, so each 16 x 16 (FP32) or 16 x 32 (BF16) piece is
-// transposed through a small per-wave LDS buffer.  The 12 column blocks stay
-// in registers for the whole tile; the waves never synchronise.
+// Tile product.  A stored tile (I <= J) holds, for bead rows i and columns j
+// of the two bead tiles, the six planes P_ab[i][j] (ab = xx, xy, xz, yy, yz,
+// zz) of the symmetric 3 x 3 blocks.  With x_J[j][b] the vectors of the beads
+// of J:
+//   row product     y_I[i][a] += sum_j P_ab[i][j] x_J[j][b]   -> slot J
+//   column product  y_J[j][b] += sum_i P_ab[i][j] x_I[i][a]   -> slot I (I < J)
+// for every plane and, off the plane diagonal (a != b), for ab and ba alike.
+// Each is a 64 x 64 plane times a 64 x 16 vector block: MFMA 16x16 blocks of
+// 16 beads x 16 vectors, FP64 16x16x4 for FP64 tiles, FP32 16x16x4 for FP32
+// tiles and BF16 16x16x32 (the vectors split into a hi + lo BF16 pair, so
+// only D is rounded) for BF16 tiles.
+#include <hip/hip_ext.h>
+
 #include "rpy_internal.h"
 
 namespace rpy {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
 typedef double d4v __attribute__((ext_vector_type(4)));
-typedef short s4v __attribute__((ext_vector_type(4)));
 typedef uint32_t u4v __attribute__((ext_vector_type(4)));
-typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
-constexpr int TLD32 = 20;      // FP32 transpose buffer row stride (floats)
-constexpr int TLD16 = 40;      // BF16 transpose buffer row stride (bf16)
 constexpr int SF_WAVES = 4;    // waves per structure-factor workgroup
 
 __device__ inline uint16_t bf16_rne(float f)
@@ -50,277 +52,386 @@ __device__ inline uint16_t bf16_rne(float f)
     return (uint16_t)(u >> 16);
 }
 
-// Packed vectors, zero beyond n3 and beyond m:
-//   FP32: xq[r / 4][j][r % 4]
-//   BF16: xh[r / 8][j][r % 8] = bf16(x), xl[...] = bf16(x - xh) (a hi + lo
-//         pair: the operand carries about 16 significant bits of x)
-//   FP64: vpk[r][j]
-// so that a lane's operand for 4 (8) consecutive rows of one vector is a
-// single 16-byte load, and 16 lanes read 16 vectors of one row together.
-__global__ void k_pack_block(int n3, int n3pad, int m, int bf16, const double *__restrict__ v,
-                             void *__restrict__ xpk, double *__restrict__ vpk,
-                             const int *__restrict__ gate)
+// Packed vectors, zero for beads >= N and vectors >= m (npad = padded beads):
+//   FP64, FP32: xs[c][bead][j]
+//   BF16:       xh[c][j][bead] = bf16(x), xl[c][j][bead] = bf16(x - xh), xl
+//               at xh + 3 npad 16 (a hi + lo pair: about 16 significant bits)
+//   FP64:       vpk[r][j], r = 3 bead + c (the reciprocal sum's operand)
+// so that a workgroup stages the 64 beads of a bead tile with contiguous
+// loads, and 16 lanes read 16 vectors of one row together.
+__global__ void k_pack_block(int N, int n3, int npad, int m, int prec,
+                             const double *__restrict__ v, void *__restrict__ xs,
+                             double *__restrict__ vpk, const int *__restrict__ gate)
 {
     if (gate && *gate) return;   // a product past the settled adaptive order
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= n3pad * BLOCK_RHS) return;
+    if (o >= 3 * npad * BLOCK_RHS) return;
     {
         const int r = o >> 4, j = o & 15;
         vpk[o] = (j < m && r < n3) ? v[(size_t)j * n3 + r] : 0.0;
     }
-    int r, j;
-    if (bf16) {
-        r = (o >> 7) * 8 + (o & 7);
-        j = (o >> 3) & 15;
-    } else {
-        r = (o >> 6) * 4 + (o & 3);
-        j = (o >> 2) & 15;
-    }
-    const double x = (j < m && r < n3) ? v[(size_t)j * n3 + r] : 0.0;
-    if (bf16) {
-        uint16_t *xh = reinterpret_cast<uint16_t *>(xpk);
+    if (prec == RPY_PREC_BF16) {
+        const int bead = o % npad, cj = o / npad, j = cj & 15, c = cj >> 4;
+        const double x = (j < m && bead < N) ? v[(size_t)j * n3 + 3 * bead + c] : 0.0;
+        uint16_t *xh = reinterpret_cast<uint16_t *>(xs);
         const uint16_t h = bf16_rne((float)x);
         const double hv = (double)__uint_as_float((uint32_t)h << 16);
         xh[o] = h;
-        xh[(size_t)n3pad * BLOCK_RHS + o] = bf16_rne((float)(x - hv));
+        xh[(size_t)3 * npad * BLOCK_RHS + o] = bf16_rne((float)(x - hv));
     } else {
-        reinterpret_cast<float *>(xpk)[o] = (float)x;
+        const int j = o & 15, bead = (o >> 4) % npad, c = (o >> 4) / npad;
+        const double x = (j < m && bead < N) ? v[(size_t)j * n3 + 3 * bead + c] : 0.0;
+        if (prec == RPY_PREC_F64) reinterpret_cast<double *>(xs)[o] = x;
+        else reinterpret_cast<float *>(xs)[o] = (float)x;
     }
 }
 
-// Orders this wave's LDS writes before its following LDS reads (and the
-// reads before the next overwrite).  Only lanes of one wave share a buffer.
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// ---------------------------------------------------------------- FP32
-// Half strip (R, h): rows 16R .. 16R + 15, columns 96h .. 96h + 95, six
-// chunks C = 6h + c of 16 columns.  Lane (g = lane / 16, i = lane % 16) holds
-// A[16R + i][16C + 4g + s], s = 0..3.  Row product step s: operand row i,
-// k = g <-> column 16C + 4g + s, B = X_J[16C + 4g + s][i].  Column product
-// step s (after the transpose): operand row i <-> column 16C + i,
-// k = g <-> row 16R + 4g + s, B = X_I[16R + 4g + s][i].  The loads of a
-// half strip are X_I for its rows (first half only) then its 6 tile pieces,
-// so that waiting for them never waits for a later prefetch.
-constexpr int RING32 = 3;      // half strips in flight per wave (FP32)
-constexpr int RING16 = 4;      // strips in flight per wave (BF16)
-
-struct Half32 {
-    f4v xi;
-    f4v a[6];
+// Per element type: the lane's 16-byte loads of a plane row, the vector and
+// accumulator types, the LDS row stride of a transposed plane (padded so
+// that the 16 rows a read instruction touches spread over the banks), and
+// the waves of a tile's workgroup: 8 for FP64 and FP32 (each contraction
+// split in two halves, 2.0x and 1.1x faster than 4 waves at N = 4000, FP64
+// 150.6 -> 129.7 us, FP32 69.0 -> 61.9 us), 4 for BF16 (the matrix cores are
+// lightly loaded and the extra barriers cost more: 35.7 against 44.9 us).
+//   A wave holds 16 bead rows i = 16 w + (lane % 16) of a plane; lane group
+//   g = lane / 16 loads NLD pieces of EPL entries, the piece p covering the
+//   columns col(p, g, e) = 4 EPL p + EPL g + e, e < EPL.  A matrix-core step
+//   contracts over the 4 (FP64, FP32: one entry each) or 32 (BF16: EPL = 8
+//   each) columns that the four lane groups hold for one (p, e) (BF16: one
+//   p); the vector operand of lane (g, n) is x at the same column, vector n.
+template <typename T> struct BK;
+template <> struct BK<double> {
+    typedef d2v ld_t;
+    typedef double x_t;
+    typedef d4v acc_t;
+    typedef double part_t;
+    static constexpr int EPL = 2, NLD = 8, PLD = 66, NWAVE = 8;
+    // accumulator entry e of lane group g is row g + 4 e of the 16 x 16 block
+    __device__ static int orow(int g, int e) { return g + 4 * e; }
+};
+template <> struct BK<float> {
+    typedef f4v ld_t;
+    typedef float x_t;
+    typedef f4v acc_t;
+    typedef float part_t;
+    static constexpr int EPL = 4, NLD = 4, PLD = 68, NWAVE = 8;
+    __device__ static int orow(int g, int e) { return 4 * g + e; }
+};
+template <> struct BK<uint16_t> {
+    typedef u4v ld_t;
+    typedef uint16_t x_t;
+    typedef f4v acc_t;
+    typedef float part_t;
+    static constexpr int EPL = 8, NLD = 2, PLD = 72, NWAVE = 4;
+    __device__ static int orow(int g, int e) { return 4 * g + e; }
 };
 
-__device__ inline void load_half32(const float *tile, const float *xq, int rowI, int q, int i,
-                                   int g, Half32 &s)
+__device__ inline int plane_a(int c) { return c < 3 ? 0 : (c < 5 ? 1 : 2); }
+__device__ inline int plane_b(int c) { return c < 3 ? c : (c < 5 ? c - 2 : 2); }
+
+__device__ inline d4v mfma(double a, double b, d4v c)
 {
-    const int R = q >> 1, h = q & 1;
-    if (h == 0)
-        s.xi = *reinterpret_cast<const f4v *>(xq + (size_t)((rowI + 16 * R) / 4 + g) * 64 + 4 * i);
-    const float *row = tile + (size_t)(16 * R + i) * TS + 96 * h + 4 * g;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) s.a[c] = *reinterpret_cast<const f4v *>(row + 16 * c);
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4v mfma(float a, float b, f4v c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline f4v mfma(u4v a, u4v b, f4v c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a),
+                                                   __builtin_bit_cast(bf8v, b), c, 0, 0, 0);
 }
 
-// racc[2]: two accumulators (even and odd chunks) halve the dependent chain.
-__device__ inline void half32(const Half32 &s, const f4v &xi, int h, bool offd, int i, int g,
-                              const f4v *xj, float *tb, f4v *cacc, f4v *racc)
-{
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const int C = 6 * h + c;
-        const f4v a = s.a[c];
-        f4v &ra = racc[c & 1];
-        ra = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, xj[C].x, ra, 0, 0, 0);
-        ra = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, xj[C].y, ra, 0, 0, 0);
-        ra = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, xj[C].z, ra, 0, 0, 0);
-        ra = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, xj[C].w, ra, 0, 0, 0);
-        if (offd) {
-            *reinterpret_cast<f4v *>(tb + i * TLD32 + 4 * g) = a;
-            wave_lds_sync();
-            const float t0 = tb[(4 * g + 0) * TLD32 + i];
-            const float t1 = tb[(4 * g + 1) * TLD32 + i];
-            const float t2 = tb[(4 * g + 2) * TLD32 + i];
-            const float t3 = tb[(4 * g + 3) * TLD32 + i];
-            wave_lds_sync();
-            cacc[C] = __builtin_amdgcn_mfma_f32_16x16x4f32(t0, xi.x, cacc[C], 0, 0, 0);
-            cacc[C] = __builtin_amdgcn_mfma_f32_16x16x4f32(t1, xi.y, cacc[C], 0, 0, 0);
-            cacc[C] = __builtin_amdgcn_mfma_f32_16x16x4f32(t2, xi.z, cacc[C], 0, 0, 0);
-            cacc[C] = __builtin_amdgcn_mfma_f32_16x16x4f32(t3, xi.w, cacc[C], 0, 0, 0);
-        }
-    }
-}
-
-// ---------------------------------------------------------------- BF16
-// Strip R, chunk C (32 columns): lane holds A[16R + i][32C + 8g + e],
-// e = 0..7 (one 16-byte load).  Row product: elements 0..3 and 4..7 are two
-// K = 16 operands with k = 4g + e <-> column 32C + 8g + e (+4), B = the
-// matching rows of X_J (hi and lo parts, FP32 accumulate).  Column product
-// for the column half h: operand row i <-> column 32C + 16h + i,
-// k = 4g + e <-> row 16R + 4g + e.
-struct Strip16 {
-    u2v xih, xil;
-    u4v a[TS / 32];
+// A wave's part of a plane stripe: NH loads of 16 bytes per lane, the
+// pieces h NH .. (h + 1) NH - 1 (NH = NLD with 4 waves, NLD / 2 with 8).  The streamed operand is not declared
+// __restrict__ and the ring lives in fixed registers (the caller's loop is
+// unrolled): loads the compiler may treat as invariant get rematerialised at
+// their use, which undoes the prefetch.
+template <typename T> struct Stripe {
+    typename BK<T>::ld_t v[BK<T>::NLD * 4 / BK<T>::NWAVE];
 };
 
-__device__ inline void load_strip16(const uint16_t *tile, const uint16_t *xh,
-                                    const uint16_t *xl, int rowI, int R, int i, int g,
-                                    Strip16 &s)
+template <typename T, bool CACHED>
+__device__ inline void load_stripe(const T *tiles, int t, int c, int row, int g, int h,
+                                   Stripe<T> &s)
 {
-    const size_t xo = (size_t)((rowI + 16 * R) / 8 + (g >> 1)) * 128 + 8 * i + 4 * (g & 1);
-    s.xih = *reinterpret_cast<const u2v *>(xh + xo);
-    s.xil = *reinterpret_cast<const u2v *>(xl + xo);
-    const uint16_t *row = tile + (size_t)(16 * R + i) * TS + 8 * g;
+    typedef typename BK<T>::ld_t L;
+    constexpr int NH = BK<T>::NLD * 4 / BK<T>::NWAVE;
+    const T *p = tiles + (size_t)t * TILE6 + ((size_t)row * 6 + c) * TB + BK<T>::EPL * g +
+                 4 * BK<T>::EPL * NH * h;
 #pragma unroll
-    for (int C = 0; C < TS / 32; ++C) s.a[C] = *reinterpret_cast<const u4v *>(row + 32 * C);
-}
-
-__device__ inline s4v as_s4(uint32_t x, uint32_t y)
-{
-    return __builtin_bit_cast(s4v, u2v{x, y});
-}
-
-__device__ inline void strip16(const Strip16 &s, int R, bool offd, int i, int g,
-                               const u4v *xjh, const u4v *xjl, uint16_t *tb, f4v *cacc,
-                               float *prow, bool store)
-{
-    const s4v xih = as_s4(s.xih.x, s.xih.y), xil = as_s4(s.xil.x, s.xil.y);
-    f4v racc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-    for (int C = 0; C < TS / 32; ++C) {
-        const u4v a = s.a[C];
-        const s4v a0 = as_s4(a.x, a.y), a1 = as_s4(a.z, a.w);
-        f4v &ra = racc[C & 1];
-        ra = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, as_s4(xjh[C].x, xjh[C].y), ra, 0, 0, 0);
-        ra = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, as_s4(xjl[C].x, xjl[C].y), ra, 0, 0, 0);
-        ra = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, as_s4(xjh[C].z, xjh[C].w), ra, 0, 0, 0);
-        ra = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, as_s4(xjl[C].z, xjl[C].w), ra, 0, 0, 0);
-        if (offd) {
-            *reinterpret_cast<u4v *>(tb + i * TLD16 + 8 * g) = a;
-            wave_lds_sync();
-            uint32_t t[2][2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const uint16_t *q = tb + (4 * g) * TLD16 + 16 * h + i;
-                t[h][0] = (uint32_t)q[0] | ((uint32_t)q[TLD16] << 16);
-                t[h][1] = (uint32_t)q[2 * TLD16] | ((uint32_t)q[3 * TLD16] << 16);
-            }
-            wave_lds_sync();
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const s4v at = as_s4(t[h][0], t[h][1]);
-                f4v &cc = cacc[2 * C + h];
-                cc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at, xih, cc, 0, 0, 0);
-                cc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at, xil, cc, 0, 0, 0);
-            }
-        }
+    for (int k = 0; k < NH; ++k) {
+        const L *a = reinterpret_cast<const L *>(p + 4 * BK<T>::EPL * k);
+        if constexpr (CACHED) s.v[k] = *a;
+        else s.v[k] = __builtin_nontemporal_load(a);
     }
-    if (store) *reinterpret_cast<f4v *>(prow + 256 * R) = racc[0] + racc[1];
 }
 
-// Wave w of workgroup b takes stored tile 4 b + w.  The strip loop is fully
-// unrolled so that the ring of prefetched strips lives in registers and the
-// load waits stay per strip.
-template <int BF16>
-__global__ __launch_bounds__(256) void k_block_tiles(int n3pad, int m, int ntiles,
+// LDS of a workgroup: the vectors of both bead tiles, and two buffers of one
+// transposed plane, pb[col][row].
+template <typename T> struct alignas(32) BlkLds {
+    static constexpr int XN = 3 * TB * BLOCK_RHS;   // entries per bead tile (x 2 for BF16 hi/lo)
+    static constexpr int XW = (sizeof(T) == 2 ? 2 : 1) * XN;
+    typename BK<T>::x_t xj[XW], xi[XW];
+    T pb[2][TB * BK<T>::PLD];
+};
+
+// Workgroup b (4 or 8 waves) takes the stored tiles b, b + gridDim.x, ... (a
+// persistent loop, so that the plane loads run ahead across tiles).  Wave w
+// (row group r = w % 4, half h = w / 4) owns the bead rows 16 r .. 16 r + 15
+// for the row product and the bead columns 16 r .. 16 r + 15 for the column
+// product, and (with 8 waves) half of each contraction: the columns (row
+// product) and rows (column product) of the pieces h NH .. (h + 1) NH - 1.
+// Per plane it loads its part of the rows (two planes ahead), runs its part
+// of the row product from registers, writes those rows transposed to LDS,
+// and after one barrier runs its part of the column product.  With 8 waves
+// the two halves are added at the end of a tile in a fixed order (h = 0 plus
+// h = 1).  Diagonal tiles hold
+// both (i, j) and (j, i) and take the row product only.  The partials of a
+// tile go to bpart[K][row][j] (K = J, rows of I for the row product; K = I,
+// rows of J for the column product), every (K, row) written by exactly one
+// tile.
+template <typename T, bool CACHED>
+__global__ __launch_bounds__(64 * BK<T>::NWAVE) void k_block_tiles(int ntiles, int npad, int n3pad,
                                                      const int2 *__restrict__ tile_ij,
-                                                     const void *__restrict__ tiles,
-                                                     const void *__restrict__ xpk,
-                                                     float *__restrict__ part,
+                                                     const T *tiles,
+                                                     const typename BK<T>::x_t *__restrict__ xs,
+                                                     typename BK<T>::part_t *__restrict__ bpart,
                                                      const int *__restrict__ gate)
 {
-    __shared__ float tbuf[4 * 16 * (BF16 ? TLD16 / 2 : TLD32)];
-    if (gate && *gate) return;
+    typedef BK<T> K;
+    typedef typename K::acc_t A;
+    typedef typename K::x_t X;
+    typedef typename K::part_t P;
+    constexpr int EPL = K::EPL, NLD = K::NLD, PLD = K::PLD, NW = K::NWAVE, NH = NLD * 4 / NW;
+    constexpr bool BF = sizeof(T) == 2;
+    constexpr int XN = BlkLds<T>::XN;
+    __shared__ BlkLds<T> L;
+    static_assert(sizeof(BlkLds<T>) >= 4 * 64 * 6 * sizeof(A), "LDS too small for the halves");
+    if (gate && *gate) return;   // a product past the settled adaptive order
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = lane & 15, g = lane >> 4;
-    const int t = (int)blockIdx.x * 4 + w;
-    if (t >= ntiles) return;
-    const int2 ij = tile_ij[t];
-    const int I = ij.x, J = ij.y;
-    const bool offd = I != J;
-    const bool store = i < m;
-    // output blocks of 16 rows x 16 vectors are contiguous (1 KB): row block
-    // I*12 + R of slot J (row product), J*12 + C of slot I (column product);
-    // lane (g, i) holds rows 4g .. 4g + 3 of vector i
-    const int nrb = n3pad / 16;
-    float *prow = part + ((size_t)J * nrb + I * (TS / 16)) * 256 + 16 * i + 4 * g;
-    float *pcol = part + ((size_t)I * nrb + J * (TS / 16)) * 256 + 16 * i + 4 * g;
-    f4v cacc[TS / 16];
-#pragma unroll
-    for (int C = 0; C < TS / 16; ++C) cacc[C] = f4v{0.f, 0.f, 0.f, 0.f};
-    if (!BF16) {
-        const float *tile = reinterpret_cast<const float *>(tiles) + (size_t)t * TILE_ELEMS;
-        const float *xq = reinterpret_cast<const float *>(xpk);
-        float *tb = tbuf + w * 16 * TLD32;
-        f4v xj[TS / 16];
-#pragma unroll
-        for (int C = 0; C < TS / 16; ++C)
-            xj[C] = *reinterpret_cast<const f4v *>(xq + (size_t)((J * TS + 16 * C) / 4 + g) * 64 + 4 * i);
-        constexpr int NQ = 2 * (TS / 16);   // half strips per tile
-        Half32 ring[RING32];
-#pragma unroll
-        for (int q = 0; q < RING32 - 1; ++q) load_half32(tile, xq, I * TS, q, i, g, ring[q]);
-        f4v xi = {0.f, 0.f, 0.f, 0.f};
-        f4v racc[2];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            if (q + RING32 - 1 < NQ)
-                load_half32(tile, xq, I * TS, q + RING32 - 1, i, g, ring[(q + RING32 - 1) % RING32]);
-            const int h = q & 1;
-            if (h == 0) {
-                xi = ring[q % RING32].xi;
-                racc[0] = racc[1] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int rg = w & 3, h = w >> 2;
+    const int n = lane & 15, g = lane >> 4;
+    const int row = 16 * rg + n;   // this lane's bead row of a plane stripe (column of P^T)
+    const int step = gridDim.x;
+    Stripe<T> ring[3];
+    int t = blockIdx.x;
+    if (t < ntiles) {
+        load_stripe<T, CACHED>(tiles, t, 0, row, g, h, ring[0]);
+        load_stripe<T, CACHED>(tiles, t, 1, row, g, h, ring[1]);
+    }
+    for (; t < ntiles; t += step) {
+        const int2 ij = tile_ij[t];
+        const int I = ij.x, J = ij.y;
+        const bool offd = I != J;
+        __syncthreads();   // the previous tile's readers of L are done
+        // stage the vectors of J (row product) and I (column product)
+        if constexpr (BF) {
+            const X *xh = xs, *xl = xs + (size_t)3 * npad * BLOCK_RHS;
+            for (int e = threadIdx.x; e < 2 * XN; e += 64 * NW) {
+                const int hl = e / XN, r = e % XN, cj = r / TB, bead = r % TB;
+                const size_t o = (size_t)cj * npad + bead;
+                L.xj[e] = (hl ? xl : xh)[o + (size_t)J * TB];
+                L.xi[e] = (hl ? xl : xh)[o + (size_t)I * TB];
             }
-            half32(ring[q % RING32], xi, h, offd, i, g, xj, tb, cacc, racc);
-            if (h == 1 && store)
-                *reinterpret_cast<f4v *>(prow + 256 * (q >> 1)) = racc[0] + racc[1];
+        } else {
+            for (int e = threadIdx.x; e < XN; e += 64 * NW) {
+                const int c = e / (TB * BLOCK_RHS), r = e % (TB * BLOCK_RHS);
+                const size_t o = (size_t)c * npad * BLOCK_RHS + r;
+                L.xj[e] = xs[o + (size_t)J * TB * BLOCK_RHS];
+                L.xi[e] = xs[o + (size_t)I * TB * BLOCK_RHS];
+            }
         }
-    } else {
-        const uint16_t *tile = reinterpret_cast<const uint16_t *>(tiles) + (size_t)t * TILE_ELEMS;
-        const uint16_t *xh = reinterpret_cast<const uint16_t *>(xpk);
-        const uint16_t *xl = xh + (size_t)n3pad * BLOCK_RHS;
-        uint16_t *tb = reinterpret_cast<uint16_t *>(tbuf) + w * 16 * TLD16;
-        u4v xjh[TS / 32], xjl[TS / 32];
+        A dacc[3], tacc[3];
 #pragma unroll
-        for (int C = 0; C < TS / 32; ++C) {
-            const size_t o = (size_t)((J * TS + 32 * C) / 8 + g) * 128 + 8 * i;
-            xjh[C] = *reinterpret_cast<const u4v *>(xh + o);
-            xjl[C] = *reinterpret_cast<const u4v *>(xl + o);
+        for (int a = 0; a < 3; ++a) dacc[a] = tacc[a] = A{};
+        __syncthreads();
+        const int tn = t + step;   // the tile whose first planes are loaded at the end
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            // two planes ahead; planes 4 and 5 fetch planes 0 and 1 of the next tile
+            if (c + 2 < 6) load_stripe<T, CACHED>(tiles, t, c + 2, row, g, h, ring[(c + 2) % 3]);
+            else if (tn < ntiles) load_stripe<T, CACHED>(tiles, tn, c - 4, row, g, h, ring[(c + 2) % 3]);
+            __asm__ volatile("" ::: "memory");
+            const Stripe<T> &st = ring[c % 3];
+            const int a = plane_a(c), b = plane_b(c);
+            // row product: A = P rows (this lane's row, columns col(p, g, e)),
+            // B = x_J at those columns
+#pragma unroll
+            for (int pp = 0; pp < NH; ++pp) {
+                const int p = NH * h + pp;
+                if constexpr (BF) {
+                    const int col0 = 4 * EPL * p + EPL * g;
+                    const u4v av = st.v[pp];
+                    const u4v xbh = *reinterpret_cast<const u4v *>(&L.xj[(b * 16 + n) * TB + col0]);
+                    const u4v xbl = *reinterpret_cast<const u4v *>(&L.xj[XN + (b * 16 + n) * TB + col0]);
+                    dacc[a] = mfma(av, xbh, dacc[a]);
+                    dacc[a] = mfma(av, xbl, dacc[a]);
+                    if (a != b) {
+                        const u4v xah = *reinterpret_cast<const u4v *>(&L.xj[(a * 16 + n) * TB + col0]);
+                        const u4v xal = *reinterpret_cast<const u4v *>(&L.xj[XN + (a * 16 + n) * TB + col0]);
+                        dacc[b] = mfma(av, xah, dacc[b]);
+                        dacc[b] = mfma(av, xal, dacc[b]);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < EPL; ++e) {
+                        const int col = 4 * EPL * p + EPL * g + e;
+                        const X av = st.v[pp][e];
+                        dacc[a] = mfma(av, L.xj[(b * TB + col) * 16 + n], dacc[a]);
+                        if (a != b) dacc[b] = mfma(av, L.xj[(a * TB + col) * 16 + n], dacc[b]);
+                    }
+                }
+            }
+            if (offd) {
+                // this wave's half rows -> LDS, transposed: pb[col][row]
+                T *pb = L.pb[c & 1];
+#pragma unroll
+                for (int pp = 0; pp < NH; ++pp) {
+                    const int p = NH * h + pp;
+                    if constexpr (BF) {
+                        const u4v av = st.v[pp];
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const uint32_t wd = av[e >> 1];
+                            pb[(4 * EPL * p + EPL * g + e) * PLD + row] =
+                                (uint16_t)((e & 1) ? (wd >> 16) : (wd & 0xFFFFu));
+                        }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < EPL; ++e)
+                            pb[(4 * EPL * p + EPL * g + e) * PLD + row] = st.v[pp][e];
+                    }
+                }
+            }
+            __syncthreads();
+            if (offd) {
+                // column product: A = P^T rows (this lane's column, rows
+                // col(p, g, e) of the plane), B = x_I at those rows
+                const T *pr = L.pb[c & 1] + (size_t)row * PLD;
+#pragma unroll
+                for (int pp = 0; pp < NH; ++pp) {
+                    const int p = NH * h + pp;
+                    const int i0 = 4 * EPL * p + EPL * g;
+                    const typename K::ld_t av = *reinterpret_cast<const typename K::ld_t *>(pr + i0);
+                    if constexpr (BF) {
+                        const u4v xah = *reinterpret_cast<const u4v *>(&L.xi[(a * 16 + n) * TB + i0]);
+                        const u4v xal = *reinterpret_cast<const u4v *>(&L.xi[XN + (a * 16 + n) * TB + i0]);
+                        tacc[b] = mfma(av, xah, tacc[b]);
+                        tacc[b] = mfma(av, xal, tacc[b]);
+                        if (a != b) {
+                            const u4v xbh = *reinterpret_cast<const u4v *>(&L.xi[(b * 16 + n) * TB + i0]);
+                            const u4v xbl = *reinterpret_cast<const u4v *>(&L.xi[XN + (b * 16 + n) * TB + i0]);
+                            tacc[a] = mfma(av, xbh, tacc[a]);
+                            tacc[a] = mfma(av, xbl, tacc[a]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < EPL; ++e) {
+                            const X at = av[e];
+                            tacc[b] = mfma(at, L.xi[(a * TB + i0 + e) * 16 + n], tacc[b]);
+                            if (a != b) tacc[a] = mfma(at, L.xi[(b * TB + i0 + e) * 16 + n], tacc[a]);
+                        }
+                    }
+                }
+            }
         }
-        Strip16 ring[RING16];
+        if constexpr (NW == 8) {
+            // the two halves, added in a fixed order through LDS (the vectors
+            // and planes of this tile are no longer read after the barrier)
+            __syncthreads();
+            A *hbuf = reinterpret_cast<A *>(&L);   // [row group][6 accumulators][64 lanes]
+            if (h == 1) {
 #pragma unroll
-        for (int R = 0; R < RING16 - 1; ++R) load_strip16(tile, xh, xl, I * TS, R, i, g, ring[R]);
+                for (int a = 0; a < 3; ++a) {
+                    hbuf[(rg * 6 + a) * 64 + lane] = dacc[a];
+                    hbuf[(rg * 6 + 3 + a) * 64 + lane] = tacc[a];
+                }
+            }
+            __syncthreads();
+            if (h == 0) {
 #pragma unroll
-        for (int R = 0; R < TS / 16; ++R) {
-            if (R + RING16 - 1 < TS / 16)
-                load_strip16(tile, xh, xl, I * TS, R + RING16 - 1, i, g,
-                             ring[(R + RING16 - 1) % RING16]);
-            strip16(ring[R % RING16], R, offd, i, g, xjh, xjl, tb, cacc, prow, store);
+                for (int a = 0; a < 3; ++a) {
+                    dacc[a] = dacc[a] + hbuf[(rg * 6 + a) * 64 + lane];
+                    tacc[a] = tacc[a] + hbuf[(rg * 6 + 3 + a) * 64 + lane];
+                }
+            }
+        }
+        if (h == 0) {
+            // entry e of lane (g, n) is bead 16 rg + orow(g, e), vector n
+            P *pd = bpart + ((size_t)J * n3pad + (size_t)I * TS) * 16 + n;
+            P *pt = bpart + ((size_t)I * n3pad + (size_t)J * TS) * 16 + n;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int bead = 16 * rg + K::orow(g, e);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    pd[(size_t)(3 * bead + a) * 16] = dacc[a][e];
+                    if (offd) pt[(size_t)(3 * bead + a) * 16] = tacc[a][e];
+                }
+            }
         }
     }
-    if (offd && store) {
-#pragma unroll
-        for (int C = 0; C < TS / 16; ++C)
-            *reinterpret_cast<f4v *>(pcol + 256 * C) = cacc[C];
-    }
+}
+
+// Tile arrays that fit the Infinity Cache (TILE_CACHE_BYTES) are read with
+// allocating loads, so that they stay resident from one product to the next.
+// The persistent grid: as many workgroups as the device holds at once
+// (compute units x resident workgroups of this kernel), found once per
+// context and precision.
+template <typename T, bool CACHED> static auto block_kernel()
+{
+    return k_block_tiles<T, CACHED>;
+}
+
+template <typename T, bool CACHED> static int block_grid(const Ctx &c)
+{
+    int &g = c.block_wgs[sizeof(T) == 8 ? 0 : sizeof(T) == 4 ? 1 : 2];
+    if (g > 0) return g;
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, block_kernel<T, CACHED>(), 64 * BK<T>::NWAVE, 0) !=
+            hipSuccess ||
+        cus < 1 || per < 1)
+        return 256;   // not cached: asked again next time
+    g = cus * per;
+    return g;
+}
+
+template <typename T>
+static void block_tiles_launch(const Ctx &c, const T *tiles, hipStream_t s)
+{
+    const bool cached = (size_t)c.ntiles * TILE6 * sizeof(T) <= TILE_CACHE_BYTES;
+    const int cap = cached ? block_grid<T, true>(c) : block_grid<T, false>(c);
+    const int grid = c.ntiles < cap ? c.ntiles : cap;
+    const int npad = c.nbt * TB;
+    typedef typename BK<T>::x_t X;
+    typedef typename BK<T>::part_t P;
+    hipEvent_t e0 = c.prof_ev0, e1 = c.prof_ev1;
+    c.prof_ev0 = c.prof_ev1 = nullptr;
+    if (cached)
+        hipExtLaunchKernelGGL((block_kernel<T, true>()), dim3(grid), dim3(64 * BK<T>::NWAVE), 0, s, e0, e1, 0u,
+                              c.ntiles, npad, c.n3pad, c.tile_ij, tiles,
+                              reinterpret_cast<const X *>(c.xpk), reinterpret_cast<P *>(c.bpart),
+                              c.gate);
+    else
+        hipExtLaunchKernelGGL((block_kernel<T, false>()), dim3(grid), dim3(64 * BK<T>::NWAVE), 0, s, e0, e1, 0u,
+                              c.ntiles, npad, c.n3pad, c.tile_ij, tiles,
+                              reinterpret_cast<const X *>(c.xpk), reinterpret_cast<P *>(c.bpart),
+                              c.gate);
 }
 
 void launch_block_tiles(const Ctx &c, int prec, const double *v, int m, hipStream_t s)
 {
-    const int bf16 = prec == RPY_PREC_BF16;
-    const int np = c.n3pad * BLOCK_RHS;
-    hipLaunchKernelGGL(k_pack_block, dim3((np + 255) / 256), dim3(256), 0, s, c.n3, c.n3pad, m,
-                       bf16, v, c.xpk, c.vpk, c.gate);
-    const dim3 grid((c.ntiles + 3) / 4);
-    if (bf16)
-        hipLaunchKernelGGL(k_block_tiles<1>, grid, dim3(256), 0, s, c.n3pad, m, c.ntiles,
-                           c.tile_ij, (const void *)c.d16, (const void *)c.xpk, c.part32, c.gate);
-    else
-        hipLaunchKernelGGL(k_block_tiles<0>, grid, dim3(256), 0, s, c.n3pad, m, c.ntiles,
-                           c.tile_ij, (const void *)c.d32, (const void *)c.xpk, c.part32, c.gate);
+    const int npad = c.nbt * TB;
+    const int np = 3 * npad * BLOCK_RHS;
+    hipLaunchKernelGGL(k_pack_block, dim3((np + 255) / 256), dim3(256), 0, s, c.N, c.n3, npad, m,
+                       prec, v, c.xpk, c.vpk, c.gate);
+    if (prec == RPY_PREC_BF16) block_tiles_launch<uint16_t>(c, c.p16, s);
+    else if (prec == RPY_PREC_F32) block_tiles_launch<float>(c, c.p32, s);
+    else block_tiles_launch<double>(c, c.d64, s);
 }
 
 // ------------------------------------------------- structure factors (FP64)
@@ -379,25 +490,24 @@ struct SfLd {
 // treat as invariant get rematerialised at their use, which undoes the
 // prefetch.
 // Workgroups past the structure-factor grid (blockIdx.x >= nkb) sum the
-// tile partials instead, 16 beads each (3 row blocks of 16 rows x 16
-// vectors, contiguous per slot K): 16 slots per batch of independent loads,
-// summed pairwise inside a batch and batch after batch in K order, into
+// tile partials instead, 16 beads each (48 rows x 16 vectors, contiguous in
+// every slot K): 16 slots per batch of independent loads, summed pairwise
+// inside a batch and batch after batch in K order, in FP64, into
 // ypart[j][row].  This HBM stream overlaps the matrix-core work.
+template <typename P>
 __device__ inline void block_part_sum(int b, int N, int n3, int n3pad, int m, int nslot,
-                                      const float *__restrict__ part, double *__restrict__ ypart)
+                                      const P *__restrict__ part, double *__restrict__ ypart)
 {
     const int nu0 = 16 * b, nb = min(16, N - nu0);
-    const int nrb = n3pad / 16;
-    for (int o = threadIdx.x; o < BLOCK_RHS * 48; o += blockDim.x) {
-        const int rbl = o >> 8, j = (o >> 4) & 15, rr = o & 15;
-        const int r = 16 * rbl + rr;     // row of the 48
+    const size_t ks = (size_t)n3pad * BLOCK_RHS;
+    for (int o = threadIdx.x; o < 48 * BLOCK_RHS; o += blockDim.x) {
+        const int r = o >> 4, j = o & 15;   // row 3 nu0 + r, vector j
         if (r >= 3 * nb || j >= m) continue;
-        const float *pp = part + (size_t)(3 * b + rbl) * 256 + 16 * j + rr;
-        const size_t ks = (size_t)nrb * 256;
+        const P *pp = part + ((size_t)3 * nu0 + r) * BLOCK_RHS + j;
         double y = 0.0;
         int K = 0;
         for (; K + 16 <= nslot; K += 16) {
-            float q[16];
+            P q[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) q[u] = pp[(K + u) * ks];
             double t[8];
@@ -414,7 +524,7 @@ __global__ __launch_bounds__(256) void k_block_sf(int nk, int nk16, int nq, int 
                                                   int N, int n3, int n3pad, int m, int nslot,
                                                   const double2 *eph, const double *vpk,
                                                   double *sfpart,
-                                                  const float *__restrict__ part,
+                                                  const void *__restrict__ part, int part64,
                                                   double *__restrict__ ypart,
                                                   const int *__restrict__ gate)
 {
@@ -422,7 +532,14 @@ __global__ __launch_bounds__(256) void k_block_sf(int nk, int nk16, int nq, int 
     if (gate && *gate) return;
     if ((int)blockIdx.x >= nkb) {
         const int b = (blockIdx.x - nkb) + blockIdx.y * (gridDim.x - nkb);
-        if (16 * b < N) block_part_sum(b, N, n3, n3pad, m, nslot, part, ypart);
+        if (16 * b < N) {
+            if (part64)
+                block_part_sum(b, N, n3, n3pad, m, nslot, reinterpret_cast<const double *>(part),
+                               ypart);
+            else
+                block_part_sum(b, N, n3, n3pad, m, nslot, reinterpret_cast<const float *>(part),
+                               ypart);
+        }
         return;
     }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -531,7 +648,7 @@ __global__ void k_block_sf_reduce(int nk, int nch, const KCoef *__restrict__ kco
     d[2 * BLOCK_RHS] = kc.w * (t2 - kc.hz * h);
 }
 
-void launch_block_sf(const Ctx &c, int m, hipStream_t s)
+void launch_block_sf(const Ctx &c, int m, int prec, hipStream_t s)
 {
     const int nq = (c.N + 3) / 4;
     const int cq = (nq + c.nchb - 1) / c.nchb;
@@ -542,7 +659,8 @@ void launch_block_sf(const Ctx &c, int m, hipStream_t s)
     const int px = (npg + c.nchb - 1) / c.nchb;
     hipLaunchKernelGGL(k_block_sf, dim3(nkb + px, c.nchb), dim3(64 * SF_WAVES), 0, s, c.nk,
                        (c.nk + 15) / 16 * 16, nq, cq, nkb, c.N, c.n3, c.n3pad, m, c.nbt, c.eph,
-                       c.vpk, c.sfpart, c.part32, c.ypart, c.gate);
+                       c.vpk, c.sfpart, (const void *)c.bpart, prec == RPY_PREC_F64 ? 1 : 0,
+                       c.ypart, c.gate);
     const int nt = (c.nk + 15) / 16 * 2 * BLOCK_RHS * 16;
     hipLaunchKernelGGL(k_block_sf_reduce, dim3((nt + 255) / 256), dim3(256), 0, s, c.nk, c.nchb,
                        c.kcoef, c.sfpart, c.tkm, c.gate);

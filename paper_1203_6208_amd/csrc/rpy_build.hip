@@ -92,8 +92,7 @@ __device__ inline uint16_t to_bf16(double d)
 // order (the operations of pair_block, so the block is bit-identical).  A
 // step in which some pair has three or more shifts on an axis falls back to
 // pair_block.  The block goes to the packed FP64 planes; LOWP also writes
-// packed FP32 (1) or BF16 (2) planes and, with rowmajor, the row-major tile
-// of the block product.
+// packed FP32 (1) or BF16 (2) planes.
 constexpr int IMG_SLOTS = 8;
 constexpr int IMG_QCAP = 128;
 
@@ -109,9 +108,7 @@ __global__ __launch_bounds__(256) void k_build_tiles(int N, const int2 *__restri
                                                      const double *__restrict__ rt, PairConst p,
                                                      double *__restrict__ d64,
                                                      float *__restrict__ p32,
-                                                     uint16_t *__restrict__ p16,
-                                                     float *__restrict__ d32,
-                                                     uint16_t *__restrict__ d16, int rowmajor)
+                                                     uint16_t *__restrict__ p16)
 {
     __shared__ double sI[TS], sJ[TS];
     __shared__ double q_r2[4][IMG_QCAP];
@@ -216,18 +213,6 @@ __global__ __launch_bounds__(256) void k_build_tiles(int N, const int2 *__restri
             if (LOWP == 1) p32[o6 + (size_t)e * TB] = (float)b[e];
             if (LOWP == 2) p16[o6 + (size_t)e * TB] = to_bf16(b[e]);
         }
-        if (LOWP && rowmajor) {
-            const double v[9] = {b[0], b[1], b[2], b[1], b[3], b[4], b[2], b[4], b[5]};
-            const size_t o = (size_t)t * TILE_ELEMS + (size_t)(3 * bi) * TS + 3 * bj;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    if (LOWP == 1) d32[o + (size_t)i * TS + j] = (float)v[3 * i + j];
-                    if (LOWP == 2) d16[o + (size_t)i * TS + j] = to_bf16(v[3 * i + j]);
-                }
-            }
-        }
     }
 }
 
@@ -240,13 +225,13 @@ void launch_build_tiles(const Ctx &c, hipStream_t s)
     const dim3 g(c.ntiles), b(256);
     if (c.lowp == RPY_PREC_F32)
         hipLaunchKernelGGL(k_build_tiles<1>, g, b, 0, s, c.N, c.tile_ij, c.rt, c.pc, c.d64,
-                           c.p32, c.p16, c.d32, c.d16, c.block ? 1 : 0);
+                           c.p32, c.p16);
     else if (c.lowp == RPY_PREC_BF16)
         hipLaunchKernelGGL(k_build_tiles<2>, g, b, 0, s, c.N, c.tile_ij, c.rt, c.pc, c.d64,
-                           c.p32, c.p16, c.d32, c.d16, c.block ? 1 : 0);
+                           c.p32, c.p16);
     else
         hipLaunchKernelGGL(k_build_tiles<0>, g, b, 0, s, c.N, c.tile_ij, c.rt, c.pc, c.d64,
-                           c.p32, c.p16, c.d32, c.d16, c.block ? 1 : 0);
+                           c.p32, c.p16);
 }
 
 // Dense row-major copy of the stored FP64 real-space matrix (test helper).

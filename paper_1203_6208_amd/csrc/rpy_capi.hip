@@ -208,9 +208,9 @@ extern "C" void rpy_destroy(rpy_ctx *x)
     if (!x) return;
     (void)hipDeviceSynchronize();
     Ctx &c = x->c;
-    void *bufs[] = {c.rt, c.rt_ev, c.eph, c.etab, c.kvec, c.kcoef, c.tile_ij, c.d64, c.d32,
-                    c.d16, c.p32, c.p16, c.part, c.xpk, c.ypart,
-                    c.vpk, c.part32, c.tkm,
+    void *bufs[] = {c.rt, c.rt_ev, c.eph, c.etab, c.kvec, c.kcoef, c.tile_ij, c.d64,
+                    c.p32, c.p16, c.part, c.xpk, c.ypart,
+                    c.vpk, c.bpart, c.tkm,
                     c.sfpart, c.tk, c.sfr, c.work, c.scal, c.red, c.flags, c.cell_start, c.lanc,
                     c.adapt, c.tpart,
                     c.vhist, c.wgrad, c.xy, c.gpart, c.gk, c.mur,
@@ -257,7 +257,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     c.grad = p->grad != 0;
     c.lma = p->lma != 0;
     c.rhs_cap = c.max_rhs > 4 ? c.max_rhs : 4;   // bd_step's product of [F, U+, U-, dW]
-    c.block = !c.lma && c.lowp != RPY_PREC_F64 && c.max_rhs >= BLOCK_MIN_RHS;
+    c.block = !c.lma && c.max_rhs >= BLOCK_MIN_RHS;
     if (c.block) c.rhs_cap = BLOCK_RHS;  // block kernels write all 16 columns
     {
         int dev = 0, lds = 0;
@@ -307,7 +307,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
     for (int I = 0; I < c.nbt; ++I)
         for (int J = I; J < c.nbt; ++J) tij.push_back(make_int2(I, J));
 
-    const size_t te = c.lma ? 0 : (size_t)c.ntiles * TILE_ELEMS;
+    const size_t te = c.lma ? 0 : (size_t)c.ntiles * TILE_ELEMS;   // row-major W tiles (grad)
     const size_t te6 = c.lma ? 0 : (size_t)c.ntiles * TILE6;
     const size_t lcells = c.lma ? (size_t)c.lma_nc * c.lma_nc * c.lma_nc : 0;
     const size_t nv = (size_t)c.n3;
@@ -324,13 +324,12 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
                    (rc = dalloc(&c.v_sorted, (size_t)c.rhs_cap * nv)))) ||
         (c.lowp == RPY_PREC_F32 && (rc = dalloc(&c.p32, te6))) ||
         (c.lowp == RPY_PREC_BF16 && (rc = dalloc(&c.p16, te6))) ||
-        (c.block && c.lowp == RPY_PREC_F32 && (rc = dalloc(&c.d32, te))) ||
-        (c.block && c.lowp == RPY_PREC_BF16 && (rc = dalloc(&c.d16, te))) ||
         (rc = dalloc(&c.part, (size_t)c.nslot * c.rhs_cap * c.n3pad)) ||
-        (c.block && ((rc = dalloc(reinterpret_cast<uint32_t **>(&c.xpk),
+        (c.block && ((rc = dalloc(reinterpret_cast<double **>(&c.xpk),
                                   (size_t)c.n3pad * BLOCK_RHS)) ||
                      (rc = dalloc(&c.vpk, (size_t)c.n3pad * BLOCK_RHS)) ||
-                     (rc = dalloc(&c.part32, (size_t)c.nbt * BLOCK_RHS * c.n3pad)) ||
+                     (rc = dalloc(reinterpret_cast<double **>(&c.bpart),
+                                  (size_t)c.nbt * BLOCK_RHS * c.n3pad)) ||
                      (rc = dalloc(&c.tkm, (size_t)c.nk4 * 6 * BLOCK_RHS)) ||
                      (rc = dalloc(&c.ypart, (size_t)BLOCK_RHS * c.n3)) ||
                      (rc = dalloc(&c.eph, (size_t)(c.N + 3) / 4 * ((c.nk + 15) / 16 * 16) * 4)))) ||
@@ -467,7 +466,7 @@ static void product(rpy_ctx *x, const double *v, int m, int prec, const EpiArgs 
         launch_kspace_epi(c, f, s);
         return;
     }
-    if (c.block && prec != RPY_PREC_F64 && m >= BLOCK_MIN_RHS) {
+    if (c.block && m >= BLOCK_MIN_RHS) {
         {
             ProfScope ps(x, RPY_PROF_SYMV, s);
             launch_block_tiles(c, prec, v, m, s);
@@ -478,7 +477,7 @@ static void product(rpy_ctx *x, const double *v, int m, int prec, const EpiArgs 
                 launch_block_phases(c, s);
                 x->eph_gen = x->wrap_gen;
             }
-            launch_block_sf(c, m, s);
+            launch_block_sf(c, m, prec, s);
         }
         ProfScope ps(x, RPY_PROF_EPI, s);
         launch_block_epi(c, f, s);

@@ -8,9 +8,8 @@
 //   (each pair term is a I + b rhat rhat), so a tile keeps 6 entries per bead
 //   pair, as planes: d64[t][i][c][j] (TILE6 doubles), i, j the beads of I and
 //   J within the tile, c = xx, xy, xz, yy, yz, zz.
-//   FP32 / BF16 tiles: packed the same way (p32, p16) for the products of up
-//   to 4 vectors, and, when the matrix-core block product is enabled, also
-//   TS x TS row-major (d32, d16, TILE_ELEMS), its operand layout.
+//   FP32 / BF16 tiles: packed the same way (p32, p16); every product, the
+//   matrix-core block product included, reads these packed planes.
 // A product y = D.x reads every stored tile once and produces both A_IJ x_J
 // (rows of I) and A_IJ^T x_I (rows of J); the partial results land in
 // part[K][j][row] so that row r of y is the fixed-order sum over K of
@@ -418,18 +417,17 @@ struct Ctx {
     KCoef *kcoef = nullptr;      // [nk]
     int2 *tile_ij = nullptr;     // [ntiles]
     double *d64 = nullptr;       // [ntiles][TILE6], packed symmetric blocks
-    float *d32 = nullptr;        // [ntiles][TILE_ELEMS] row-major, block products only
-    uint16_t *d16 = nullptr;
     float *p32 = nullptr;        // [ntiles][TILE6] packed planes, lowp FP32
     uint16_t *p16 = nullptr;     // [ntiles][TILE6] packed planes, lowp BF16
     double *part = nullptr;      // [nbt][rhs_cap][n3pad] tile-column partials
-    // block products (FP32 / BF16 tiles, up to 16 vectors on the matrix cores)
-    bool block = false;          // enabled: lowp tiles and max_rhs >= BLOCK_MIN_RHS
+    // block products (5 to 16 vectors on the matrix cores, any tile precision)
+    bool block = false;          // enabled: stored tiles and max_rhs >= BLOCK_MIN_RHS
+    mutable int block_wgs[3] = {0, 0, 0};   // persistent grid of the tile kernel per precision
     int nchb;                    // bead chunks of the block structure factors
     int nk4;                     // nk rounded up to a multiple of 4
-    void *xpk = nullptr;         // packed low-precision right-hand sides (n3pad x 16 x 4 bytes)
+    void *xpk = nullptr;         // packed right-hand sides of the tile product (3 npad x 16 x 8 bytes)
     double *vpk = nullptr;       // the same vectors in FP64, [n3pad][16]
-    float *part32 = nullptr;     // [nbt][n3pad/16][16 vectors][16 rows] FP32 tile partials
+    void *bpart = nullptr;       // [nbt][n3pad][16] tile partials (FP64 for FP64 tiles, else FP32)
     double *tkm = nullptr;       // [nk4][6][16] 2 m(k) P_k (C_k, S_k), rows >= nk zero
     double *ypart = nullptr;     // [16][3N] summed FP64 tile partials of a block product
     double2 *eph = nullptr;      // [ceil(N/4)][nk16][4] e^{i k.r_mu} of the wrapped positions
@@ -505,15 +503,14 @@ struct EpiArgs {
     double xs;             // EPI_ADJ: dv = xs * ya * vout
 };
 void launch_symv(const Ctx &c, int prec, const double *v, int j0, int mc, hipStream_t s);
-// FP32 / BF16 tiles, up to 16 vectors at once on the matrix cores; same
-// outputs (part, sfpart) as launch_symv over the vectors j0 .. j0 + mc - 1.
-// Block product D.V for m <= 16 vectors (c.block): the tile product on the
-// matrix cores (FP32 partials), the FP64 matrix-core structure factors and
-// their reduction to tkm, and the FP64 matrix-core back-projection fused with
-// the partial sum and the epilogue `f`.
+// Block product D.V for 5 <= m <= 16 vectors (c.block): the tile product on
+// the matrix cores from the packed planes of precision `prec` (FP64 or FP32
+// partials), the FP64 matrix-core structure factors and their reduction to
+// tkm (with the fixed-order sum of the partials), and the FP64 matrix-core
+// back-projection fused with the epilogue `f`.
 void launch_block_tiles(const Ctx &c, int prec, const double *v, int m, hipStream_t s);
 void launch_block_phases(const Ctx &c, hipStream_t s);   // eph from the current tables
-void launch_block_sf(const Ctx &c, int m, hipStream_t s);
+void launch_block_sf(const Ctx &c, int m, int prec, hipStream_t s);
 void launch_block_epi(const Ctx &c, const EpiArgs &f, hipStream_t s);
 constexpr int BLOCK_MIN_RHS = 5;   // products with at least this many vectors use it
 constexpr int BLOCK_RHS = 16;

@@ -1,7 +1,8 @@
-"""GPU parity of the matrix-core block product (5..16 vectors at once, FP32 or
-BF16 stored real-space tiles, FP32 accumulation inside a tile) through the
-C ABI against the CPU oracle (arXiv:1203.6208, eq. DFmodified; the product
-is the one every Chebyshev term of eq. cheb1-cheb3 takes).
+"""GPU parity of the matrix-core block product (5..16 vectors at once on the
+packed planes of the stored real-space tiles: FP64 tiles with FP64
+accumulation, FP32 or BF16 tiles with FP32 accumulation inside a tile)
+through the C ABI against the CPU oracle (arXiv:1203.6208, eq. DFmodified;
+the product is the one every Chebyshev term of eq. cheb1-cheb3 takes).
 
 Bounds are elementwise and worst-case, from the rounding of what is stored:
 only the real-space part (self term, M1 images, M*) is held in low precision,
@@ -88,7 +89,25 @@ def test_block_apply_n100(n100, orc, prec, m):
     _check_bound(out, valu, Drs, v, tol)
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("m", [5, 16])
+def test_block_apply_f64_n100(n100, orc, m):
+    """FP64 tiles on the FP64 matrix cores (16x16x4, FP64 accumulation): to
+    rel 1e-12 against the oracle, and against the vector-unit FP64 product
+    of the same vectors four at a time."""
+    _say(f"block apply n100 f64 m={m}")
+    w, pos, D, _ = n100
+    ctx = rpy.context_for(w, max_rhs=16)
+    ctx.build(_cuda(pos))
+    v = np.random.default_rng(200 + m).standard_normal((m, w.n, 3))
+    out = ctx.apply(_cuda(v)).cpu().numpy().reshape(m, -1)
+    ref = orc.matvec(D, v.reshape(m, -1))
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+    valu = np.concatenate([ctx.apply(_cuda(v[j:j + 4])).cpu().numpy()
+                           for j in range(0, m, 4)]).reshape(m, -1)
+    assert np.max(np.abs(out - valu)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 def test_block_apply_n1000(orc, prec):
     """N = 1000: 16 bead tiles per side, 136 stored tiles (120 off the
     diagonal), 16 vectors."""
@@ -102,7 +121,10 @@ def test_block_apply_n1000(orc, prec):
     v = np.random.default_rng(1000).standard_normal((16, w.n, 3))
     out = ctx.apply(_cuda(v), prec=prec).cpu().numpy().reshape(16, -1)
     ref = orc.matvec(D, v.reshape(16, -1))
-    _check_bound(out, ref, Drs, v, EPS[prec])
+    if prec == "f64":
+        assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+    else:
+        _check_bound(out, ref, Drs, v, EPS[prec])
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])

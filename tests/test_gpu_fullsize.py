@@ -116,6 +116,20 @@ def test_apply_n4000_multi_vector(n4000, orc, m):
     assert _rel(out, ref) < TOL
 
 
+def test_apply_n4000_block_f64(n4000, orc):
+    """Sixteen vectors at once on the FP64 matrix cores (the packed planes as
+    16x16x4 FP64 operands, FP64 partials per tile column): every output
+    element against the dense oracle."""
+    _say("apply n4000 block f64 m=16")
+    w, pos, D, _, _ = n4000
+    ctx = rpy.context_for(w, max_rhs=16)
+    ctx.build(_cuda(pos))
+    v = np.random.default_rng(4016).standard_normal((16, w.n, 3))
+    out = ctx.apply(_cuda(v)).cpu().numpy().reshape(16, -1)
+    ref = orc.matvec(D, v.reshape(16, -1))
+    assert _rel(out, ref) < TOL
+
+
 def _prop_bound(orc, Drs, eps, nch, lo, hi, dw):
     c = orc.cheb_coeffs(nch, lo, hi)
     eta = eps * np.max(np.abs(Drs).sum(axis=1))
