@@ -60,6 +60,9 @@ TRAFFIC_BATCH = {"src_sha256": "733cc46850c2f62d0ad3c3f0ec07554155937491b7b1ee49
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 TOL_EF = 1e-2     # E_f tolerance of the headline's adaptive order
+# E_f is measured against the FP64 quadratic form dW.D.dW; BF16 tiles leave a
+# floor of about 0.02 at N = 4000, so the BF16 adaptive form asks for 3e-2.
+TOL_BY_PREC = {"f64": TOL_EF, "f32": TOL_EF, "bf16": 3e-2}
 N_MAX = 160       # N_Ch the context keeps (the adaptive order's largest possible)
 SLACK = 12        # the adaptive search runs to eq. nint + SLACK at most
 LANCZOS_STEPS = 60
@@ -89,6 +92,10 @@ def parse():
                          "and on all threads (about a minute of host time)")
     ap.add_argument("--oracle-table-seconds", type=float, default=2.5,
                     help="host seconds per cell of the oracle table")
+    ap.add_argument("--theta-steps", type=int, default=3000,
+                    help="steps per state of the theta-statics grid")
+    ap.add_argument("--studies-only", action="store_true",
+                    help="run only the eigenvalue scaling and theta-statics studies")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -139,7 +146,7 @@ class Stepper:
 def time_form(w, prec, steps, warmup, torch, rpy, kind="adaptive"):
     """Steps/s of bd_step with Chebyshev products in `prec` in the step
     configuration `kind`; E_f of every timed step is kept on the device."""
-    st = Stepper(w, prec, kind, torch, rpy)
+    st = Stepper(w, prec, kind, torch, rpy, tol=TOL_BY_PREC[prec])
     for _ in range(warmup):
         st.step(seed=1)
     if kind != "paper_fixed":
@@ -337,6 +344,159 @@ def trajectory_n1000(torch, rpy, inputs, steps=1000, refresh=100):
             "Re2_mean": [float(re0.mean()), float(re2.mean())],
             "Rg2_mean": [float(rg0.mean()), float(rg2.mean())],
             "Re2_theta": 3.0 * (w.bpc - 1), "Rg2_theta": inputs.theta_rg2(w.bpc)}
+
+
+EIGEN_SIZES = (100, 200, 400, 1000, 2000, 4000)
+EIGEN_REPLICAS = 3
+EIGEN_LANCZOS = 1500
+THETA_BPC = (20, 40)
+THETA_CONC = (3e-4, 3e-3, 3e-2, 0.3, 1.0, 3.0)
+
+
+def ritz_extremes(alpha, beta):
+    """Extreme Ritz values of a k-step Lanczos run and their residual bounds
+    |beta_k s_k| (s_k the last component of the unit Ritz vector): the
+    tridiagonal has diagonal alpha[0..k-1] and off-diagonal beta[0..k-2];
+    beta[k-1] is the norm of the last residual."""
+    a = np.asarray(alpha, dtype=np.float64)
+    b = np.asarray(beta, dtype=np.float64)
+    k = len(a)
+    T = np.diag(a) + np.diag(b[:k - 1], 1) + np.diag(b[:k - 1], -1)
+    ev, vec = np.linalg.eigh(T)   # k <= 512: the dense solver is cheap and robust
+    return (float(ev[0]), float(ev[-1]), abs(b[k - 1] * vec[-1, 0]),
+            abs(b[k - 1] * vec[-1, -1]))
+
+
+def power_fit(ns, ys):
+    """Least-squares fit y = A N^p on log-log axes: (p, A)."""
+    p, la = np.polyfit(np.log(np.asarray(ns, dtype=np.float64)),
+                       np.log(np.asarray(ys, dtype=np.float64)), 1)
+    return float(p), float(math.exp(la))
+
+
+def eigen_scaling(torch, rpy, inputs, sizes=EIGEN_SIZES, replicas=EIGEN_REPLICAS,
+                  n_iter=EIGEN_LANCZOS):
+    """How the extreme eigenvalues of D grow with N at the state of the
+    paper's eigenvalue study (section "Decomposition of the diffusion
+    tensor": N_b = 10, c = 4.44 c*, a = 0.5): for each N and start
+    conformation, lambda_max and lambda_min of D from an FP64 Lanczos run
+    (min(`n_iter`, 2N) steps in the 3N-dimensional space, extreme Ritz values
+    with their residual bounds), and
+    Fixman's estimates lambda^F = U.D.U / 3N with U = U+ and U- (eq.
+    lmax-lmin-dilute, from the dilute rule's interval: d_max = 2 lambda^F_max,
+    d_min = lambda^F_min / 2).  Fits lambda_max / lambda^F_max = A N^p
+    (eq. fmax: 0.35 N^0.6) and lambda_max / lambda_min = C N^q (eq. fmin:
+    C = 8, q = 0.6), and the prefactors with the exponent held at 0.6."""
+    states = []
+    for n in sizes:
+        for r in range(replicas):
+            w = inputs.eigen_state(n, r)
+            ctx = rpy.context_for(w, max_rhs=2)
+            ctx.build(torch.from_numpy(w.positions()).cuda())
+            a, b = ctx.bounds(0.0, rule=rpy.BOUNDS_DILUTE)
+            _, _, al, be = ctx.lanczos_bounds(min(n_iter, 2 * n), seed=7 + r, margin=0.0)
+            del ctx
+            tmin, tmax, rmin, rmax = ritz_extremes(al, be)
+            states.append({"N": n, "replica": r, "L": w.L, "lambda_min": tmin,
+                           "lambda_max": tmax, "residual_min": rmin, "residual_max": rmax,
+                           "lambda_max_fixman": 0.5 * b, "lambda_min_fixman": 2.0 * a,
+                           "max_over_fixman": tmax / (0.5 * b), "max_over_min": tmax / tmin})
+    ns = [s["N"] for s in states]
+    p1, a1 = power_fit(ns, [s["max_over_fixman"] for s in states])
+    p2, c2 = power_fit(ns, [s["max_over_min"] for s in states])
+    pf, lf = power_fit(ns, [s["lambda_max_fixman"] for s in states])
+    pm, lm = power_fit(ns, [s["lambda_min"] for s in states])
+    at06 = lambda key: float(np.mean([s[key] / s["N"] ** 0.6 for s in states]))
+    return {"state": "N_b=10, c=4.44 c*, a=0.5, theta conformations (random walks), "
+                     "alpha L=6, alpha r_c=3.5",
+            "lanczos_steps": n_iter, "replicas": replicas, "states": states,
+            "fit": {"max_over_fixman": {"exponent": p1, "prefactor": a1,
+                                        "prefactor_at_0.6": at06("max_over_fixman")},
+                    "max_over_min": {"exponent": p2, "prefactor": c2,
+                                     "prefactor_at_0.6": at06("max_over_min")},
+                    "lambda_max_fixman": {"exponent": pf, "prefactor": lf},
+                    "lambda_min": {"exponent": pm, "prefactor": lm}},
+            "paper": {"max_over_fixman": "0.35 N^0.6 (eq. fmax)",
+                      "max_over_min": "C N^0.6, C = 8 at this state (eq. fmin)"}}
+
+
+def theta_statics(torch, rpy, inputs, steps=3000, replicas=2, every=10, refresh=250,
+                  tol=TOL_EF, bpcs=THETA_BPC, concs=THETA_CONC):
+    """Theta-solvent statics on the paper's grid (section "Testing and
+    verification", theta solvents): N_c = 20 chains of N_b = 20 and 40
+    beads, a = 0.5, dt = 0.01, c/c* from 3e-4 to 3 by the box length, FP64
+    with hydrodynamic interaction, N_Ch by eq. nint raised until E_f < tol on
+    a Lanczos interval (80 steps, margin 0.2) refreshed every `refresh`
+    steps; `replicas` independent boxes per state.  The start is an
+    equilibrium sample, so every window of the run samples equilibrium;
+    <R_e^2> and <R_g^2> are averaged over time (every `every` steps) and
+    chains, with the standard error from the spread of the per-chain
+    averages over all replicas, against eq. Re2 and Rg2.  The runs are
+    shorter than the longest relaxation time of a 40-bead chain, so the
+    averages stay close to those of the start conformations (`*_start`,
+    same chains at t = 0), which carry the sampling error of the start: the
+    per-chain R_g^2 of a 40-bead random walk has a relative spread of about
+    0.5 and a long upper tail, so a low sample mean comes with a small
+    sample spread (for 20 start chains drawn from the generator, the mean
+    lies more than 2 standard errors below the exact value in 6% of draws,
+    where a normal sample would give 2.3%)."""
+    out = []
+    for bpc in bpcs:
+        for cc in concs:
+            series = {"Re2": [], "Rg2": []}
+            start = {"Re2": [], "Rg2": []}
+            res = {"N_b": bpc, "c_over_cstar": cc, "steps": steps, "replicas": replicas,
+                   "seconds": 0.0, "n_cheb_mean": 0.0, "n_cheb_max": 0, "missed_tol": 0,
+                   "E_f_max": 0.0, "status": []}
+            for rep in range(replicas):
+                w = inputs.theta_state(bpc, cc, replica=rep)
+                res["N"], res["L"] = w.n, w.L
+                ctx = rpy.context_for(w, cheb_keep=N_MAX)
+                pos = torch.from_numpy(w.positions()).cuda()
+                bp = rpy.make_bd_params(dt=w.dt, n_cheb=0, bounds_rule=rpy.BOUNDS_EXPLICIT,
+                                        tol=tol, n_max=N_MAX)
+                ns = steps // every
+                re2 = torch.empty((ns, w.nchains), dtype=torch.float64, device="cuda")
+                rg2 = torch.empty_like(re2)
+                efs = torch.empty(steps, dtype=torch.float64, device="cuda")
+                re0, rg0 = ctx.observables(pos)
+                start["Re2"].append(re0.cpu().numpy())
+                start["Rg2"].append(rg0.cpu().numpy())
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for i in range(steps):
+                    if i % refresh == 0:
+                        ctx.build(pos)
+                        lo, hi, _, _ = ctx.lanczos_bounds(80, seed=300 + i, margin=0.2)
+                        bp.d_min, bp.d_max = lo, hi
+                        bp.n_max = min(N_MAX, math.floor(math.sqrt(hi / lo) + 0.5) + 1 + SLACK)
+                    ctx.step(pos, bp, seed=17 + rep, step=i, e_f=efs[i:i + 1])
+                    if (i + 1) % every == 0:
+                        r = (i + 1) // every - 1
+                        ctx.observables(pos, re2[r], rg2[r])
+                torch.cuda.synchronize()
+                res["seconds"] += time.perf_counter() - t0
+                calls, mean_n, max_n, missed = ctx.order_stats()
+                res["n_cheb_mean"] += mean_n / replicas
+                res["n_cheb_max"] = max(res["n_cheb_max"], max_n)
+                res["missed_tol"] += missed
+                res["E_f_max"] = max(res["E_f_max"], float(efs.max()))
+                res["status"].append(ctx.status())
+                series["Re2"].append(re2.mean(dim=0).cpu().numpy())
+                series["Rg2"].append(rg2.mean(dim=0).cpu().numpy())
+                del ctx
+            res["steps_per_s"] = steps * replicas / res["seconds"]
+            for nm, exact in (("Re2", 3.0 * (bpc - 1)), ("Rg2", inputs.theta_rg2(bpc))):
+                per_chain = np.concatenate(series[nm])
+                mean = float(per_chain.mean())
+                se = float(per_chain.std(ddof=1) / math.sqrt(len(per_chain)))
+                res[nm] = mean
+                res[nm + "_se"] = se
+                res[nm + "_exact"] = exact
+                res[nm + "_dev_in_se"] = (mean - exact) / se
+                res[nm + "_start"] = float(np.concatenate(start[nm]).mean())
+            out.append(res)
+    return {"states": out, "tol": tol, "every": every, "lanczos_refresh_every": refresh}
 
 
 def batch_study(torch, rpy, inputs, steps=5, per_box=True):
@@ -748,6 +908,11 @@ def main():
     if args.diff_only:
         print(json.dumps({"differentiation": diff_study(torch, rpy, inputs)}))
         return
+    if args.studies_only:
+        print(json.dumps({"eigen_scaling": eigen_scaling(torch, rpy, inputs),
+                          "theta_statics": theta_statics(torch, rpy, inputs,
+                                                         steps=args.theta_steps)}))
+        return
     if args.batch_only:
         print(json.dumps({"batch": batch_study(torch, rpy, inputs, steps=args.steps,
                                                per_box=False)}))
@@ -799,6 +964,12 @@ def main():
         print(f"# eigen {eigen}", file=sys.stderr, flush=True)
     if studies:
         torch.cuda.empty_cache()
+        eigen["scaling_with_N"] = eigen_scaling(torch, rpy, inputs)
+        print(f"# eigen scaling {json.dumps(eigen['scaling_with_N']['fit'])}", file=sys.stderr,
+              flush=True)
+        forms["theta_statics"] = theta_statics(torch, rpy, inputs, steps=args.theta_steps)
+        print(f"# theta statics {json.dumps(forms['theta_statics'])}", file=sys.stderr,
+              flush=True)
         traj = trajectory_n1000(torch, rpy, inputs)
         print(f"# trajectory n1000 {traj}", file=sys.stderr, flush=True)
         forms["trajectory_n1000"] = traj

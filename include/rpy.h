@@ -191,7 +191,7 @@ int chebyshev_sqrt_apply(rpy_ctx *c, const double *dw, double *out, int m,
  *   d_max = (theta_max + res_max)(1 + margin)
  * (d_min = theta_min/2 if that is not positive).  d_min, d_max: HOST outputs;
  * alpha, beta: optional HOST [n_iter] outputs.  Synchronises the stream.
- * Errors: RPY_EINVAL for n_iter outside 2..512, margin < 0 or null outputs. */
+ * Errors: RPY_EINVAL for n_iter outside 2..2048, margin < 0 or null outputs. */
 int rpy_lanczos_bounds(rpy_ctx *c, int n_iter, uint64_t seed, const double *start,
                        double margin, double *d_min, double *d_max, double *alpha,
                        double *beta, void *stream);
@@ -227,8 +227,9 @@ int chebyshev_sqrt_adaptive(rpy_ctx *c, const double *dw, double *out, int m,
  * N_Ch = n_max (needs 2 <= n_max <= cheb_keep) -- with no host
  * synchronisation; a missed tolerance is counted and reported as RPY_ETOL by
  * rpy_status, and rpy_order_stats reports the orders used.
- * prec selects the arithmetic of the Chebyshev products; the drift and the
- * bounds always use FP64.  The forces and the device noise run on a second
+ * prec selects the arithmetic of the Chebyshev products from V_1 on; the
+ * drift, the bounds and the first product D.dW (taken in the same FP64 pass
+ * over D as D.F, and reused by E_f) always use FP64.  The forces and the device noise run on a second
  * stream owned by the context, forked from `stream` after the wrap and
  * joined back before the drift product (event record / wait, no host
  * synchronisation), so that they overlap the tile build; everything the call

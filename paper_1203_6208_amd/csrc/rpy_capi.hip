@@ -1051,12 +1051,11 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
     const size_t nv = (size_t)c.n3;
     launch_wrap_tables(c, pos, s);
     ++x->wrap_gen;
-    // The FP64 step folds the first Chebyshev product into the drift
-    // product: one pass over D for [F, U+, (U-,) dW], then the coefficients,
-    // then V_1 from D.dW.  Lower-precision Chebyshev products keep their own
-    // first product.
-    const bool fold = bp->prec == RPY_PREC_F64;
-    double *w = fold ? x->F + 2 * nv : x->dW;
+    // The first Chebyshev product rides with the drift product: one FP64
+    // pass over D for [F, U+, (U-,) dW], then the coefficients, then V_1
+    // from D.dW; the products from V_1 on take bp->prec.  D.dW in FP64 also
+    // makes E_f measure the square root against the FP64 quadratic form.
+    double *w = x->F + 2 * nv;
     // forces and noise on the side stream, beside the build
     HIP_TRY(hipEventRecord(x->fork, s));
     HIP_TRY(hipStreamWaitEvent(x->side, x->fork, 0));
@@ -1064,8 +1063,7 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
         ProfScope ps(x, RPY_PROF_OTHER, x->side);
         forces(x, pos, c.rt, bp->ev_zstar, bp->ev_dstar, bp->ev_rcut, x->F, x->side);
         if (!dw) launch_noise(w, (int64_t)nv, seed, step, bp->dt, x->side);
-        else if (fold) launch_copy(w, dw, nv, x->side);
-        else w = const_cast<double *>(dw);
+        else launch_copy(w, dw, nv, x->side);
     }
     HIP_TRY(hipEventRecord(x->join, x->side));
     {
@@ -1074,14 +1072,14 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
     }
     HIP_TRY(hipStreamWaitEvent(s, x->join, 0));
     // the drift product: F, then U+ (paper and dilute rules) and U- (dilute),
-    // then dW when folded; D.F lands in Y, D.U+ in Y + nv, D.dW last
+    // then dW; D.F lands in Y, D.U+ in Y + nv, D.dW last
     const int nb = rule == RPY_BOUNDS_PAPER ? 1 : rule == RPY_BOUNDS_DILUTE ? 2 : 0;
     EpiArgs f{};
     f.mode = EPI_APPLY;
     f.vout = x->Y;
-    f.m = 1 + nb + (fold ? 1 : 0);
-    if (nb == 1 || f.m == 1) {
-        product(x, x->F, f.m, RPY_PREC_F64, f, s);   // [F], or [F, U+, dW] contiguous
+    f.m = 2 + nb;
+    if (nb == 1) {
+        product(x, x->F, f.m, RPY_PREC_F64, f, s);   // [F, U+, dW] contiguous
     } else {
         double *g = x->Bv[0];   // free until the recurrence's second product
         launch_copy(g, x->F, nv, s);
@@ -1089,7 +1087,7 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
             launch_copy(g + nv, x->F + nv, nv, s);
             launch_copy(g + 2 * nv, x->Um, nv, s);
         }
-        if (fold) launch_copy(g + (1 + nb) * nv, w, nv, s);
+        launch_copy(g + (1 + nb) * nv, w, nv, s);
         product(x, g, f.m, RPY_PREC_F64, f, s);
     }
     const double *du = x->Y + nv;
@@ -1112,20 +1110,12 @@ extern "C" int bd_step(rpy_ctx *x, double *pos, const bd_params *bp, const doubl
             const int k = adapt_first(0, 1.0, bp->bounds_C * pow((double)c.N, 0.6), nmax) - 1;
             host_first = k < 2 ? 2 : k;
         }
-        if (fold) {
-            const double *ddw = x->Y + (1 + nb) * nv;   // D.dW
-            launch_cheb_first(c, ddw, w, c.vhist + ps, x->acc, x->ddw, s);
-        }
-        cheb_adapt_run(x, 1, bp->prec, fold ? 2 : 1, host_first, nmax, bp->tol, x->dS,
+        launch_cheb_first(c, x->Y + (1 + nb) * nv, w, c.vhist + ps, x->acc, x->ddw, s);
+        cheb_adapt_run(x, 1, bp->prec, 2, host_first, nmax, bp->tol, x->dS,
                        e_f ? e_f : c.red, s);
     } else {
-        if (fold) {
-            const double *ddw = x->Y + (1 + nb) * nv;   // D.dW
-            launch_cheb_first(c, ddw, w, x->Bv[1], x->dS, x->ddw, s);
-            cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s, 2);
-        } else {
-            cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s);
-        }
+        launch_cheb_first(c, x->Y + (1 + nb) * nv, w, x->Bv[1], x->dS, x->ddw, s);
+        cheb_run(x, w, x->dS, 1, bp->n_cheb, bp->prec, s, 2);
         if (e_f) launch_sqrt_error(c, 1, w, x->ddw, x->dS, e_f, s);
     }
     if (drift) launch_copy(drift, x->Y, nv, s);

@@ -45,7 +45,7 @@ constexpr int NSER = 20;        // terms of the small-r series of S(r)
 constexpr double XSER = 0.75;   // use the series for alpha*r below this
 constexpr int MAX_RHS = 16;
 constexpr int MAX_NCHEB = 512;
-constexpr int MAX_LANCZOS = 512;
+constexpr int MAX_LANCZOS = 2048;
 constexpr int KSLICE = 16;      // wave-vector / tile-column slices of the back-projection
 constexpr int SF_BEADS = 64;    // beads per structure-factor partial
 

@@ -132,6 +132,28 @@ def workload(name: str) -> Workload:
     raise KeyError(name)
 
 
+def eigen_state(n: int, replica: int = 0) -> Workload:
+    """A state of the eigenvalue study (section "Decomposition of the
+    diffusion tensor", eq. fmax and fmin): chains of N_b = 10 beads at
+    c = 4.44 c*, bead radius a = 0.5, N = 10 N_c beads, no excluded volume,
+    the start conformation of `replica`."""
+    if n % 10:
+        raise ValueError("N must be a multiple of N_b = 10")
+    return Workload(f"eigen{n}_{replica}", n // 10, 10, 4.44, hstar=0.5 / math.sqrt(math.pi),
+                    nch=0, seed=POSITION_SEED_BASE + 100 + 97 * n + replica)
+
+
+def theta_state(bpc: int, c_over_cstar: float, nchains: int = 20, replica: int = 0) -> Workload:
+    """A state of the theta-statics grid (section "Testing and verification",
+    theta solvents): N_c = 20 chains of N_b beads, a = 0.5, dt = 0.01, no
+    excluded volume, c/c* set by the box length; `replica` picks an
+    independent start."""
+    return Workload(f"theta{bpc}_c{c_over_cstar:g}_{replica}", nchains, bpc, c_over_cstar,
+                    hstar=0.5 / math.sqrt(math.pi), nch=0, dt=0.01,
+                    seed=POSITION_SEED_BASE + 200 + 1009 * bpc + int(round(1e4 * c_over_cstar))
+                    + 100003 * replica)
+
+
 def batch_boxes(count: int = 256, seed: int = POSITION_SEED_BASE + 3, n_lo: int = 100,
                 n_hi: int = 2000):
     """Ragged ensemble: N_b ~ U{10..50}, N in whole chains with n_lo <= N <= n_hi

@@ -11,14 +11,47 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def test_tile_bytes_packed_and_half():
+def test_tile_bytes_packed():
     n = 4000
     # packed: 6 distinct entries per symmetric 3 x 3 block, N(N+1)/2 pairs
     assert bench.tile_bytes(n, "f64") == 6 * (n * (n + 1) // 2) * 8 == 384_096_000
     assert bench.tile_bytes(n, "f32") == 384_096_000 // 2
     assert bench.tile_bytes(n, "bf16") == 384_096_000 // 4
-    # symmetric half of the 3N x 3N matrix
-    assert bench.tile_bytes(n, "f64", packed=False) == 12000 * 12001 // 2 * 8
+
+
+def test_ritz_extremes_of_an_exact_lanczos_run():
+    """Lanczos on a diagonal matrix with a known spectrum, run in numpy with
+    full reorthogonalisation: the extreme Ritz values converge to the extreme
+    eigenvalues and their residual bounds bracket the error."""
+    np = pytest.importorskip("numpy")
+    rng = np.random.default_rng(3)
+    lam = np.sort(np.concatenate([[0.05, 41.0], rng.uniform(0.3, 30.0, 398)]))
+    q = rng.standard_normal(lam.size)
+    q /= np.linalg.norm(q)
+    Q = [q]
+    alpha, beta = [], []
+    qprev, bprev = np.zeros_like(q), 0.0
+    for _ in range(120):
+        w = lam * Q[-1] - bprev * qprev
+        a = float(Q[-1] @ w)
+        w -= a * Q[-1]
+        for v in Q:
+            w -= (v @ w) * v
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        beta.append(b)
+        qprev, bprev = Q[-1], b
+        Q.append(w / b)
+    tmin, tmax, rmin, rmax = bench.ritz_extremes(alpha, beta)
+    assert abs(tmax - 41.0) <= max(rmax, 1e-9 * 41.0)
+    assert abs(tmin - 0.05) <= max(rmin, 1e-9)
+    assert abs(tmax - 41.0) < 1e-6 and abs(tmin - 0.05) < 1e-3
+
+
+def test_power_fit_recovers_a_power_law():
+    ns = [100, 200, 400, 1000, 2000, 4000]
+    p, a = bench.power_fit(ns, [8.0 * n ** 0.6 for n in ns])
+    assert abs(p - 0.6) < 1e-12 and abs(a - 8.0) < 1e-9
 
 
 def test_traffic_is_null_for_other_sources():

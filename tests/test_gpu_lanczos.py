@@ -62,6 +62,35 @@ def test_lanczos_matches_oracle(orc, wname, k):
         assert lo <= lam[0] and hi >= lam[-1]
 
 
+@pytest.mark.parametrize("n", [100, 400])
+def test_eigen_study_state(orc, n):
+    """A state of the eigenvalue study (N_b = 10, c = 4.44 c*, a = 0.5;
+    section "Decomposition of the diffusion tensor", eq. fmax and fmin) as
+    the benchmark measures it: Fixman's estimates of eq. lmax-lmin-dilute,
+    taken from the dilute rule's interval, equal the oracle's to 1e-12, and
+    the extreme Ritz values of the library's Lanczos coefficients (min(300,
+    2N) steps from the device start) equal the oracle's dense extreme
+    eigenvalues within their residual bounds and to 1e-6 relative."""
+    import bench
+    _say(f"eigen study state N={n}")
+    w = inputs.eigen_state(n, 0)
+    pos = w.positions()
+    D = orc.diffusion_matrix(pos, w.L, w.a, w.alpha, w.rc, w.n2max)
+    lam = np.linalg.eigvalsh(D)
+    ctx = rpy.context_for(w, max_rhs=2)
+    ctx.build(_cuda(pos))
+    a, b = ctx.bounds(0.0, rule=rpy.BOUNDS_DILUTE)
+    ra, rb = orc.bounds_dilute(D, w.n)
+    assert abs(a - ra) <= 1e-12 * ra and abs(b - rb) <= 1e-12 * rb
+    _, _, al, be = ctx.lanczos_bounds(min(300, 2 * n), seed=7, margin=0.0)
+    tmin, tmax, rmin, rmax = bench.ritz_extremes(al, be)
+    _say(f"  lambda [{lam[0]:.6g}, {lam[-1]:.6g}] ritz [{tmin:.6g}, {tmax:.6g}] "
+         f"residuals {rmin:.2e} {rmax:.2e}")
+    assert abs(tmin - lam[0]) <= max(rmin, 1e-12 * lam[-1])
+    assert abs(tmax - lam[-1]) <= max(rmax, 1e-12 * lam[-1])
+    assert abs(tmin - lam[0]) <= 1e-6 * lam[0] and abs(tmax - lam[-1]) <= 1e-6 * lam[-1]
+
+
 def test_lanczos_device_start_brackets(n100):
     """Default start (device Philox noise): the bounds contain the spectrum."""
     w, pos, D, lam = n100
