@@ -42,12 +42,12 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "c4c06c4aed797dc739456cbe5678da63a92a4f9829682d79982186d1b4eec8e7",
+TRAFFIC = {"src_sha256": "162c3efd77ecbc2c8ebded97ec4518a982da8898347d662c98dc919d5faa9d38",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
            "bytes_per_launch": 411336252}
 # The matrix-core tile kernel (k_block_tiles) of a 16-vector product: tile and
 # vector reads plus the per-tile FP64/FP32 partial sums it writes.
-TRAFFIC_BLOCK = {"src_sha256": "5ebf909f27e9dcbc3ef4b553eb98fb58c3745f8038d56eb74c78f584c7e10900",
+TRAFFIC_BLOCK = {"src_sha256": "8d588113f61ed8f5d5b1b75bb6262794ff41391bca81ced309d972c548b089b6",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
                  "bytes_per_launch": {"f64": 420293966 + 97542144,
                                       "f32": 215921135 + 48771788,
