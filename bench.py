@@ -67,14 +67,15 @@ N_MAX = 160       # N_Ch the context keeps (the adaptive order's largest possibl
 SLACK = 12        # the adaptive search runs to eq. nint + SLACK at most
 LANCZOS_STEPS = 60
 LANCZOS_MARGIN = 0.05
-REFRESH = 50      # steps between Lanczos refreshes of the interval
+REFRESH = 250     # steps between Lanczos refreshes of the interval (0.25 time units at dt = 1e-3)
 ORACLE_REF = os.path.join(ROOT, "tests", "golden", "n4000_oracle.npz")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=REFRESH,
+                    help="timed steps (default: one Lanczos refresh period, the refresh included)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -503,7 +504,9 @@ def batch_study(torch, rpy, inputs, steps=5, per_box=True):
     """Batching form: the 256-box ragged ensemble (N 125..1989 in whole chains
     of 10..50 beads, c/c* 0.5..3, no excluded volume), FP64 core with FP32
     Chebyshev products (N_Ch = 30, paper rule), every step one HIP graph
-    replay.  Tile size from the autotuner, compared with both fixed sizes;
+    replay.  Tile size, structure-factor placement and tile-load policy from
+    the autotuner (its whole table is reported), compared with both fixed
+    tile sizes in the default variant;
     the same ensemble with FP64 products, and box by box through the
     single-box library (FP64, one bd_step per box) as the plain baseline.
     Throughput is aggregate box-steps/s (boxes x steps / s)."""
@@ -519,12 +522,16 @@ def batch_study(torch, rpy, inputs, steps=5, per_box=True):
     t0 = time.perf_counter()
     best, times = autotune.tune_batch(ws, bp32, lowp="f32", steps=3, positions=pos_np)
     t_tune = time.perf_counter() - t0
+    table = [dict(c.as_dict(), ms_per_step=1e3 * t, box_steps_per_s=nbox / t)
+             for c, t in sorted(times.items(), key=lambda kv: kv[1])]
     out = {"boxes": nbox, "beads": beads, "n_cheb": 30,
-           "autotune": {"tile_beads": best, "seconds_tuning": t_tune,
-                        "candidates_ms_per_step": {str(k): 1e3 * v for k, v in times.items()}}}
+           "autotune": {"best": best.as_dict(), "seconds_tuning": t_tune,
+                        "search_space": "tile_beads {32, 64} x sf_place {spread, front} x "
+                                        "tile_loads {stream, cached}, 3 graph replays each",
+                        "table": table}}
 
-    def graph_rate(lowp, bp, tb):
-        B = rpy.Batch(ws, lowp=lowp, tile_beads=tb)
+    def graph_rate(lowp, bp, config):
+        B = autotune.make_batch(ws, config, lowp=lowp)
         pos = B.pack(pos_np)
         B.run(pos, bp, seed=1, step0=0, n_steps=1)
         torch.cuda.synchronize()
@@ -537,7 +544,8 @@ def batch_study(torch, rpy, inputs, steps=5, per_box=True):
 
     B, pos, sec, st = graph_rate("f32", bp32, best)
     out["f32_autotuned"] = {"box_steps_per_s": nbox / sec, "ensemble_steps_per_s": 1.0 / sec,
-                            "ms_per_step": 1e3 * sec, "status": st, "tile_beads": best}
+                            "ms_per_step": 1e3 * sec, "status": st, **best.as_dict(),
+                            "graph_nodes_per_step": B.graph_nodes()}
     # one FP32 product (tile kernel + reduction + back-projection) timed with events
     v = B.pack([np.ones((w.n, 3)) for w in ws], m=1)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -553,9 +561,9 @@ def batch_study(torch, rpy, inputs, steps=5, per_box=True):
                           "GBs": alg / (us * 1e-6) / 1e9,
                           "hbm_frac": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
                           "tile_kernel_traffic_bytes": (measured_traffic(TRAFFIC_BATCH)
-                                                        if best == 64 else None)}
+                                                        if best == autotune.Config() else None)}
     # accuracy of the FP32 form on one step against FP64 products (same state)
-    B64 = rpy.Batch(ws, lowp="f64", tile_beads=best)
+    B64 = autotune.make_batch(ws, best, lowp="f64")
     p64 = B64.pack(pos_np)
     p32 = B.pack(pos_np)
     d64, n64, _ = B64.step(p64, bp64, seed=5, step=0, want=True)
@@ -567,13 +575,14 @@ def batch_study(torch, rpy, inputs, steps=5, per_box=True):
               for a, b in zip(B.unpack(d32), B64.unpack(d64)))
     out["f32_vs_f64_max_box_rel_err"] = {"dS": e_n, "drift": e_d}
     del B, B64, pos, p64, p32
-    for tb in (32, 64):
-        if tb == best:
+    for tb in (32, 64):   # fixed tiles with the default variant
+        fixed = autotune.Config(tile_beads=tb)
+        if fixed == best:
+            out[f"f32_fixed_tile{tb}"] = dict(out["f32_autotuned"])
             continue
-        Bx, px, sx, stx = graph_rate("f32", bp32, tb)
+        Bx, px, sx, stx = graph_rate("f32", bp32, fixed)
         out[f"f32_fixed_tile{tb}"] = {"box_steps_per_s": nbox / sx, "ms_per_step": 1e3 * sx}
         del Bx, px
-    out[f"f32_fixed_tile{best}"] = dict(out["f32_autotuned"])
     Bd, pd, sd, std = graph_rate("f64", bp64, best)
     out["f64_batched"] = {"box_steps_per_s": nbox / sd, "ms_per_step": 1e3 * sd, "status": std}
     del Bd, pd

@@ -468,6 +468,25 @@ int rpy_batch_step(rpy_batch *b, double *pos, const bd_params *bp,
 int rpy_batch_run(rpy_batch *b, double *pos, const bd_params *bp,
                   uint64_t seed, uint64_t step0, int n_steps, void *stream);
 
+/* Product variant of the batched tile kernel, for the autotuner (the values
+ * are identical whichever variant runs; only the time differs):
+ *   sf_place   RPY_SF_SPREAD (default): the structure-factor workgroups are
+ *              spread evenly through the launch, so that their FP64
+ *              arithmetic overlaps the tile stream; RPY_SF_FRONT: they are
+ *              the first workgroups of the launch;
+ *   tile_loads RPY_LOADS_STREAM (default): non-temporal tile loads;
+ *              RPY_LOADS_CACHED: ordinary loads that allocate in the caches.
+ * A change drops the captured step graph (the next rpy_batch_run captures
+ * again) and synchronises the device first.  Errors: RPY_EINVAL for other
+ * values. */
+enum { RPY_SF_SPREAD = 0, RPY_SF_FRONT = 1 };
+enum { RPY_LOADS_STREAM = 0, RPY_LOADS_CACHED = 1 };
+int rpy_batch_set_variant(rpy_batch *b, int sf_place, int tile_loads);
+
+/* Nodes (kernel launches) of the captured step graph of rpy_batch_run, or -1
+ * before the first capture. */
+int64_t rpy_batch_graph_nodes(const rpy_batch *b);
+
 /* Per-chain R_e^2 and R_g^2 of all boxes, chains in box order: device
  * outputs [sum of n_chains]. */
 int rpy_batch_observables(rpy_batch *b, const double *pos, double *re2,

@@ -197,14 +197,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f2v __attribute__((ext_vector_type(2)));
+// A tile load: non-temporal (streamed past the caches) or, with CACHED, an
+// ordinary load that allocates in the L2 and the Infinity Cache.
+template <bool CACHED, typename V> __device__ inline V tload(const V *p)
+{
+    if constexpr (CACHED) return *p;
+    else return __builtin_nontemporal_load(p);
+}
 template <typename T, int TBB> struct BLd;
 template <> struct BLd<double, 64> {
     static constexpr int NE = 4;
     __device__ static int col(int q, int e) { return 32 * (e >> 1) + 2 * q + (e & 1); }
-    __device__ static void load(const double *row, int q, double a[NE])
+    template <bool CACHED> __device__ static void load(const double *row, int q, double a[NE])
     {
-        const d2v u = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 2 * q));
-        const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 32 + 2 * q));
+        const d2v u = tload<CACHED>(reinterpret_cast<const d2v *>(row + 2 * q));
+        const d2v v = tload<CACHED>(reinterpret_cast<const d2v *>(row + 32 + 2 * q));
         a[0] = u.x;
         a[1] = u.y;
         a[2] = v.x;
@@ -214,9 +221,9 @@ template <> struct BLd<double, 64> {
 template <> struct BLd<double, 32> {
     static constexpr int NE = 2;
     __device__ static int col(int q, int e) { return 2 * q + e; }
-    __device__ static void load(const double *row, int q, double a[NE])
+    template <bool CACHED> __device__ static void load(const double *row, int q, double a[NE])
     {
-        const d2v u = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(row + 2 * q));
+        const d2v u = tload<CACHED>(reinterpret_cast<const d2v *>(row + 2 * q));
         a[0] = u.x;
         a[1] = u.y;
     }
@@ -224,9 +231,9 @@ template <> struct BLd<double, 32> {
 template <> struct BLd<float, 64> {
     static constexpr int NE = 4;
     __device__ static int col(int q, int e) { return 4 * q + e; }
-    __device__ static void load(const float *row, int q, double a[NE])
+    template <bool CACHED> __device__ static void load(const float *row, int q, double a[NE])
     {
-        const f4v u = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(row + 4 * q));
+        const f4v u = tload<CACHED>(reinterpret_cast<const f4v *>(row + 4 * q));
         a[0] = u.x;
         a[1] = u.y;
         a[2] = u.z;
@@ -236,9 +243,9 @@ template <> struct BLd<float, 64> {
 template <> struct BLd<float, 32> {
     static constexpr int NE = 2;
     __device__ static int col(int q, int e) { return 2 * q + e; }
-    __device__ static void load(const float *row, int q, double a[NE])
+    template <bool CACHED> __device__ static void load(const float *row, int q, double a[NE])
     {
-        const f2v u = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(row + 2 * q));
+        const f2v u = tload<CACHED>(reinterpret_cast<const f2v *>(row + 2 * q));
         a[0] = u.x;
         a[1] = u.y;
     }
@@ -252,7 +259,7 @@ template <> struct BLd<float, 32> {
 // The other workgroups: one stored packed tile each, as the single-box FP64
 // product (4 waves; a 16-lane row group per bead row; each lane owns the
 // NE bead columns of BLd; FP64 accumulation for both tile types).
-template <int TBB, typename T, int M>
+template <int TBB, typename T, int M, bool CACHED>
 __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb, int nk, int nm1,
                                                const int *__restrict__ tile_box,
                                                const BoxDev *__restrict__ boxes,
@@ -356,7 +363,7 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb
         const T *row = tile + (size_t)i * 6 * TBB;
         double b[6][NE];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) BLd<T, TBB>::load(row + c * TBB, q, b[c]);
+        for (int c = 0; c < 6; ++c) BLd<T, TBB>::template load<CACHED>(row + c * TBB, q, b[c]);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             double r0 = 0.0, r1 = 0.0, r2 = 0.0;
@@ -754,6 +761,7 @@ using namespace rpy;
 
 struct rpy_batch {
     int nbox = 0, tbb = 64, lowp = RPY_PREC_F64;
+    int sf_front = 0, tile_cached = 0;   // product variant (rpy_batch_set_variant)
     int G = 0, ntb = 0, nstor = 0, maxnbt = 0, nchain = 0;
     int nk = 0, nmax = 0;
     std::vector<int64_t> bead0;   // padded bead offsets of the boxes (nbox + 1)
@@ -1035,11 +1043,17 @@ static void bsymv(rpy_batch *b, const T *tiles, const double *v, hipStream_t s)
     const size_t sm_sf = (size_t)(2 * TBB * 3 * nm1 + TBB * 3 * M) * sizeof(double);
     const size_t sm_t = (size_t)5 * M * 3 * TBB * sizeof(double);
     const int total = nsf + b->nstor;
-    const int sfr = total / nsf > 1 ? total / nsf : 1;   // one structure-factor workgroup per sfr
-    hipLaunchKernelGGL((k_bsymv<TBB, T, M>), dim3(total), dim3(256),
-                       sm_sf > sm_t ? sm_sf : sm_t, s, 3 * b->G, nsf, sfr, nkb, b->nk, nm1,
-                       b->tile_box, b->boxes, b->stor, b->kvec, b->etab, b->sfpart, tiles, v,
-                       b->part);
+    // spread: one structure-factor workgroup every sfr; front: the first nsf
+    const int sfr = b->sf_front ? 1 : (total / nsf > 1 ? total / nsf : 1);
+    const size_t lds = sm_sf > sm_t ? sm_sf : sm_t;
+    if (b->tile_cached)
+        hipLaunchKernelGGL((k_bsymv<TBB, T, M, true>), dim3(total), dim3(256), lds, s, 3 * b->G,
+                           nsf, sfr, nkb, b->nk, nm1, b->tile_box, b->boxes, b->stor, b->kvec,
+                           b->etab, b->sfpart, tiles, v, b->part);
+    else
+        hipLaunchKernelGGL((k_bsymv<TBB, T, M, false>), dim3(total), dim3(256), lds, s, 3 * b->G,
+                           nsf, sfr, nkb, b->nk, nm1, b->tile_box, b->boxes, b->stor, b->kvec,
+                           b->etab, b->sfpart, tiles, v, b->part);
 }
 
 // y = D.v for m = 1 or 2 vectors in the padded layout, epilogue f.
@@ -1063,6 +1077,8 @@ static void bproduct(rpy_batch *b, const double *v, int m, int prec, const EpiAr
                         (size_t)(b->nruns + 1) * sizeof(int4);
     const size_t red = (size_t)3 * m * 256 * sizeof(double);
     const size_t stk = (size_t)b->nk * 6 * m * sizeof(double) + sizeof(double2);
+    // staging T_k costs occupancy: with two vectors (82 KB of LDS at 618
+    // wave vectors) the back-projection took 762 against 531 us unstaged
     const bool stage = tabb + stk <= 65536;
     size_t lds = tabb + (stage ? stk : 0);
     lds = lds > red ? lds : red;
@@ -1276,6 +1292,37 @@ extern "C" int rpy_batch_run(rpy_batch *b, double *pos, const bd_params *bp, uin
     if (rc) return rc;
     for (int i = 0; i < n_steps; ++i) BHIP(hipGraphLaunch(b->gexec, s));
     return RPY_OK;
+}
+
+static void bgraph_drop(rpy_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+}
+
+extern "C" int rpy_batch_set_variant(rpy_batch *b, int sf_place, int tile_loads)
+{
+    if (!b || (sf_place != RPY_SF_SPREAD && sf_place != RPY_SF_FRONT) ||
+        (tile_loads != RPY_LOADS_STREAM && tile_loads != RPY_LOADS_CACHED))
+        return RPY_EINVAL;
+    const int front = sf_place == RPY_SF_FRONT, cached = tile_loads == RPY_LOADS_CACHED;
+    if (front != b->sf_front || cached != b->tile_cached) {
+        BHIP(hipDeviceSynchronize());   // a replay in flight keeps its own variant
+        bgraph_drop(b);
+        b->sf_front = front;
+        b->tile_cached = cached;
+    }
+    return RPY_OK;
+}
+
+extern "C" int64_t rpy_batch_graph_nodes(const rpy_batch *b)
+{
+    if (!b || !b->graph) return -1;
+    size_t n = 0;
+    if (hipGraphGetNodes(b->graph, nullptr, &n) != hipSuccess) return -1;
+    return (int64_t)n;
 }
 
 extern "C" int rpy_batch_observables(rpy_batch *b, const double *pos, double *re2, double *rg2,

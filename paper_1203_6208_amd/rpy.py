@@ -91,6 +91,8 @@ _SIG = {
     "rpy_batch_run": (_i, [_v, _v, _P(BdParams), ctypes.c_uint64, ctypes.c_uint64, _i, _v]),
     "rpy_batch_observables": (_i, [_v, _v, _v, _v, _v]),
     "rpy_batch_status": (_i, [_v, _v]),
+    "rpy_batch_set_variant": (_i, [_v, _i, _i]),
+    "rpy_batch_graph_nodes": (ctypes.c_int64, [_v]),
 }
 for _name, (_res, _args) in _SIG.items():
     _f = getattr(_lib, _name)
@@ -483,6 +485,19 @@ def rpy_batch_status(b, stream=None) -> int:
     return _lib.rpy_batch_status(b, _stream(stream))
 
 
+SF_SPREAD, SF_FRONT = 0, 1
+LOADS_STREAM, LOADS_CACHED = 0, 1
+
+
+def rpy_batch_set_variant(b, sf_place=SF_SPREAD, tile_loads=LOADS_STREAM):
+    _check(_lib.rpy_batch_set_variant(b, int(sf_place), int(tile_loads)),
+           "rpy_batch_set_variant")
+
+
+def rpy_batch_graph_nodes(b) -> int:
+    return int(_lib.rpy_batch_graph_nodes(b))
+
+
 class Batch:
     """Owns one rpy_batch over ``inputs.Workload`` boxes; converts between the
     per-box ``[N_b, 3]`` arrays and the padded global layout."""
@@ -524,6 +539,12 @@ class Batch:
 
     def build(self, pos, stream=None):
         rpy_batch_build(self.handle, pos, stream)
+
+    def set_variant(self, sf_place=SF_SPREAD, tile_loads=LOADS_STREAM):
+        rpy_batch_set_variant(self.handle, sf_place, tile_loads)
+
+    def graph_nodes(self):
+        return rpy_batch_graph_nodes(self.handle)
 
     def apply(self, v, prec="f64", stream=None):
         v = v.reshape(-1, self.G, 3).contiguous()

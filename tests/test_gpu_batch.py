@@ -254,16 +254,51 @@ def test_full_ensemble_sampled(orc):
 
 
 def test_autotuner_picks_a_measured_candidate(ref):
-    """The tile autotuner times every candidate on the given boxes and returns
-    the fastest one together with its measurements."""
+    """The autotuner times every candidate of its search space (tile size x
+    structure-factor placement x tile-load policy) on the given boxes and
+    returns the fastest one together with its measurements."""
     _say("autotune")
     ws = [r[0] for r in ref]
     bp = rpy.make_bd_params(dt=1e-3, n_cheb=NCH, bounds_rule=rpy.BOUNDS_PAPER,
                             bounds_C=C_RULE, prec="f32")
     best, times = autotune.tune_batch(ws, bp, lowp="f32", steps=2)
-    assert set(times) == {32, 64}
+    assert set(times) == set(autotune.search_space()) and len(times) == 8
     assert best in times and times[best] == min(times.values())
     assert all(t > 0 for t in times.values())
+
+
+@pytest.mark.parametrize("tb", [32, 64])
+def test_batch_variants_give_identical_steps(ref, tb):
+    """Every product variant (structure-factor workgroups spread or in front,
+    non-temporal or allocating tile loads) gives the same step bit for bit,
+    eager and as a graph replay; the captured step graph has a fixed number
+    of kernel nodes (wrap, build, springs, the drift product's 3 launches,
+    noise, interval, N_Ch - 1 Chebyshev products of 3 launches, the update and
+    the step counter)."""
+    _say(f"batch variants tb={tb}")
+    ws = [r[0] for r in ref]
+    bp = rpy.make_bd_params(dt=1e-3, n_cheb=NCH, bounds_rule=rpy.BOUNDS_PAPER,
+                            bounds_C=C_RULE, prec="f32")
+    B = rpy.Batch(ws, lowp="f32", tile_beads=tb)
+    pos0 = B.pack([w.positions() for w in ws])
+    outs = []
+    for sf in (rpy.SF_SPREAD, rpy.SF_FRONT):
+        for ld in (rpy.LOADS_STREAM, rpy.LOADS_CACHED):
+            B.set_variant(sf, ld)
+            pe, pg = pos0.clone(), pos0.clone()
+            B.step(pe, bp, seed=6, step=2)
+            B.run(pg, bp, seed=6, step0=2, n_steps=1)
+            torch.cuda.synchronize()
+            assert torch.equal(pe, pg)
+            outs.append(pe)
+            nodes = B.graph_nodes()
+            assert nodes == 10 + 3 * (NCH - 1), nodes
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    with pytest.raises(rpy.RpyError):
+        rpy.rpy_batch_set_variant(B.handle, 2, 0)
+    assert B.status() == 0
+    B.close()
 
 
 @pytest.mark.parametrize("tb", [32, 64])
