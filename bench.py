@@ -54,9 +54,9 @@ TRAFFIC_BLOCK = {"src_sha256": "8d588113f61ed8f5d5b1b75bb6262794ff41391bca81ced3
                                       "bf16": 111240949 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "733cc46850c2f62d0ad3c3f0ec07554155937491b7b1ee49058b1139a98bf04f",
+TRAFFIC_BATCH = {"src_sha256": "e968381d06deee0563331851c49a226c070f3db0eb7822c4a75f23952ab142ce",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4931232044}
+                 "bytes_per_launch": 4965670275}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 TOL_EF = 1e-2     # E_f tolerance of the headline's adaptive order
