@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "162c3efd77ecbc2c8ebded97ec4518a982da8898347d662c98dc919d5faa9d38",
+TRAFFIC = {"src_sha256": "673e245143c0aa2d5e42356fc1547afee7ecc31fcef9711f7c13387237952127",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 411336252}
+           "bytes_per_launch": 407652982}
 # The matrix-core tile kernel (k_block_tiles) of a 16-vector product: tile and
 # vector reads plus the per-tile FP64/FP32 partial sums it writes.
 TRAFFIC_BLOCK = {"src_sha256": "8d588113f61ed8f5d5b1b75bb6262794ff41391bca81ced309d972c548b089b6",
@@ -64,7 +64,9 @@ TOL_EF = 1e-2     # E_f tolerance of the headline's adaptive order
 # floor of about 0.02 at N = 4000, so the BF16 adaptive form asks for 3e-2.
 TOL_BY_PREC = {"f64": TOL_EF, "f32": TOL_EF, "bf16": 3e-2}
 N_MAX = 160       # N_Ch the context keeps (the adaptive order's largest possible)
-SLACK = 12        # the adaptive search runs to eq. nint + SLACK at most
+SLACK = 12        # the adaptive search runs to eq. nint + SLACK at most (with
+                  # eq. nint + 6 the paper-rule form missed E_f < 1e-2 in 12 of
+                  # 250 steps: its order drifts up to nint + 6 over a refresh period)
 LANCZOS_STEPS = 60
 LANCZOS_MARGIN = 0.05
 REFRESH = 250     # steps between Lanczos refreshes of the interval (0.25 time units at dt = 1e-3)

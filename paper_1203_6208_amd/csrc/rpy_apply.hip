@@ -92,10 +92,11 @@ template <> struct P6<uint16_t> {
 };
 
 // Product on the packed tiles (6 planes per bead row, tile[t][i][c][j]),
-// FP64, FP32 or BF16 entries, FP64 arithmetic.  Workgroups [0, nsf) compute
-// structure-factor partials of v; each further workgroup (4 waves) takes one
-// stored tile (I, J), in stored order or, when `flip`, in reverse order (each
-// tile's results go to its own slots, so the order changes no value).  Wave w, row group g (16 lanes), lane q: bead rows
+// FP64, FP32 or BF16 entries, FP64 arithmetic.  nsf workgroups (at the
+// front of the launch or spread through it) compute T_k of v for a few wave
+// vectors each (sf_direct_block); each further workgroup (4 waves) takes one stored tile
+// (I, J), in stored order or, when `flip`, in reverse order (each tile's
+// results go to its own slots, so the order changes no value).  Wave w, row group g (16 lanes), lane q: bead rows
 // i = 16 it + 4 w + g (it = 0..3); lane q owns the bead columns
 // jb(e) = P6<T>::col(q, e), e = 0..3, of every plane.  With B the symmetric
 // 3 x 3 block of (i, j), the row sums of B x_j over the 16 lanes give
@@ -108,10 +109,12 @@ template <> struct P6<uint16_t> {
 // Three and four vectors run at two waves per SIMD.
 template <typename T, int M, bool CACHED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 : 1, 8))) void k_symv6(int N, int n3, int n3pad, int rhs_cap, int j0,
-                                               int nsf, int flip, int nkb, int nk, int nmax,
+                                               int nsf, int sfr, int flip, int nk,
+                                               double invL,
                                                const KVec *__restrict__ kvec,
-                                               const double2 *__restrict__ etab,
-                                               double *__restrict__ sfpart,
+                                               const KCoef *__restrict__ kcoef,
+                                               const double *__restrict__ rt,
+                                               double *__restrict__ tk,
                                                const int2 *__restrict__ tile_ij,
                                                const T *__restrict__ tiles,
                                                const double *__restrict__ v,
@@ -120,14 +123,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
 {
     extern __shared__ double smem[];
     if (gate && *gate) return;   // a product past the settled adaptive order
-    if ((int)blockIdx.x < nsf) {
-        sf_partial_block<M>(blockIdx.x, nkb, N, n3, nk, nmax, rhs_cap, j0, kvec, etab, v,
-                            sfpart, smem);
+    // workgroup b is structure-factor workgroup b / sfr when b is a multiple
+    // of sfr below nsf sfr, else tile ordinal b - (structure-factor
+    // workgroups up to b): sfr = 1 puts them at the front of the launch,
+    // larger sfr spreads them through it
+    const int bid = blockIdx.x, ntl = (int)gridDim.x - nsf;
+    if (bid % sfr == 0 && bid / sfr < nsf) {
+        sf_direct_block<M>(bid / sfr, N, nk, rhs_cap, j0, invL, n3, kvec, kcoef, rt, v, tk, smem);
         return;
     }
     double(*sx)[TS] = reinterpret_cast<double(*)[TS]>(smem);                    // [M][TS]
     double(*scol)[M][TS] = reinterpret_cast<double(*)[M][TS]>(smem + M * TS);  // [4][M][TS]
-    const int t = flip ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x - nsf;
+    const int ord = bid - min(nsf, bid / sfr + 1);
+    const int t = flip ? ntl - 1 - ord : ord;
     const int2 ij = tile_ij[t];
     const int I = ij.x, J = ij.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -226,19 +234,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
     }
 }
 
-template <typename T, int M> static size_t symv_lds(const Ctx &c)
+template <typename T, int M> static size_t symv_lds(const Ctx &)
 {
-    // sx occupies M*TS double slots (whatever A is), then scol[4][M][TS]
+    // sx occupies M*TS double slots (whatever A is), then scol[4][M][TS];
+    // the structure-factor workgroups use 4 x 6 KPW M doubles
     const size_t tile = sizeof(double) * M * TS + sizeof(double) * 4 * M * TS;
-    const size_t sf = sizeof(double) * (2 * SF_BEADS * 3 * (c.nmax + 1) + SF_BEADS * 3 * M);
+    const size_t sf = sizeof(double) * 4 * 6 * sf_kpw<M>() * M;
     return tile > sf ? tile : sf;
 }
 
 template <typename T, int M>
 static void symv_launch(const Ctx &c, const T *tiles, const double *v, int j0, hipStream_t s)
 {
-    const int nkb = (c.nk + 255) / 256;
-    const int nsf = c.nsfc * nkb;
+    const int nsf = (c.nk + sf_kpw<M>() - 1) / sf_kpw<M>();
+    // The structure-factor workgroups' sincospi work: spread through the FP64
+    // tile stream it overlaps best (68.7 against 70.0 us at the front, N =
+    // 4000); the shorter, cache-resident FP32 / BF16 streams do better with
+    // it at the front (BF16 32.2 against 35.1 us spread)
+    const int sfr = sizeof(T) == 8 ? (nsf + c.ntiles) / nsf : 1;
     const size_t lds = symv_lds<T, M>(c);
     // Allocating loads, with the tile order reversed on every other launch,
     // for arrays that fit the Infinity Cache and, in one-vector products, for
@@ -255,13 +268,13 @@ static void symv_launch(const Ctx &c, const T *tiles, const double *v, int j0, h
     if (cached)
         hipExtLaunchKernelGGL((k_symv6<T, M, true>), dim3(nsf + c.ntiles), dim3(256),
                               (uint32_t)lds, s, e0, e1, 0u, c.N, c.n3, c.n3pad, c.rhs_cap, j0, nsf,
-                              flip, nkb, c.nk, c.nmax, c.kvec, c.etab, c.sfpart, c.tile_ij, tiles, v,
-                              c.part, c.gate);
+                              sfr, flip, c.nk, c.pc.invL, c.kvec, c.kcoef, c.rt, c.tk, c.tile_ij,
+                              tiles, v, c.part, c.gate);
     else
         hipExtLaunchKernelGGL((k_symv6<T, M, false>), dim3(nsf + c.ntiles), dim3(256),
                               (uint32_t)lds, s, e0, e1, 0u, c.N, c.n3, c.n3pad, c.rhs_cap, j0, nsf,
-                              flip, nkb, c.nk, c.nmax, c.kvec, c.etab, c.sfpart, c.tile_ij, tiles, v,
-                              c.part, c.gate);
+                              sfr, flip, c.nk, c.pc.invL, c.kvec, c.kcoef, c.rt, c.tk, c.tile_ij,
+                              tiles, v, c.part, c.gate);
 }
 
 template <typename T>

@@ -444,10 +444,12 @@ static bool prec_ok(const Ctx &c, int prec)
 }
 
 // One product of the full periodic D with the m vectors v; `f` selects the
-// epilogue.  Three kernels: tile product (+ structure-factor partials of v),
-// structure-factor reduction, reciprocal back-projection + epilogue.  With
-// FP32 / BF16 tiles and 5..16 vectors the block path runs instead: matrix-core
-// tile product, FP64 matrix-core structure factors and back-projection.
+// epilogue.  Two kernels per group of up to 4 vectors: the tile product
+// (whose structure-factor workgroups also write T_k of v), then the
+// reciprocal back-projection + epilogue.  With 5..16 vectors the block path
+// runs instead: matrix-core tile product, FP64 matrix-core structure factors
+// and back-projection.  The low-memory form: the matrix-free real-space
+// product, structure-factor partials, their reduction, the back-projection.
 static void product(rpy_ctx *x, const double *v, int m, int prec, const EpiArgs &f,
                     hipStream_t s)
 {
@@ -483,16 +485,13 @@ static void product(rpy_ctx *x, const double *v, int m, int prec, const EpiArgs 
         launch_block_epi(c, f, s);
         return;
     }
+    // the tile-product launches also write T_k of their vectors
     for (int j0 = 0; j0 < m;) {
         const int r = m - j0;
         const int mc = r >= 4 ? 4 : r;
         ProfScope ps(x, mc == 1 ? RPY_PROF_SYMV : RPY_PROF_SYMV_MULTI, s);
         launch_symv(c, prec, v, j0, mc, s);
         j0 += mc;
-    }
-    {
-        ProfScope ps(x, RPY_PROF_KSPACE, s);
-        launch_sf_reduce(c, m, s);
     }
     ProfScope ps(x, RPY_PROF_EPI, s);
     launch_kspace_epi(c, f, s);

@@ -8,7 +8,9 @@ N_c = 20 chains, a = 0.5, dt = 0.01, periodic Ewald RPY with the overlap
 correction, FP64.  The order of every step is the paper's: eq. nint on the
 interval, raised until E_f < 1e-2 (bd_step with tol > 0, on the device); the
 interval comes from an 80-step Lanczos run (margin 0.2) on the current
-positions, refreshed every 250 steps.  Cases: N_b = 20 at c/c* = 1, and
+positions, refreshed every 100 steps, and the order may grow to eq. nint + 24
+(at dt = 0.01 a close approach of two beads between refreshes can push the
+smallest eigenvalue of D below the interval, and the order then grows).  Cases: N_b = 20 at c/c* = 1, and
 N_b = 40 at both ends of the paper's concentration range, c/c* = 3e-4 and 3.
 The start is an equilibrium sample (random walks), so the time averages are
 unbiased apart from the O(dt) bias of the Euler scheme (below 1%).  The
@@ -34,7 +36,7 @@ from paper_1203_6208_amd import rpy  # noqa: E402
 
 TOL = 1e-2
 N_MAX = 96
-SLACK = 12
+SLACK = 24
 
 
 def _say(msg):
@@ -50,7 +52,7 @@ def test_theta_statics_with_hydrodynamic_interaction(bpc, cc, nsteps):
     ctx = rpy.context_for(w, cheb_keep=N_MAX)
     bp = rpy.make_bd_params(dt=w.dt, n_cheb=0, bounds_rule=rpy.BOUNDS_EXPLICIT, tol=TOL,
                             n_max=N_MAX)
-    every, refresh = 10, 250
+    every, refresh = 10, 100
     ns = nsteps // every
     re2 = torch.empty((ns, w.nchains), dtype=torch.float64, device="cuda")
     rg2 = torch.empty_like(re2)
@@ -70,9 +72,9 @@ def test_theta_statics_with_hydrodynamic_interaction(bpc, cc, nsteps):
             q2[r] = (bonds * bonds).sum(dim=2).mean(dim=1)
         if (i + 1) % 4000 == 0:
             _say(f"  step {i + 1}")
-    assert ctx.status() == 0
     calls, mean_n, max_n, missed = ctx.order_stats()
     _say(f"  N_Ch mean {mean_n:.2f} max {max_n}, missed {missed}, max E_f {float(efs.max()):.3e}")
+    assert ctx.status() == 0
     assert calls == nsteps and missed == 0
     assert float(efs.max()) < TOL
     for series, exact, nm in ((re2, 3.0 * (bpc - 1), "R_e^2"),
