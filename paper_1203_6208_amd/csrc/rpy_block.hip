@@ -44,6 +44,10 @@ typedef uint32_t u4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 constexpr int SF_WAVES = 4;    // waves per structure-factor workgroup
+constexpr int SF_U = 16;       // unrolled steps per block (quads per wave at N = 4000)
+constexpr int SF_PF = 3;       // steps loaded ahead
+constexpr int EPI_U = 10;      // the same for the back-projection (two blocks at 618 k)
+constexpr int EPI_PF = 3;
 
 __device__ inline uint16_t bf16_rne(float f)
 {
@@ -477,7 +481,7 @@ void launch_block_phases(const Ctx &c, hipStream_t s)
 // the quads w, w + 4, ... of the chunk.  Per quad, lane (g, i) holds the
 // phase of k = k0 + i and bead 4 q + g (the A operand of both products: row
 // = k, inner index = bead) and V[4 q + g][c][j = i] (the B operand), both
-// loaded 3 quads ahead; six 16x16x4 FP64 MFMAs add
+// loaded SF_PF quads ahead; six 16x16x4 FP64 MFMAs add
 //   sum_mu {cos, sin}(k.r_mu) v_{mu c j}.
 // The waves are summed in a fixed order through LDS and wave 0 writes the
 // block's partial sums contiguously:
@@ -490,34 +494,37 @@ struct SfLd {
 // treat as invariant get rematerialised at their use, which undoes the
 // prefetch.
 // Workgroups past the structure-factor grid (blockIdx.x >= nkb) sum the
-// tile partials instead, 16 beads each (48 rows x 16 vectors, contiguous in
-// every slot K): 16 slots per batch of independent loads, summed pairwise
-// inside a batch and batch after batch in K order, in FP64, into
-// ypart[j][row].  This HBM stream overlaps the matrix-core work.
+// tile partials instead: 16 rows x 16 vectors each, one output per thread
+// (rows 16 b .. 16 b + 15, contiguous with the vectors in every slot K).  A
+// thread issues the loads of PS_BATCH slots at once, sums them as a pairwise
+// tree and adds the batches in K order, in FP64, into ypart[j][row].  This
+// HBM stream overlaps the matrix-core work.
+constexpr int PS_BATCH = 32;
 template <typename P>
-__device__ inline void block_part_sum(int b, int N, int n3, int n3pad, int m, int nslot,
+__device__ inline void block_part_sum(int b, int n3, int n3pad, int m, int nslot,
                                       const P *__restrict__ part, double *__restrict__ ypart)
 {
-    const int nu0 = 16 * b, nb = min(16, N - nu0);
+    const int row = 16 * b + (threadIdx.x >> 4), j = threadIdx.x & 15;
+    if (row >= n3 || j >= m) return;
+    const P *pp = part + (size_t)row * BLOCK_RHS + j;
     const size_t ks = (size_t)n3pad * BLOCK_RHS;
-    for (int o = threadIdx.x; o < 48 * BLOCK_RHS; o += blockDim.x) {
-        const int r = o >> 4, j = o & 15;   // row 3 nu0 + r, vector j
-        if (r >= 3 * nb || j >= m) continue;
-        const P *pp = part + ((size_t)3 * nu0 + r) * BLOCK_RHS + j;
-        double y = 0.0;
-        int K = 0;
-        for (; K + 16 <= nslot; K += 16) {
-            P q[16];
+    double y = 0.0;
+    for (int K = 0; K < nslot; K += PS_BATCH) {
+        // branch-free: a slot past nslot re-reads the last one and is zeroed
+        // after the loads (a conditional load would wait at every join)
+        P raw[PS_BATCH];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) q[u] = pp[(K + u) * ks];
-            double t[8];
+        for (int u = 0; u < PS_BATCH; ++u) raw[u] = pp[(size_t)min(K + u, nslot - 1) * ks];
+        double q[PS_BATCH];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) t[u] = (double)q[2 * u] + (double)q[2 * u + 1];
-            y += ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
-        }
-        for (; K < nslot; ++K) y += (double)pp[K * ks];
-        ypart[(size_t)j * n3 + 3 * nu0 + r] = y;
+        for (int u = 0; u < PS_BATCH; ++u) q[u] = K + u < nslot ? (double)raw[u] : 0.0;
+#pragma unroll
+        for (int h = PS_BATCH / 2; h >= 1; h >>= 1)
+#pragma unroll
+            for (int u = 0; u < h; ++u) q[u] += q[u + h];
+        y += q[0];
     }
+    ypart[(size_t)j * n3 + row] = y;
 }
 
 __global__ __launch_bounds__(256) void k_block_sf(int nk, int nk16, int nq, int cq, int nkb,
@@ -532,14 +539,10 @@ __global__ __launch_bounds__(256) void k_block_sf(int nk, int nk16, int nq, int 
     if (gate && *gate) return;
     if ((int)blockIdx.x >= nkb) {
         const int b = (blockIdx.x - nkb) + blockIdx.y * (gridDim.x - nkb);
-        if (16 * b < N) {
-            if (part64)
-                block_part_sum(b, N, n3, n3pad, m, nslot, reinterpret_cast<const double *>(part),
-                               ypart);
-            else
-                block_part_sum(b, N, n3, n3pad, m, nslot, reinterpret_cast<const float *>(part),
-                               ypart);
-        }
+        if (part64)
+            block_part_sum(b, n3, n3pad, m, nslot, reinterpret_cast<const double *>(part), ypart);
+        else
+            block_part_sum(b, n3, n3pad, m, nslot, reinterpret_cast<const float *>(part), ypart);
         return;
     }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -562,9 +565,9 @@ __global__ __launch_bounds__(256) void k_block_sf(int nk, int nk16, int nq, int 
         d.x[1] = xv[BLOCK_RHS];
         d.x[2] = xv[2 * BLOCK_RHS];
     };
-    // Ring of 4 buffers in fixed registers (loop unrolled by 4): buffer b
-    // is loaded 3 steps before it is consumed.  A step past the chunk
-    // consumes a zero phase.
+    // A ring of SF_PF + 1 buffers in fixed registers: each is loaded SF_PF
+    // steps before it is consumed.  A step past the chunk consumes a zero
+    // phase.
     auto use = [&](const SfLd &d, int q) {
         const bool on = q < q1;
         const double c = on ? d.e.x : 0.0, sn = on ? d.e.y : 0.0;
@@ -576,27 +579,26 @@ __global__ __launch_bounds__(256) void k_block_sf(int nk, int nk16, int nq, int 
         acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(sn, d.x[2], acc[5], 0, 0, 0);
     };
     constexpr int S = SF_WAVES;
-    SfLd b0, b1, b2, b3;
+    // Blocks of SF_U steps, each fully unrolled: the prefetches stay inside
+    // a block, so no load is in flight across a loop back edge (the
+    // compiler then waits for all of them at the loop head) and every wait
+    // leaves the next SF_PF steps' loads outstanding.
     const int qa = q0 + w;
-    fetch(qa, b0);
-    fetch(qa + S, b1);
-    fetch(qa + 2 * S, b2);
-    for (int q = qa; q < q1; q += 4 * S) {
-        // compiler-only barriers keep each prefetch where it is written (the
-        // loaded values are otherwise forwarded and the loads re-issued
-        // where they are consumed)
-        fetch(q + 3 * S, b3);
-        __asm__ volatile("" ::: "memory");
-        use(b0, q);
-        fetch(q + 4 * S, b0);
-        __asm__ volatile("" ::: "memory");
-        use(b1, q + S);
-        fetch(q + 5 * S, b1);
-        __asm__ volatile("" ::: "memory");
-        use(b2, q + 2 * S);
-        fetch(q + 6 * S, b2);
-        __asm__ volatile("" ::: "memory");
-        use(b3, q + 3 * S);
+    const int nsteps = q1 > qa ? (q1 - qa + S - 1) / S : 0;
+    for (int t0 = 0; t0 < nsteps; t0 += SF_U) {
+        const int qb = qa + t0 * S;
+        SfLd b[SF_PF + 1];
+#pragma unroll
+        for (int t = 0; t < SF_PF; ++t) fetch(qb + t * S, b[t]);
+#pragma unroll
+        for (int t = 0; t < SF_U; ++t) {
+            // compiler-only barrier: keeps each prefetch where it is written
+            // (the loaded values are otherwise forwarded and the loads
+            // re-issued where they are consumed)
+            if (t + SF_PF < SF_U) fetch(qb + (t + SF_PF) * S, b[(t + SF_PF) % (SF_PF + 1)]);
+            __asm__ volatile("" ::: "memory");
+            use(b[t % (SF_PF + 1)], qb + t * S);
+        }
     }
     if (w > 0)
 #pragma unroll
@@ -654,8 +656,8 @@ void launch_block_sf(const Ctx &c, int m, int prec, hipStream_t s)
     const int cq = (nq + c.nchb - 1) / c.nchb;
     const int nkb = (c.nk + 15) / 16;
     // grid x: nkb structure-factor blocks, then ceil(npg / nchb) part-sum
-    // workgroups per grid row (npg = 16-bead groups)
-    const int npg = (c.N + 15) / 16;
+    // workgroups per grid row (npg = groups of 16 rows)
+    const int npg = (c.n3 + 15) / 16;
     const int px = (npg + c.nchb - 1) / c.nchb;
     hipLaunchKernelGGL(k_block_sf, dim3(nkb + px, c.nchb), dim3(64 * SF_WAVES), 0, s, c.nk,
                        (c.nk + 15) / 16 * 16, nq, cq, nkb, c.N, c.n3, c.n3pad, m, c.nbt, c.eph,
@@ -671,7 +673,7 @@ void launch_block_sf(const Ctx &c, int m, int prec, hipStream_t s)
 // wave-vector steps w, w + EPI_W, ... (4 wave vectors each).  Lane (g, i)
 // holds the phase of bead nu0 + i and k = 4 step + g (A operand: row =
 // bead, inner = k) and T[k][3 half + c][j = i] (B operand; tkm rows >= nk are
-// zero), loaded 3 steps ahead; six FP64 MFMAs per step add
+// zero), loaded EPI_PF steps ahead; six FP64 MFMAs per step add
 //   sum_k cos(k.r) Tc + sin(k.r) Ts,  c = 0..2.
 // The waves are summed in a fixed order in LDS; thread (j, bead) adds the
 // summed tile partials ypart and applies the epilogue of f.mode (as in
@@ -710,31 +712,29 @@ __global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int nk4
     auto use = [&](const EpiLd &d, int st) {
         const bool on = st < nst;
         const double c = on ? d.e.x : 0.0, sn = on ? d.e.y : 0.0;
+        // the three cos products, then the three sin products: no MFMA waits
+        // on the one just issued
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
+        for (int cc = 0; cc < 3; ++cc)
             acc[cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(c, d.t[cc], acc[cc], 0, 0, 0);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
             acc[cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(sn, d.t[3 + cc], acc[cc], 0, 0, 0);
-        }
     };
-    // ring of 4 buffers in fixed registers, as in k_block_sf
     constexpr int S = EPI_W;
-    EpiLd b0, b1, b2, b3;
-    fetch(w, b0);
-    fetch(w + S, b1);
-    fetch(w + 2 * S, b2);
-    for (int st = w; st < nst; st += 4 * S) {
-        fetch(st + 3 * S, b3);
-        __asm__ volatile("" ::: "memory");
-        use(b0, st);
-        fetch(st + 4 * S, b0);
-        __asm__ volatile("" ::: "memory");
-        use(b1, st + S);
-        fetch(st + 5 * S, b1);
-        __asm__ volatile("" ::: "memory");
-        use(b2, st + 2 * S);
-        fetch(st + 6 * S, b2);
-        __asm__ volatile("" ::: "memory");
-        use(b3, st + 3 * S);
+    // blocks of EPI_U fully unrolled steps, as in k_block_sf
+    const int nsteps = (nst - w + S - 1) / S;
+    for (int t0 = 0; t0 < nsteps; t0 += EPI_U) {
+        const int sb = w + t0 * S;
+        EpiLd b[EPI_PF + 1];
+#pragma unroll
+        for (int t = 0; t < EPI_PF; ++t) fetch(sb + t * S, b[t]);
+#pragma unroll
+        for (int t = 0; t < EPI_U; ++t) {
+            if (t + EPI_PF < EPI_U) fetch(sb + (t + EPI_PF) * S, b[(t + EPI_PF) % (EPI_PF + 1)]);
+            __asm__ volatile("" ::: "memory");
+            use(b[t % (EPI_PF + 1)], sb + t * S);
+        }
     }
     // FP64 MFMA output: lane holds beads g + 4e of vector i
 #pragma unroll
