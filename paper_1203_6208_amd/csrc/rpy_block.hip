@@ -62,7 +62,28 @@ __device__ inline uint16_t bf16_rne(float f)
 //               at xh + 3 npad 16 (a hi + lo pair: about 16 significant bits)
 //   FP64:       vpk[r][j], r = 3 bead + c (the reciprocal sum's operand)
 // so that a workgroup stages the 64 beads of a bead tile with contiguous
-// loads, and 16 lanes read 16 vectors of one row together.
+// loads, and 16 lanes read 16 vectors of one row together.  pack_entry writes
+// one (bead, c, j) entry of both; k_pack_block packs a whole block (zeros
+// included), and the Chebyshev epilogue packs its output for the next product.
+__device__ inline void pack_entry(int prec, int npad, int bead, int c, int j, double x,
+                                  void *__restrict__ xs, double *__restrict__ vpk)
+{
+    vpk[(size_t)(3 * bead + c) * BLOCK_RHS + j] = x;
+    if (prec == RPY_PREC_BF16) {
+        const size_t o = (size_t)(c * BLOCK_RHS + j) * npad + bead;
+        uint16_t *xh = reinterpret_cast<uint16_t *>(xs);
+        const uint16_t h = bf16_rne((float)x);
+        const double hv = (double)__uint_as_float((uint32_t)h << 16);
+        xh[o] = h;
+        xh[(size_t)3 * npad * BLOCK_RHS + o] = bf16_rne((float)(x - hv));
+    } else {
+        const size_t o = ((size_t)c * npad + bead) * BLOCK_RHS + j;
+        if (prec == RPY_PREC_F64) reinterpret_cast<double *>(xs)[o] = x;
+        else reinterpret_cast<float *>(xs)[o] = (float)x;
+    }
+}
+
+// One thread per packed entry (bead < npad, c, j < 16).
 __global__ void k_pack_block(int N, int n3, int npad, int m, int prec,
                              const double *__restrict__ v, void *__restrict__ xs,
                              double *__restrict__ vpk, const int *__restrict__ gate)
@@ -70,24 +91,9 @@ __global__ void k_pack_block(int N, int n3, int npad, int m, int prec,
     if (gate && *gate) return;   // a product past the settled adaptive order
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= 3 * npad * BLOCK_RHS) return;
-    {
-        const int r = o >> 4, j = o & 15;
-        vpk[o] = (j < m && r < n3) ? v[(size_t)j * n3 + r] : 0.0;
-    }
-    if (prec == RPY_PREC_BF16) {
-        const int bead = o % npad, cj = o / npad, j = cj & 15, c = cj >> 4;
-        const double x = (j < m && bead < N) ? v[(size_t)j * n3 + 3 * bead + c] : 0.0;
-        uint16_t *xh = reinterpret_cast<uint16_t *>(xs);
-        const uint16_t h = bf16_rne((float)x);
-        const double hv = (double)__uint_as_float((uint32_t)h << 16);
-        xh[o] = h;
-        xh[(size_t)3 * npad * BLOCK_RHS + o] = bf16_rne((float)(x - hv));
-    } else {
-        const int j = o & 15, bead = (o >> 4) % npad, c = (o >> 4) / npad;
-        const double x = (j < m && bead < N) ? v[(size_t)j * n3 + 3 * bead + c] : 0.0;
-        if (prec == RPY_PREC_F64) reinterpret_cast<double *>(xs)[o] = x;
-        else reinterpret_cast<float *>(xs)[o] = (float)x;
-    }
+    const int j = o & 15, r = o >> 4, bead = r / 3, c = r % 3;
+    const double x = (j < m && bead < N) ? v[(size_t)j * n3 + r] : 0.0;
+    pack_entry(prec, npad, bead, c, j, x, xs, vpk);
 }
 
 // Per element type: the lane's 16-byte loads of a plane row, the vector and
@@ -427,12 +433,14 @@ static void block_tiles_launch(const Ctx &c, const T *tiles, hipStream_t s)
                               c.gate);
 }
 
-void launch_block_tiles(const Ctx &c, int prec, const double *v, int m, hipStream_t s)
+void launch_block_tiles(const Ctx &c, int prec, const double *v, int m, hipStream_t s,
+                        bool packed)
 {
     const int npad = c.nbt * TB;
     const int np = 3 * npad * BLOCK_RHS;
-    hipLaunchKernelGGL(k_pack_block, dim3((np + 255) / 256), dim3(256), 0, s, c.N, c.n3, npad, m,
-                       prec, v, c.xpk, c.vpk, c.gate);
+    if (!packed)
+        hipLaunchKernelGGL(k_pack_block, dim3((np + 255) / 256), dim3(256), 0, s, c.N, c.n3, npad,
+                           m, prec, v, c.xpk, c.vpk, c.gate);
     if (prec == RPY_PREC_BF16) block_tiles_launch<uint16_t>(c, c.p16, s);
     else if (prec == RPY_PREC_F32) block_tiles_launch<float>(c, c.p32, s);
     else block_tiles_launch<double>(c, c.d64, s);
@@ -677,7 +685,8 @@ void launch_block_sf(const Ctx &c, int m, int prec, hipStream_t s)
 //   sum_k cos(k.r) Tc + sin(k.r) Ts,  c = 0..2.
 // The waves are summed in a fixed order in LDS; thread (j, bead) adds the
 // summed tile partials ypart and applies the epilogue of f.mode (as in
-// k_kspace_epi).
+// k_kspace_epi); with f.pack it also writes V_p in the packed layouts, so the
+// next product of the series needs no packing launch.
 constexpr int EPI_W = 8;
 struct EpiLd {
     double2 e;
@@ -686,7 +695,10 @@ struct EpiLd {
 __global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int nk4, int nk16,
                                                           const double2 *eph, const double *tkm,
                                                           const double *__restrict__ ypart,
-                                                          EpiArgs f, const int *__restrict__ gate)
+                                                          EpiArgs f, int npad,
+                                                          void *__restrict__ xs,
+                                                          double *__restrict__ vpk,
+                                                          const int *__restrict__ gate)
 {
     __shared__ double red[EPI_W][3][16][17];
     if (gate && *gate) return;
@@ -762,10 +774,12 @@ __global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int nk4
             f.vout[o] = v1;
             f.acc[o] = 0.5 * f.scal[8] * v0 + f.scal[9] * v1;
             if (f.dv) f.dv[o] = yy;
+            if (f.pack) pack_entry(f.pack_prec, npad, bead, c, j, v1, xs, vpk);
         } else {
             const double vp = 2.0 * (ya * yy - yb * f.vprev[o]) - f.vprev2[o];
             f.vout[o] = vp;
             f.acc[o] += f.scal[8 + f.p] * vp;
+            if (f.pack) pack_entry(f.pack_prec, npad, bead, c, j, vp, xs, vpk);
         }
     }
 }
@@ -773,7 +787,8 @@ __global__ __launch_bounds__(64 * EPI_W) void k_block_epi(int N, int n3, int nk4
 void launch_block_epi(const Ctx &c, const EpiArgs &f, hipStream_t s)
 {
     hipLaunchKernelGGL(k_block_epi, dim3((c.N + 15) / 16), dim3(64 * EPI_W), 0, s, c.N, c.n3,
-                       c.nk4, (c.nk + 15) / 16 * 16, c.eph, c.tkm, c.ypart, f, c.gate);
+                       c.nk4, (c.nk + 15) / 16 * 16, c.eph, c.tkm, c.ypart, f, c.nbt * TB, c.xpk,
+                       c.vpk, c.gate);
 }
 
 }  // namespace rpy

@@ -450,8 +450,10 @@ static bool prec_ok(const Ctx &c, int prec)
 // runs instead: matrix-core tile product, FP64 matrix-core structure factors
 // and back-projection.  The low-memory form: the matrix-free real-space
 // product, structure-factor partials, their reduction, the back-projection.
+// prepacked: v is the output of the previous product of the same series,
+// whose block epilogue (f.pack) already wrote it in the packed layouts.
 static void product(rpy_ctx *x, const double *v, int m, int prec, const EpiArgs &f,
-                    hipStream_t s)
+                    hipStream_t s, bool prepacked = false)
 {
     const Ctx &c = x->c;
     if (c.lma) {   // matrix-free real space + structure factors of v
@@ -471,7 +473,7 @@ static void product(rpy_ctx *x, const double *v, int m, int prec, const EpiArgs 
     if (c.block && m >= BLOCK_MIN_RHS) {
         {
             ProfScope ps(x, RPY_PROF_SYMV, s);
-            launch_block_tiles(c, prec, v, m, s);
+            launch_block_tiles(c, prec, v, m, s, prepacked);
         }
         {
             ProfScope ps(x, RPY_PROF_KSPACE, s);
@@ -533,7 +535,9 @@ static void cheb_run(rpy_ctx *x, const double *dw, double *out, int m, int n_che
             f.vprev2 = p == 2 ? dw : x->Bv[p % 2];
             f.vout = x->Bv[p % 2];
         }
-        product(x, f.vprev, m, prec, f, s);
+        f.pack = p + 1 < n_cheb;   // V_p is the next product's input
+        f.pack_prec = prec;
+        product(x, f.vprev, m, prec, f, s, p > first);
     }
 }
 
@@ -586,8 +590,10 @@ static void cheb_adapt_run(rpy_ctx *x, int m, int prec, int first, int host_firs
             f.mode = EPI_CHEB_NEXT;
             f.vprev2 = vh + (p - 2) * ps;
         }
+        f.pack = p + 1 < nmax;   // V_p is the next product's input
+        f.pack_prec = prec;
         c.gate = p >= host_first ? done : nullptr;   // a trial may have settled the order
-        product(x, f.vprev, m, prec, f, s);
+        product(x, f.vprev, m, prec, f, s, p > first);
         c.gate = nullptr;
         trial(p + 1);
     }

@@ -501,6 +501,8 @@ struct EpiArgs {
     double *dv;            // optional: D.V_0 (EPI_CHEB_FIRST)
     const double *scal;    // device scalars (ya, yb, coeffs)
     double xs;             // EPI_ADJ: dv = xs * ya * vout
+    int pack;              // block product: also write vout in the operand layouts of
+    int pack_prec;         //   tiles of precision pack_prec (the next product's input)
 };
 void launch_symv(const Ctx &c, int prec, const double *v, int j0, int mc, hipStream_t s);
 // Block product D.V for 5 <= m <= 16 vectors (c.block): the tile product on
@@ -508,7 +510,8 @@ void launch_symv(const Ctx &c, int prec, const double *v, int j0, int mc, hipStr
 // partials), the FP64 matrix-core structure factors and their reduction to
 // tkm (with the fixed-order sum of the partials), and the FP64 matrix-core
 // back-projection fused with the epilogue `f`.
-void launch_block_tiles(const Ctx &c, int prec, const double *v, int m, hipStream_t s);
+void launch_block_tiles(const Ctx &c, int prec, const double *v, int m, hipStream_t s,
+                        bool packed = false);   // packed: the previous epilogue packed v
 void launch_block_phases(const Ctx &c, hipStream_t s);   // eph from the current tables
 void launch_block_sf(const Ctx &c, int m, int prec, hipStream_t s);
 void launch_block_epi(const Ctx &c, const EpiArgs &f, hipStream_t s);
