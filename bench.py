@@ -42,21 +42,21 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "673e245143c0aa2d5e42356fc1547afee7ecc31fcef9711f7c13387237952127",
+TRAFFIC = {"src_sha256": "1a61082e1a2133396411b69f66bb30ab0e066c9bf4b6da2e36fc0571f0920d38",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 407652982}
+           "bytes_per_launch": 407715533}
 # The matrix-core tile kernel (k_block_tiles) of a 16-vector product: tile and
 # vector reads plus the per-tile FP64/FP32 partial sums it writes.
-TRAFFIC_BLOCK = {"src_sha256": "8d588113f61ed8f5d5b1b75bb6262794ff41391bca81ced309d972c548b089b6",
+TRAFFIC_BLOCK = {"src_sha256": "58cbb4f9487cd3a8b60da89666800f48465459afbc6e0bf433161839ac58d974",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f64": 420293966 + 97542144,
-                                      "f32": 215921135 + 48771788,
-                                      "bf16": 111240949 + 48771072}}
+                 "bytes_per_launch": {"f64": 420254106 + 97542144,
+                                      "f32": 215976550 + 48771789,
+                                      "bf16": 111239578 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "e968381d06deee0563331851c49a226c070f3db0eb7822c4a75f23952ab142ce",
+TRAFFIC_BATCH = {"src_sha256": "e88eeeb4264571a41bd407e09d2888a931cc67dbbdd4d8bd0720cbdb5e5ad223",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4965670275}
+                 "bytes_per_launch": 4965848986}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 TOL_EF = 1e-2     # E_f tolerance of the headline's adaptive order
