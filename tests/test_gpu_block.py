@@ -147,6 +147,26 @@ def test_block_apply_n4000_sampled_rows(orc, prec):
     _check_bound(got, ref, Rrs, v, EPS[prec])
 
 
+def test_block_chebyshev_f64_n100(n100, orc):
+    """16 simultaneous dW through the Chebyshev recurrence (N_Ch = 20) on the
+    FP64 block product (FP64 tiles and accumulation on the matrix cores; each
+    product after the first reads the operands its predecessor's epilogue
+    packed), against the oracle's FP64 recurrence (eq. cheb1-cheb3) to the
+    FP64 parity tolerance."""
+    _say("block chebyshev n100 f64")
+    w, pos, D, Drs = n100
+    ctx = rpy.context_for(w, max_rhs=16)
+    ctx.build(_cuda(pos))
+    lam = np.linalg.eigvalsh(D)
+    lo, hi = 0.9 * lam[0], 1.1 * lam[-1]
+    nch = 20
+    dw = w.noise(m=16)
+    ds = ctx.sqrt_apply(_cuda(dw), nch, lo, hi).cpu().numpy().reshape(16, -1)
+    ref = orc.cheb_sqrt(D, dw.reshape(16, -1), nch, lo, hi)
+    rel = float(np.max(np.abs(ds - ref)) / np.max(np.abs(ref)))
+    assert rel < 1e-12, rel
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_block_chebyshev_n100(n100, orc, prec):
     """16 simultaneous dW through the Chebyshev recurrence (N_Ch = 20) on the
