@@ -468,7 +468,8 @@ __global__ __launch_bounds__(64) void k_bsf_reduce(int nk, const BoxDev *__restr
 // consecutive n_z at fixed (n_x, n_y) (runs[r] = (n_x, n_y, first n_z, first
 // k), runs[nruns].w = nk; krun[k] = run of k); the phase of bead l is
 // e^{i 2 pi n.s} = ex[n_x] ey[n_y] ez[n_z] from its wrap tables (negative
-// components conjugate), ex ey once per run.  Slices are combined in
+// components conjugate) at the slice's first wave vector of a run, then
+// advanced by e^{i 2 pi s_z} per step in n_z.  Slices are combined in
 // ascending order.  STAGE: the box's T_k are copied to LDS (else read from
 // global memory).  Every global load of the prologue (partial slots, tables,
 // T_k) is issued before the first wait (the table pointers are not
@@ -477,6 +478,7 @@ __global__ __launch_bounds__(64) void k_bsf_reduce(int nk, const BoxDev *__restr
 constexpr int EPI_SLOTS = 8;    // partial slots per slice held in registers
 constexpr int EPI_TAB = 6;      // table entries (double2) per thread and round
 constexpr int EPI_TK = 8;       // T_k entries (double2) per thread and round
+constexpr int BEPI_KU = 2;      // wave vectors per pass of the back-projection loop
 
 template <int TBB, int M, bool STAGE>
 __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns,
@@ -565,6 +567,7 @@ __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns
     const double *tks = STAGE ? stk : tkb;
     if (live) {
         const double2 *tx = tab + l, *ty = tab + nm1 * TBB + l, *tz = tab + 2 * nm1 * TBB + l;
+        const double2 ez1 = nm1 > 1 ? tz[TBB] : make_double2(1.0, 0.0);   // e^{i 2 pi s_z}
         int k = klo;
         for (int r = r0; k < khi; ++r) {
             const int4 R = srun[r];
@@ -573,17 +576,44 @@ __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns
             double2 ey = ty[(R.y < 0 ? -R.y : R.y) * TBB];
             if (R.y < 0) ey.y = -ey.y;
             const double xr = ex.x * ey.x - ex.y * ey.y, xi = ex.x * ey.y + ex.y * ey.x;
+            // the phase at the slice's first wave vector of this run from the
+            // tables, then one factor e^{i 2 pi s_z} per step in n_z
+            const int nz0 = R.z + (k - R.w);
+            double2 ez = tz[(nz0 < 0 ? -nz0 : nz0) * TBB];
+            if (nz0 < 0) ez.y = -ez.y;
+            double cs = xr * ez.x - xi * ez.y, sn = xr * ez.y + xi * ez.x;
+            // BEPI_KU wave vectors per pass with their T_k reads issued
+            // together, then the rest one at a time
+            for (; k + BEPI_KU <= kend; k += BEPI_KU) {
+                double tt[BEPI_KU][M][6];
+#pragma unroll
+                for (int q = 0; q < BEPI_KU; ++q)
+#pragma unroll
+                    for (int j = 0; j < M; ++j)
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) tt[q][j][c] = tks[((size_t)j * nk + k + q) * 6 + c];
+#pragma unroll
+                for (int q = 0; q < BEPI_KU; ++q) {
+#pragma unroll
+                    for (int j = 0; j < M; ++j)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            y[j][c] = fma(sn, tt[q][j][3 + c], fma(cs, tt[q][j][c], y[j][c]));
+                    const double c2 = cs * ez1.x - sn * ez1.y;
+                    sn = cs * ez1.y + sn * ez1.x;
+                    cs = c2;
+                }
+            }
             for (; k < kend; ++k) {
-                const int nz = R.z + (k - R.w);
-                double2 ez = tz[(nz < 0 ? -nz : nz) * TBB];
-                if (nz < 0) ez.y = -ez.y;
-                const double cs = xr * ez.x - xi * ez.y, sn = xr * ez.y + xi * ez.x;
 #pragma unroll
                 for (int j = 0; j < M; ++j) {
                     const double *tt = tks + ((size_t)j * nk + k) * 6;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) y[j][c] += cs * tt[c] + sn * tt[3 + c];
+                    for (int c = 0; c < 3; ++c) y[j][c] = fma(sn, tt[3 + c], fma(cs, tt[c], y[j][c]));
                 }
+                const double c2 = cs * ez1.x - sn * ez1.y;
+                sn = cs * ez1.y + sn * ez1.x;
+                cs = c2;
             }
         }
     }
