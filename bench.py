@@ -54,9 +54,9 @@ TRAFFIC_BLOCK = {"src_sha256": "58cbb4f9487cd3a8b60da89666800f48465459afbc6e0bf4
                                       "bf16": 111239578 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "e88eeeb4264571a41bd407e09d2888a931cc67dbbdd4d8bd0720cbdb5e5ad223",
+TRAFFIC_BATCH = {"src_sha256": "9406c9992841a7c6f06f22bf9d850d46559e14c9a2450d9e22aab93c52df9e6a",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4965848986}
+                 "bytes_per_launch": 4965860147}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 TOL_EF = 1e-2     # E_f tolerance of the headline's adaptive order
