@@ -164,8 +164,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
     const bool offd = I != J;
     // BF16 rows are small: all four of a lane's rows are loaded before any
     // arithmetic (more bytes in flight per wave; 34.1 against 37.4 us at
-    // N = 4000); FP64 and FP32 rows are loaded one at a time (hoisting them
-    // costs occupancy: FP32 46.9 against 43.8 us)
+    // N = 4000).  FP64 and FP32 rows of one-vector products are loaded one
+    // row ahead, each while the previous one is used (FP64 at N = 4000: 67.2
+    // against 69.2 us, at two waves per SIMD instead of three); with more
+    // vectors one at a time (hoisting them costs occupancy: FP32 46.9
+    // against 43.8 us)
     typename P6<T>::raw_t rw[TB / 16][6];
     if constexpr (P6<T>::hoist) {
 #pragma unroll
@@ -174,15 +177,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
             for (int c = 0; c < 6; ++c)
                 rw[it][c] = P6<T>::template raw<CACHED>(
                     tile + (size_t)(16 * it + 4 * w + g) * 6 * TB + c * TB, q);
+    } else if constexpr (M == 1) {   // the first row; the loop loads the next
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            rw[0][c] = P6<T>::template raw<CACHED>(tile + (size_t)(4 * w + g) * 6 * TB + c * TB, q);
     }
 #pragma unroll
     for (int it = 0; it < TB / 16; ++it) {
         const int i = 16 * it + 4 * w + g;
-        const T *row = tile + (size_t)i * 6 * TB;
         double b[6][4];
-        if constexpr (!P6<T>::hoist) {
+        if constexpr (!P6<T>::hoist && M == 1) {
+            if (it + 1 < TB / 16) {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) rw[it][c] = P6<T>::template raw<CACHED>(row + c * TB, q);
+                for (int c = 0; c < 6; ++c)
+                    rw[it + 1][c] = P6<T>::template raw<CACHED>(
+                        tile + (size_t)(i + 16) * 6 * TB + c * TB, q);
+            }
+            // compiler-only barrier: keeps the next row's loads ahead of this
+            // row's arithmetic
+            __asm__ volatile("" ::: "memory");
+        } else if constexpr (!P6<T>::hoist) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+                rw[it][c] = P6<T>::template raw<CACHED>(tile + (size_t)i * 6 * TB + c * TB, q);
         }
 #pragma unroll
         for (int c = 0; c < 6; ++c) P6<T>::cvt(rw[it][c], b[c]);
