@@ -164,12 +164,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
     const bool offd = I != J;
     // BF16 rows are small: all four of a lane's rows are loaded before any
     // arithmetic (more bytes in flight per wave; 34.1 against 37.4 us at
-    // N = 4000).  FP64 and FP32 rows of one-vector products are loaded one
-    // row ahead, each while the previous one is used (FP64 at N = 4000: 67.2
-    // against 69.2 us, at two waves per SIMD instead of three); with more
-    // vectors one at a time (hoisting them costs occupancy: FP32 46.9
-    // against 43.8 us)
+    // N = 4000).  FP64 rows of one-vector products are loaded one row
+    // ahead, each while the previous one is used (67.2 against 69.2 us at
+    // N = 4000, at two waves per SIMD instead of three); FP32 rows and the
+    // rows of several vectors one at a time (hoisting them costs occupancy:
+    // FP32 46.9 against 43.8 us)
     typename P6<T>::raw_t rw[TB / 16][6];
+    constexpr bool PF = !P6<T>::hoist && M == 1 && sizeof(T) == 8;   // rows one ahead
     if constexpr (P6<T>::hoist) {
 #pragma unroll
         for (int it = 0; it < TB / 16; ++it)
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
             for (int c = 0; c < 6; ++c)
                 rw[it][c] = P6<T>::template raw<CACHED>(
                     tile + (size_t)(16 * it + 4 * w + g) * 6 * TB + c * TB, q);
-    } else if constexpr (M == 1) {   // the first row; the loop loads the next
+    } else if constexpr (PF) {   // the first row; the loop loads the next
 #pragma unroll
         for (int c = 0; c < 6; ++c)
             rw[0][c] = P6<T>::template raw<CACHED>(tile + (size_t)(4 * w + g) * 6 * TB + c * TB, q);
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
     for (int it = 0; it < TB / 16; ++it) {
         const int i = 16 * it + 4 * w + g;
         double b[6][4];
-        if constexpr (!P6<T>::hoist && M == 1) {
+        if constexpr (PF) {
             if (it + 1 < TB / 16) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c)
