@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "1a61082e1a2133396411b69f66bb30ab0e066c9bf4b6da2e36fc0571f0920d38",
+TRAFFIC = {"src_sha256": "537a17b3be6db0294da9463782163801d08896eacf87d3586b3e58ca3819986c",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 407715533}
+           "bytes_per_launch": 407634944}
 # The matrix-core tile kernel (k_block_tiles) of a 16-vector product: tile and
 # vector reads plus the per-tile FP64/FP32 partial sums it writes.
 TRAFFIC_BLOCK = {"src_sha256": "58cbb4f9487cd3a8b60da89666800f48465459afbc6e0bf433161839ac58d974",
