@@ -1009,9 +1009,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_symv6<double,1> (packed symmetric tile product, FP64, m=1)",
-                     "memory": "effective bandwidth: the 384 MB tile array is read with "
-                               "allocating loads, the tile order reversed on every other launch, "
-                               "so part of it comes from the 256 MB Infinity Cache",
+                     "memory": "the 396 MB stored tile array is streamed from HBM with "
+                               "non-temporal loads (larger than the 256 MB Infinity Cache)",
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_us": sym["avg_us"], "launches": sym["launches"]},
         "step_configurations": configs,

@@ -272,12 +272,11 @@ static void symv_launch(const Ctx &c, const T *tiles, const double *v, int j0, h
     const int sfr = sizeof(T) == 8 ? (nsf + c.ntiles) / nsf : 1;
     const size_t lds = symv_lds<T, M>(c);
     // Allocating loads, with the tile order reversed on every other launch,
-    // for arrays that fit the Infinity Cache and, in one-vector products, for
-    // arrays up to TILE_ZIGZAG_BYTES (each product then starts on the tiles
-    // the previous one left in the cache); otherwise non-temporal loads in
+    // for arrays that fit the Infinity Cache (each product then starts on the
+    // tiles the previous one read last); otherwise non-temporal loads in
     // stored order, which keep the stream from evicting the rest.
     const size_t bytes = (size_t)c.ntiles * TILE6 * sizeof(T);
-    const bool cached = bytes <= TILE_CACHE_BYTES || (M == 1 && bytes <= TILE_ZIGZAG_BYTES);
+    const bool cached = bytes <= TILE_CACHE_BYTES;
     const int flip = cached ? (int)(c.symv_calls++ & 1u) : 0;
     // when profiled, the dispatch itself records the start and end events,
     // so that they time the kernel alone (null events: a plain launch)

@@ -32,15 +32,12 @@ constexpr int TILE6 = 6 * TB * TB;   // packed FP64 tile: 6 planes per bead row
 // Tile arrays up to TILE_CACHE_BYTES are read with allocating loads and stay
 // in the 256 MB Infinity Cache from one product to the next (measured at
 // N = 4000: FP32 tiles, 192 MB, 44.1 -> 39.2 us; BF16, 96 MB, 33.9 -> 30.6
-// us).  One-vector products also read arrays up to TILE_ZIGZAG_BYTES with
-// allocating loads, walking the tiles in reverse order on every other
-// launch, so that the tiles one product read last (those still in the
-// cache) are the first the next one reads (FP64 tiles at N = 4000, 384 MB:
-// 70.5 -> 67.6 us).  Products of 2-4 vectors on such arrays lose by it (87.5
-// -> 103.4 us for three vectors) and, like every larger array, stream the
-// tiles with non-temporal loads in stored order.
+// us).  Larger arrays stream with non-temporal loads in stored order, which
+// keeps the rest of the product's data (partials, vectors, T_k) cached: for
+// the FP64 tiles at N = 4000 (384 MB) allocating loads with the tile order
+// reversed on every other launch read part of the array from the cache, but
+// the step runs faster without them (254.0 against 251.5 steps/s).
 constexpr size_t TILE_CACHE_BYTES = (size_t)200 << 20;
-constexpr size_t TILE_ZIGZAG_BYTES = (size_t)384 << 20;
 constexpr int NSER = 20;        // terms of the small-r series of S(r)
 constexpr double XSER = 0.75;   // use the series for alpha*r below this
 constexpr int MAX_RHS = 16;

@@ -7,8 +7,8 @@ direct cosines) is formed once per module.  Every launch configuration the
 benchmark times is compared with it:
   * one whole FP64 bd_step -- springs + excluded volume, the folded product
     of [F, U+, dW] (the three-vector tile product with non-temporal loads),
-    the paper's bound rule, N_Ch = 30 (28 one-vector products, allocating
-    loads, alternating tile order), E_f and the Euler update -- to rel 1e-12;
+    the paper's bound rule, N_Ch = 30 (28 one-vector products, non-temporal
+    loads), E_f and the Euler update -- to rel 1e-12;
   * rpy_apply with 2, 3 and 4 vectors (the non-temporal tile products);
   * bd_step with the Chebyshev products in FP32 and in BF16, within the
     bound propagated from the rounding of the stored real-space part.
