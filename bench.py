@@ -42,21 +42,21 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "537a17b3be6db0294da9463782163801d08896eacf87d3586b3e58ca3819986c",
+TRAFFIC = {"src_sha256": "bec65d615d4ad79d90288e9ec56715d6ab17280957f6beae70a2c8dba4d9c501",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 407634944}
+           "bytes_per_launch": 404570010}
 # The matrix-core tile kernel (k_block_tiles) of a 16-vector product: tile and
 # vector reads plus the per-tile FP64/FP32 partial sums it writes.
-TRAFFIC_BLOCK = {"src_sha256": "58cbb4f9487cd3a8b60da89666800f48465459afbc6e0bf433161839ac58d974",
+TRAFFIC_BLOCK = {"src_sha256": "710dc0c12315010bb07e8029c50b40f138f72e6fcf9a5e7a522afe482b149e78",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f64": 420254106 + 97542144,
-                                      "f32": 215976550 + 48771789,
-                                      "bf16": 111239578 + 48771072}}
+                 "bytes_per_launch": {"f64": 420303462 + 97542144,
+                                      "f32": 215974093 + 48771789,
+                                      "bf16": 111228928 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "9406c9992841a7c6f06f22bf9d850d46559e14c9a2450d9e22aab93c52df9e6a",
+TRAFFIC_BATCH = {"src_sha256": "dbbba596e85311aa884e072fb0b34f1800ecb41a2cf29cdf501c1cbd4efeacf4",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4965860147}
+                 "bytes_per_launch": 4965859304}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 TOL_EF = 1e-2     # E_f tolerance of the headline's adaptive order
