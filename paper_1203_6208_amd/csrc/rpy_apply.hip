@@ -136,13 +136,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
     double(*scol)[M][TS] = reinterpret_cast<double(*)[M][TS]>(smem + M * TS);  // [4][M][TS]
     const int ord = bid - min(nsf, bid / sfr + 1);
     const int t = flip ? ntl - 1 - ord : ord;
-    const int2 ij = tile_ij[t];
-    const int I = ij.x, J = ij.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane >> 4, q = lane & 15;
-    for (int e = threadIdx.x; e < M * TS; e += blockDim.x) {
-        const int j = e / TS, r = e % TS, row = I * TS + r;
-        sx[j][r] = row < n3 ? v[(size_t)(j0 + j) * n3 + row] : 0.0;
+    // BF16 rows are small: all four of a lane's rows are loaded before any
+    // arithmetic (more bytes in flight per wave; 34.1 against 37.4 us at
+    // N = 4000).  FP64 rows of one-vector products are loaded one row
+    // ahead, each while the previous one is used (67.2 against 69.2 us at
+    // N = 4000, at two waves per SIMD instead of three); FP32 rows and the
+    // rows of several vectors one at a time (hoisting them costs occupancy:
+    // FP32 46.9 against 43.8 us).  The tile's address needs only t, so the
+    // first FP64 or FP32 row is loaded before the vector loads, which wait
+    // on the tile's (I, J) (FP32 one-vector steps 577 -> 582 per second;
+    // BF16 rows all issued there lose: 32.2 -> 33.1 us).
+    const T *tile = tiles + (size_t)t * TILE6;
+    typename P6<T>::raw_t rw[TB / 16][6];
+    constexpr bool PF = !P6<T>::hoist && M == 1 && sizeof(T) == 8;   // rows one ahead
+    if constexpr (!P6<T>::hoist) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            rw[0][c] = P6<T>::template raw<CACHED>(tile + (size_t)(4 * w + g) * 6 * TB + c * TB, q);
+    }
+    const int2 ij = tile_ij[t];
+    const int I = ij.x, J = ij.y;
+    // the vector loads of x_I (for LDS) and x_J (registers) all go out
+    // before the first LDS store, which waits for them (256 threads)
+    constexpr int NSX = (M * TS + 255) / 256;
+    double sxv[NSX];
+#pragma unroll
+    for (int u = 0; u < NSX; ++u) {
+        const int e = threadIdx.x + 256 * u, j = e / TS, row = I * TS + e % TS;
+        sxv[u] = e < M * TS && row < n3 ? v[(size_t)(j0 + j) * n3 + row] : 0.0;
     }
     double xj[M][4][3];
 #pragma unroll
@@ -154,23 +177,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
                 const int col = J * TS + 3 * P6<T>::col(q, e) + c;
                 xj[j][e][c] = col < n3 ? v[(size_t)(j0 + j) * n3 + col] : 0.0;
             }
+#pragma unroll
+    for (int u = 0; u < NSX; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        if (e < M * TS) sx[e / TS][e % TS] = sxv[u];
+    }
     double cacc[M][4][3];
 #pragma unroll
     for (int j = 0; j < M; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e) cacc[j][e][0] = cacc[j][e][1] = cacc[j][e][2] = 0.0;
     __syncthreads();
-    const T *tile = tiles + (size_t)t * TILE6;
     const bool offd = I != J;
-    // BF16 rows are small: all four of a lane's rows are loaded before any
-    // arithmetic (more bytes in flight per wave; 34.1 against 37.4 us at
-    // N = 4000).  FP64 rows of one-vector products are loaded one row
-    // ahead, each while the previous one is used (67.2 against 69.2 us at
-    // N = 4000, at two waves per SIMD instead of three); FP32 rows and the
-    // rows of several vectors one at a time (hoisting them costs occupancy:
-    // FP32 46.9 against 43.8 us)
-    typename P6<T>::raw_t rw[TB / 16][6];
-    constexpr bool PF = !P6<T>::hoist && M == 1 && sizeof(T) == 8;   // rows one ahead
     if constexpr (P6<T>::hoist) {
 #pragma unroll
         for (int it = 0; it < TB / 16; ++it)
@@ -178,10 +196,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
             for (int c = 0; c < 6; ++c)
                 rw[it][c] = P6<T>::template raw<CACHED>(
                     tile + (size_t)(16 * it + 4 * w + g) * 6 * TB + c * TB, q);
-    } else if constexpr (PF) {   // the first row; the loop loads the next
-#pragma unroll
-        for (int c = 0; c < 6; ++c)
-            rw[0][c] = P6<T>::template raw<CACHED>(tile + (size_t)(4 * w + g) * 6 * TB + c * TB, q);
     }
 #pragma unroll
     for (int it = 0; it < TB / 16; ++it) {
@@ -198,9 +212,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
             // row's arithmetic
             __asm__ volatile("" ::: "memory");
         } else if constexpr (!P6<T>::hoist) {
+            if (it > 0) {
 #pragma unroll
-            for (int c = 0; c < 6; ++c)
-                rw[it][c] = P6<T>::template raw<CACHED>(tile + (size_t)i * 6 * TB + c * TB, q);
+                for (int c = 0; c < 6; ++c)
+                    rw[it][c] = P6<T>::template raw<CACHED>(tile + (size_t)i * 6 * TB + c * TB, q);
+            }
         }
 #pragma unroll
         for (int c = 0; c < 6; ++c) P6<T>::cvt(rw[it][c], b[c]);

@@ -207,60 +207,67 @@ template <bool CACHED, typename V> __device__ inline V tload(const V *p)
 template <typename T, int TBB> struct BLd;
 template <> struct BLd<double, 64> {
     static constexpr int NE = 4;
+    struct raw_t {
+        d2v u, v;
+    };
     __device__ static int col(int q, int e) { return 32 * (e >> 1) + 2 * q + (e & 1); }
-    template <bool CACHED> __device__ static void load(const double *row, int q, double a[NE])
+    template <bool CACHED> __device__ static raw_t raw(const double *row, int q)
     {
-        const d2v u = tload<CACHED>(reinterpret_cast<const d2v *>(row + 2 * q));
-        const d2v v = tload<CACHED>(reinterpret_cast<const d2v *>(row + 32 + 2 * q));
-        a[0] = u.x;
-        a[1] = u.y;
-        a[2] = v.x;
-        a[3] = v.y;
+        return {tload<CACHED>(reinterpret_cast<const d2v *>(row + 2 * q)),
+                tload<CACHED>(reinterpret_cast<const d2v *>(row + 32 + 2 * q))};
+    }
+    __device__ static double at(const raw_t &r, int e)
+    {
+        return e == 0 ? r.u.x : e == 1 ? r.u.y : e == 2 ? r.v.x : r.v.y;
     }
 };
 template <> struct BLd<double, 32> {
     static constexpr int NE = 2;
+    typedef d2v raw_t;
     __device__ static int col(int q, int e) { return 2 * q + e; }
-    template <bool CACHED> __device__ static void load(const double *row, int q, double a[NE])
+    template <bool CACHED> __device__ static raw_t raw(const double *row, int q)
     {
-        const d2v u = tload<CACHED>(reinterpret_cast<const d2v *>(row + 2 * q));
-        a[0] = u.x;
-        a[1] = u.y;
+        return tload<CACHED>(reinterpret_cast<const d2v *>(row + 2 * q));
     }
+    __device__ static double at(const raw_t &u, int e) { return e == 0 ? u.x : u.y; }
 };
 template <> struct BLd<float, 64> {
     static constexpr int NE = 4;
+    typedef f4v raw_t;
     __device__ static int col(int q, int e) { return 4 * q + e; }
-    template <bool CACHED> __device__ static void load(const float *row, int q, double a[NE])
+    template <bool CACHED> __device__ static raw_t raw(const float *row, int q)
     {
-        const f4v u = tload<CACHED>(reinterpret_cast<const f4v *>(row + 4 * q));
-        a[0] = u.x;
-        a[1] = u.y;
-        a[2] = u.z;
-        a[3] = u.w;
+        return tload<CACHED>(reinterpret_cast<const f4v *>(row + 4 * q));
     }
+    __device__ static double at(const raw_t &u, int e) { return u[e]; }
 };
 template <> struct BLd<float, 32> {
     static constexpr int NE = 2;
+    typedef f2v raw_t;
     __device__ static int col(int q, int e) { return 2 * q + e; }
-    template <bool CACHED> __device__ static void load(const float *row, int q, double a[NE])
+    template <bool CACHED> __device__ static raw_t raw(const float *row, int q)
     {
-        const f2v u = tload<CACHED>(reinterpret_cast<const f2v *>(row + 2 * q));
-        a[0] = u.x;
-        a[1] = u.y;
+        return tload<CACHED>(reinterpret_cast<const f2v *>(row + 2 * q));
     }
+    __device__ static double at(const raw_t &u, int e) { return u[e]; }
 };
 
+// Structure-factor workgroups per bead tile: each stages the tile's phase
+// tables once, so one workgroup walking all wave vectors reads them once
+// (256 FP32 boxes: 6735 -> 6876 box-steps per second against one per block
+// of 256 wave vectors; 6628 with two).
+constexpr int BSF_SPLIT = 1;
+
 // nsf structure-factor workgroups (spread over the launch, see below): the
-// partials of one bead tile (chunk) for a block of wave vectors, one thread
-// per k:
+// partials of one bead tile (chunk) for the wave vectors k = kb 256 + lane,
+// stepping by nsplit 256 (kb < nsplit), one thread per k at a time:
 //   sfpart[chunk][6 j + c][k] = sum over the chunk's real beads of
 //   {cos, sin}(k.r) v_c.
 // The other workgroups: one stored packed tile each, as the single-box FP64
 // product (4 waves; a 16-lane row group per bead row; each lane owns the
 // NE bead columns of BLd; FP64 accumulation for both tile types).
 template <int TBB, typename T, int M, bool CACHED>
-__global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb, int nk, int nm1,
+__global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nsplit, int nk, int nm1,
                                                const int *__restrict__ tile_box,
                                                const BoxDev *__restrict__ boxes,
                                                const int4 *__restrict__ stor,
@@ -282,7 +289,7 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb
     const int nsf_before = min(nsf, bid / sfr + 1);
     if (bid % sfr == 0 && bid / sfr < nsf) {
         const int sfb = bid / sfr;
-        const int chunk = sfb / nkb, kb = sfb % nkb;
+        const int chunk = sfb / nsplit, kb = sfb % nsplit;
         const BoxDev &d = boxes[tile_box[chunk]];
         const int loc0 = (chunk - d.tile0) * TBB;
         const int nb = max(0, min(TBB, d.N - loc0));
@@ -295,51 +302,69 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb
             sv[q] = v[(size_t)j * G3 + 3 * (g0 + bl) + c];
         }
         __syncthreads();
-        const int k = kb * blockDim.x + threadIdx.x;
-        if (k >= nk) return;
-        const KVec kv = kvec[k];
-        double acc[M][6];
-#pragma unroll
-        for (int j = 0; j < M; ++j)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) acc[j][c] = 0.0;
-        for (int bl = 0; bl < nb; ++bl) {
-            const double2 *tab = stab + bl * 3 * nm1;
-            double2 ex = tab[kv.nx];
-            double2 ey = tab[nm1 + (kv.ny < 0 ? -kv.ny : kv.ny)];
-            double2 ez = tab[2 * nm1 + (kv.nz < 0 ? -kv.nz : kv.nz)];
-            if (kv.ny < 0) ey.y = -ey.y;
-            if (kv.nz < 0) ez.y = -ez.y;
-            const double xr = ex.x * ey.x - ex.y * ey.y, xi = ex.x * ey.y + ex.y * ey.x;
-            const double cs = xr * ez.x - xi * ez.y, sn = xr * ez.y + xi * ez.x;
+        for (int k = kb * blockDim.x + threadIdx.x; k < nk; k += nsplit * blockDim.x) {
+            const KVec kv = kvec[k];
+            double acc[M][6];
 #pragma unroll
             for (int j = 0; j < M; ++j)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double x = sv[bl * 3 * M + 3 * j + c];
-                    acc[j][c] += cs * x;
-                    acc[j][3 + c] += sn * x;
-                }
+                for (int c = 0; c < 6; ++c) acc[j][c] = 0.0;
+            for (int bl = 0; bl < nb; ++bl) {
+                const double2 *tab = stab + bl * 3 * nm1;
+                double2 ex = tab[kv.nx];
+                double2 ey = tab[nm1 + (kv.ny < 0 ? -kv.ny : kv.ny)];
+                double2 ez = tab[2 * nm1 + (kv.nz < 0 ? -kv.nz : kv.nz)];
+                if (kv.ny < 0) ey.y = -ey.y;
+                if (kv.nz < 0) ez.y = -ez.y;
+                const double xr = ex.x * ey.x - ex.y * ey.y, xi = ex.x * ey.y + ex.y * ey.x;
+                const double cs = xr * ez.x - xi * ez.y, sn = xr * ez.y + xi * ez.x;
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double x = sv[bl * 3 * M + 3 * j + c];
+                        acc[j][c] += cs * x;
+                        acc[j][3 + c] += sn * x;
+                    }
+            }
+            double *o = sfpart + (size_t)chunk * 6 * BRC * nk + k;
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) o[(size_t)(6 * j + c) * nk] = acc[j][c];
         }
-        double *o = sfpart + (size_t)chunk * 6 * BRC * nk + k;
-#pragma unroll
-        for (int j = 0; j < M; ++j)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) o[(size_t)(6 * j + c) * nk] = acc[j][c];
         return;
     }
     double(*sx)[TSB] = reinterpret_cast<double(*)[TSB]>(smem);                    // [M][TSB]
     double(*scol)[M][TSB] = reinterpret_cast<double(*)[M][TSB]>(smem + M * TSB);  // [4][M][TSB]
     const int t = bid - nsf_before;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, q = lane & 15;
+    // The tile's address needs only t: the first bead row's loads go out
+    // before the vector loads, which wait on the tile table and the box
+    // record.  With one vector the loop then loads each next row while the
+    // current one is used (three waves per SIMD instead of four; 256 FP32
+    // boxes: 6531 -> 6655 box-steps per second).  Two tiles per workgroup,
+    // the second one's first row loaded during the first one's column
+    // combine, lost (5899, and 6263 without that load).
+    const T *tile = tiles + (size_t)t * 6 * TBB * TBB;
+    constexpr bool PF = M == 1;
+    typename BLd<T, TBB>::raw_t rw[TBB / 16][6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        rw[0][c] = BLd<T, TBB>::template raw<CACHED>(tile + (size_t)(4 * w + g) * 6 * TBB + c * TBB, q);
     const int4 e = stor[t];
     const BoxDev &d = boxes[e.x];
     const int I = e.y, J = e.z;
     const size_t rowI = 3 * (size_t)(d.tile0 + I) * TBB, rowJ = 3 * (size_t)(d.tile0 + J) * TBB;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int g = lane >> 4, q = lane & 15;
-    for (int z = threadIdx.x; z < M * TSB; z += blockDim.x) {
-        const int j = z / TSB, r = z % TSB;
-        sx[j][r] = v[(size_t)j * G3 + rowI + r];
+    // the vector loads of x_I (for LDS) and x_J (registers) all go out
+    // before the first LDS store, which waits for them (256 threads)
+    constexpr int NSX = (M * TSB + 255) / 256;
+    double sxv[NSX];
+#pragma unroll
+    for (int u = 0; u < NSX; ++u) {
+        const int z = threadIdx.x + 256 * u;
+        sxv[u] = z < M * TSB ? v[(size_t)(z / TSB) * G3 + rowI + z % TSB] : 0.0;
     }
     double xj[M][NE][3];
 #pragma unroll
@@ -349,31 +374,67 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb
 #pragma unroll
             for (int x = 0; x < 3; ++x)
                 xj[j][c][x] = v[(size_t)j * G3 + rowJ + 3 * BLd<T, TBB>::col(q, c) + x];
+#pragma unroll
+    for (int u = 0; u < NSX; ++u) {
+        const int z = threadIdx.x + 256 * u;
+        if (z < M * TSB) sx[z / TSB][z % TSB] = sxv[u];
+    }
     double cacc[M][NE][3];
 #pragma unroll
     for (int j = 0; j < M; ++j)
 #pragma unroll
         for (int c = 0; c < NE; ++c) cacc[j][c][0] = cacc[j][c][1] = cacc[j][c][2] = 0.0;
     __syncthreads();
-    const T *tile = tiles + (size_t)t * 6 * TBB * TBB;
     const bool offd = I != J;
 #pragma unroll
     for (int it = 0; it < TBB / 16; ++it) {
         const int i = 16 * it + 4 * w + g;
-        const T *row = tile + (size_t)i * 6 * TBB;
-        double b[6][NE];
+        if constexpr (PF) {
+            if (it + 1 < TBB / 16) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) BLd<T, TBB>::template load<CACHED>(row + c * TBB, q, b[c]);
+                for (int c = 0; c < 6; ++c)
+                    rw[it + 1][c] = BLd<T, TBB>::template raw<CACHED>(
+                        tile + (size_t)(i + 16) * 6 * TBB + c * TBB, q);
+            }
+            // compiler-only barrier: keeps the next row's loads ahead of this
+            // row's arithmetic
+            __asm__ volatile("" ::: "memory");
+        } else if (it > 0) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+                rw[it][c] = BLd<T, TBB>::template raw<CACHED>(tile + (size_t)i * 6 * TBB + c * TBB, q);
+        }
+        // one bead column at a time: its six entries are widened where they
+        // are used (fewer live registers than widening the whole row)
+        double r[M][3], y[M][3];
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                r[j][x] = 0.0;
+                y[j][x] = sx[j][3 * i + x];
+            }
+#pragma unroll
+        for (int c = 0; c < NE; ++c) {
+            double b[6];
+#pragma unroll
+            for (int p = 0; p < 6; ++p) b[p] = BLd<T, TBB>::at(rw[it][p], c);
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const double x0 = xj[j][c][0], x1 = xj[j][c][1], x2 = xj[j][c][2];
+                r[j][0] += b[0] * x0 + b[1] * x1 + b[2] * x2;
+                r[j][1] += b[1] * x0 + b[3] * x1 + b[4] * x2;
+                r[j][2] += b[2] * x0 + b[4] * x1 + b[5] * x2;
+                if (offd) {
+                    cacc[j][c][0] += b[0] * y[j][0] + b[1] * y[j][1] + b[2] * y[j][2];
+                    cacc[j][c][1] += b[1] * y[j][0] + b[3] * y[j][1] + b[4] * y[j][2];
+                    cacc[j][c][2] += b[2] * y[j][0] + b[4] * y[j][1] + b[5] * y[j][2];
+                }
+            }
+        }
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-#pragma unroll
-            for (int c = 0; c < NE; ++c) {
-                const double x0 = xj[j][c][0], x1 = xj[j][c][1], x2 = xj[j][c][2];
-                r0 += b[0][c] * x0 + b[1][c] * x1 + b[2][c] * x2;
-                r1 += b[1][c] * x0 + b[3][c] * x1 + b[4][c] * x2;
-                r2 += b[2][c] * x0 + b[4][c] * x1 + b[5][c] * x2;
-            }
+            double r0 = r[j][0], r1 = r[j][1], r2 = r[j][2];
 #pragma unroll
             for (int o = 8; o >= 1; o >>= 1) {
                 r0 += __shfl_xor(r0, o, 16);
@@ -382,15 +443,6 @@ __global__ __launch_bounds__(256) void k_bsymv(int G3, int nsf, int sfr, int nkb
             }
             if (q < 3)
                 part[((size_t)J * BRC + j) * G3 + rowI + 3 * i + q] = q == 0 ? r0 : q == 1 ? r1 : r2;
-            if (offd) {
-                const double y0 = sx[j][3 * i], y1 = sx[j][3 * i + 1], y2 = sx[j][3 * i + 2];
-#pragma unroll
-                for (int c = 0; c < NE; ++c) {
-                    cacc[j][c][0] += b[0][c] * y0 + b[1][c] * y1 + b[2][c] * y2;
-                    cacc[j][c][1] += b[1][c] * y0 + b[3][c] * y1 + b[4][c] * y2;
-                    cacc[j][c][2] += b[2][c] * y0 + b[4][c] * y1 + b[5][c] * y2;
-                }
-            }
         }
     }
     if (!offd) return;
@@ -1068,8 +1120,8 @@ template <int TBB> static void bwrap_build(rpy_batch *b, const double *pos, hipS
 template <int TBB, typename T, int M>
 static void bsymv(rpy_batch *b, const T *tiles, const double *v, hipStream_t s)
 {
-    const int nm1 = b->nmax + 1, nkb = (b->nk + 255) / 256;
-    const int nsf = b->ntb * nkb;
+    const int nm1 = b->nmax + 1, nsplit = BSF_SPLIT < (b->nk + 255) / 256 ? BSF_SPLIT : (b->nk + 255) / 256;
+    const int nsf = b->ntb * nsplit;
     const size_t sm_sf = (size_t)(2 * TBB * 3 * nm1 + TBB * 3 * M) * sizeof(double);
     const size_t sm_t = (size_t)5 * M * 3 * TBB * sizeof(double);
     const int total = nsf + b->nstor;
@@ -1078,11 +1130,11 @@ static void bsymv(rpy_batch *b, const T *tiles, const double *v, hipStream_t s)
     const size_t lds = sm_sf > sm_t ? sm_sf : sm_t;
     if (b->tile_cached)
         hipLaunchKernelGGL((k_bsymv<TBB, T, M, true>), dim3(total), dim3(256), lds, s, 3 * b->G,
-                           nsf, sfr, nkb, b->nk, nm1, b->tile_box, b->boxes, b->stor, b->kvec,
+                           nsf, sfr, nsplit, b->nk, nm1, b->tile_box, b->boxes, b->stor, b->kvec,
                            b->etab, b->sfpart, tiles, v, b->part);
     else
         hipLaunchKernelGGL((k_bsymv<TBB, T, M, false>), dim3(total), dim3(256), lds, s, 3 * b->G,
-                           nsf, sfr, nkb, b->nk, nm1, b->tile_box, b->boxes, b->stor, b->kvec,
+                           nsf, sfr, nsplit, b->nk, nm1, b->tile_box, b->boxes, b->stor, b->kvec,
                            b->etab, b->sfpart, tiles, v, b->part);
 }
 
