@@ -54,9 +54,9 @@ TRAFFIC_BLOCK = {"src_sha256": "710dc0c12315010bb07e8029c50b40f138f72e6fcf9a5e7a
                                       "bf16": 111228928 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "dbbba596e85311aa884e072fb0b34f1800ecb41a2cf29cdf501c1cbd4efeacf4",
+TRAFFIC_BATCH = {"src_sha256": "6a6d0cc5ef43ee5703dd62ff81fe39d036b3d7b0c93991789e0c0285f09a68e8",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4965859304}
+                 "bytes_per_launch": 4845331214}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 TOL_EF = 1e-2     # E_f tolerance of the headline's adaptive order
