@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "d87899498f4cfc485e914318a9de74a63f7b0dcb47561becf8b00238dac43fc6",
+TRAFFIC = {"src_sha256": "38e142e8d04e505fe5c20f27e296ad4dc3e96f37c4ba5638e296a664a112663f",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 404567110}
+           "bytes_per_launch": 404568118}
 # The matrix-core tile kernel (k_block_tiles) of a 16-vector product: tile and
 # vector reads plus the per-tile FP64/FP32 partial sums it writes.
 TRAFFIC_BLOCK = {"src_sha256": "710dc0c12315010bb07e8029c50b40f138f72e6fcf9a5e7a522afe482b149e78",

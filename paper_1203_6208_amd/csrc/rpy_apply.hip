@@ -94,21 +94,30 @@ template <> struct P6<uint16_t> {
 // Product on the packed tiles (6 planes per bead row, tile[t][i][c][j]),
 // FP64, FP32 or BF16 entries, FP64 arithmetic.  nsf workgroups (at the
 // front of the launch or spread through it) compute T_k of v for a few wave
-// vectors each (sf_direct_block); each further workgroup (4 waves) takes one stored tile
-// (I, J), in stored order or, when `flip`, in reverse order (each tile's
-// results go to its own slots, so the order changes no value).  Wave w, row group g (16 lanes), lane q: bead rows
-// i = 16 it + 4 w + g (it = 0..3); lane q owns the bead columns
-// jb(e) = P6<T>::col(q, e), e = 0..3, of every plane.  With B the symmetric
-// 3 x 3 block of (i, j), the row sums of B x_j over the 16 lanes give
-// A_IJ x_J -> part[J][j][rows of I]; for off-diagonal tiles each lane also
-// accumulates B x_i for its columns, and the 4 row groups and 4 waves are
-// combined in a fixed order -> part[I][j][rows of J].  Diagonal tiles hold
-// both (i, j) and (j, i) and take row sums only.
+// vectors each (sf_direct_block); each further workgroup (NW waves) takes
+// one stored tile (I, J), in stored order or, when `flip`, in reverse order
+// (each tile's results go to its own slots, so the order changes no value).
+// Wave w, row group g (16 lanes), lane q: bead rows i = 4 NW it + 4 w + g
+// (it < 16 / NW); lane q owns the bead columns jb(e) = P6<T>::col(q, e),
+// e = 0..3, of every plane.  With B the symmetric 3 x 3 block of (i, j), the
+// row sums of B x_j over the 16 lanes give A_IJ x_J -> part[J][j][rows of I];
+// for off-diagonal tiles each lane also accumulates B x_i for its columns,
+// and the 4 row groups and the NW waves are combined in a fixed order ->
+// part[I][j][rows of J].  Diagonal tiles hold both (i, j) and (j, i) and
+// take row sums only.
 // Four vectors need 274 VGPRs, one wave per SIMD; capped at 256 (two waves,
 // a few spills) the FP64 launch takes 132 us instead of 176 us at N = 4000.
 // Three and four vectors run at two waves per SIMD.
-template <typename T, int M, bool CACHED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 : 1, 8))) void k_symv6(int N, int n3, int n3pad, int rhs_cap, int j0,
+// Waves per tile workgroup: 4, or 2 for BF16 tiles with one vector.  Those
+// short, cache-resident rows are latency-bound: two waves of 32 rows each,
+// every next row loaded while the current one is used, take 28.5 us at
+// N = 4000 against 32.3 us for four waves with all of a lane's rows loaded
+// at once (one wave: 41.6 us, eight: 38.6 us).  FP32 tiles keep four waves
+// (37.6 us; two: 38.1 us).
+template <typename T, int M> constexpr int symv_waves() { return sizeof(T) == 2 && M == 1 ? 2 : 4; }
+
+template <typename T, int M, bool CACHED, int NW = symv_waves<T, M>()>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 : 1, 8))) void k_symv6(int N, int n3, int n3pad, int rhs_cap, int j0,
                                                int nsf, int sfr, int flip, int nk,
                                                double invL,
                                                const KVec *__restrict__ kvec,
@@ -129,29 +138,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
     // larger sfr spreads them through it
     const int bid = blockIdx.x, ntl = (int)gridDim.x - nsf;
     if (bid % sfr == 0 && bid / sfr < nsf) {
-        sf_direct_block<M>(bid / sfr, N, nk, rhs_cap, j0, invL, n3, kvec, kcoef, rt, v, tk, smem);
+        sf_direct_block<M, NW>(bid / sfr, N, nk, rhs_cap, j0, invL, n3, kvec, kcoef, rt, v, tk, smem);
         return;
     }
     double(*sx)[TS] = reinterpret_cast<double(*)[TS]>(smem);                    // [M][TS]
-    double(*scol)[M][TS] = reinterpret_cast<double(*)[M][TS]>(smem + M * TS);  // [4][M][TS]
+    double(*scol)[M][TS] = reinterpret_cast<double(*)[M][TS]>(smem + M * TS);  // [NW][M][TS]
+    constexpr int NT = 64 * NW, RPI = 4 * NW, NIT = TB / RPI;   // threads, rows per pass, passes
+    constexpr bool HOIST = P6<T>::hoist && NW == 4;
     const int ord = bid - min(nsf, bid / sfr + 1);
     const int t = flip ? ntl - 1 - ord : ord;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane >> 4, q = lane & 15;
-    // BF16 rows are small: all four of a lane's rows are loaded before any
-    // arithmetic (more bytes in flight per wave; 34.1 against 37.4 us at
-    // N = 4000).  FP64 rows of one-vector products are loaded one row
-    // ahead, each while the previous one is used (67.2 against 69.2 us at
-    // N = 4000, at two waves per SIMD instead of three); FP32 rows and the
-    // rows of several vectors one at a time (hoisting them costs occupancy:
-    // FP32 46.9 against 43.8 us).  The tile's address needs only t, so the
-    // first FP64 or FP32 row is loaded before the vector loads, which wait
-    // on the tile's (I, J) (FP32 one-vector steps 577 -> 582 per second;
-    // BF16 rows all issued there lose: 32.2 -> 33.1 us).
+    // BF16 rows of several vectors are small: all four of a lane's rows
+    // are loaded before any arithmetic (more bytes in flight per wave;
+    // 34.1 against 37.4 us at N = 4000 for one vector, before it moved to two
+    // waves).  FP64 rows of one-vector products, and the BF16 rows of the
+    // two-wave form, are loaded one row ahead, each while the previous one
+    // is used (FP64: 67.2 against 69.2 us at N = 4000, at two waves per SIMD
+    // instead of three); FP32 rows and the rows of several vectors one at a
+    // time (hoisting them costs occupancy: FP32 46.9 against 43.8 us).  The
+    // tile's address needs only t, so the first row is loaded before the
+    // vector loads, which wait on the tile's (I, J) (FP32 one-vector steps
+    // 577 -> 582 per second; all four hoisted BF16 rows issued there lose:
+    // 32.2 -> 33.1 us).
     const T *tile = tiles + (size_t)t * TILE6;
-    typename P6<T>::raw_t rw[TB / 16][6];
-    constexpr bool PF = !P6<T>::hoist && M == 1 && sizeof(T) == 8;   // rows one ahead
-    if constexpr (!P6<T>::hoist) {
+    typename P6<T>::raw_t rw[NIT][6];
+    constexpr bool PF = !HOIST && M == 1 && (sizeof(T) == 8 || NW < 4);   // rows one ahead
+    if constexpr (!HOIST) {
 #pragma unroll
         for (int c = 0; c < 6; ++c)
             rw[0][c] = P6<T>::template raw<CACHED>(tile + (size_t)(4 * w + g) * 6 * TB + c * TB, q);
@@ -159,12 +172,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
     const int2 ij = tile_ij[t];
     const int I = ij.x, J = ij.y;
     // the vector loads of x_I (for LDS) and x_J (registers) all go out
-    // before the first LDS store, which waits for them (256 threads)
-    constexpr int NSX = (M * TS + 255) / 256;
+    // before the first LDS store, which waits for them
+    constexpr int NSX = (M * TS + NT - 1) / NT;
     double sxv[NSX];
 #pragma unroll
     for (int u = 0; u < NSX; ++u) {
-        const int e = threadIdx.x + 256 * u, j = e / TS, row = I * TS + e % TS;
+        const int e = threadIdx.x + NT * u, j = e / TS, row = I * TS + e % TS;
         sxv[u] = e < M * TS && row < n3 ? v[(size_t)(j0 + j) * n3 + row] : 0.0;
     }
     double xj[M][4][3];
@@ -179,7 +192,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
             }
 #pragma unroll
     for (int u = 0; u < NSX; ++u) {
-        const int e = threadIdx.x + 256 * u;
+        const int e = threadIdx.x + NT * u;
         if (e < M * TS) sx[e / TS][e % TS] = sxv[u];
     }
     double cacc[M][4][3];
@@ -189,29 +202,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
         for (int e = 0; e < 4; ++e) cacc[j][e][0] = cacc[j][e][1] = cacc[j][e][2] = 0.0;
     __syncthreads();
     const bool offd = I != J;
-    if constexpr (P6<T>::hoist) {
+    if constexpr (HOIST) {
 #pragma unroll
-        for (int it = 0; it < TB / 16; ++it)
+        for (int it = 0; it < NIT; ++it)
 #pragma unroll
             for (int c = 0; c < 6; ++c)
                 rw[it][c] = P6<T>::template raw<CACHED>(
-                    tile + (size_t)(16 * it + 4 * w + g) * 6 * TB + c * TB, q);
+                    tile + (size_t)(RPI * it + 4 * w + g) * 6 * TB + c * TB, q);
     }
 #pragma unroll
-    for (int it = 0; it < TB / 16; ++it) {
-        const int i = 16 * it + 4 * w + g;
+    for (int it = 0; it < NIT; ++it) {
+        const int i = RPI * it + 4 * w + g;
         double b[6][4];
         if constexpr (PF) {
-            if (it + 1 < TB / 16) {
+            if (it + 1 < NIT) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c)
                     rw[it + 1][c] = P6<T>::template raw<CACHED>(
-                        tile + (size_t)(i + 16) * 6 * TB + c * TB, q);
+                        tile + (size_t)(i + RPI) * 6 * TB + c * TB, q);
             }
             // compiler-only barrier: keeps the next row's loads ahead of this
             // row's arithmetic
             __asm__ volatile("" ::: "memory");
-        } else if constexpr (!P6<T>::hoist) {
+        } else if constexpr (!HOIST) {
             if (it > 0) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c)
@@ -263,7 +276,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 3 ? 2 
     __syncthreads();
     for (int e = threadIdx.x; e < M * TS; e += blockDim.x) {
         const int j = e / TS, cidx = e % TS;
-        const double s = ((scol[0][j][cidx] + scol[1][j][cidx]) + scol[2][j][cidx]) + scol[3][j][cidx];
+        double s = scol[0][j][cidx];
+#pragma unroll
+        for (int w2 = 1; w2 < NW; ++w2) s += scol[w2][j][cidx];
         part[((size_t)I * rhs_cap + j0 + j) * n3pad + J * TS + cidx] = s;
     }
 }
@@ -272,8 +287,9 @@ template <typename T, int M> static size_t symv_lds(const Ctx &)
 {
     // sx occupies M*TS double slots (whatever A is), then scol[4][M][TS];
     // the structure-factor workgroups use 4 x 6 KPW M doubles
-    const size_t tile = sizeof(double) * M * TS + sizeof(double) * 4 * M * TS;
-    const size_t sf = sizeof(double) * 4 * 6 * sf_kpw<M>() * M;
+    constexpr int NW = symv_waves<T, M>();
+    const size_t tile = sizeof(double) * M * TS + sizeof(double) * NW * M * TS;
+    const size_t sf = sizeof(double) * NW * 6 * sf_kpw<M>() * M;
     return tile > sf ? tile : sf;
 }
 
@@ -299,12 +315,12 @@ static void symv_launch(const Ctx &c, const T *tiles, const double *v, int j0, h
     hipEvent_t e0 = c.prof_ev0, e1 = c.prof_ev1;
     c.prof_ev0 = c.prof_ev1 = nullptr;
     if (cached)
-        hipExtLaunchKernelGGL((k_symv6<T, M, true>), dim3(nsf + c.ntiles), dim3(256),
+        hipExtLaunchKernelGGL((k_symv6<T, M, true>), dim3(nsf + c.ntiles), dim3(64 * symv_waves<T, M>()),
                               (uint32_t)lds, s, e0, e1, 0u, c.N, c.n3, c.n3pad, c.rhs_cap, j0, nsf,
                               sfr, flip, c.nk, c.pc.invL, c.kvec, c.kcoef, c.rt, c.tk, c.tile_ij,
                               tiles, v, c.part, c.gate);
     else
-        hipExtLaunchKernelGGL((k_symv6<T, M, false>), dim3(nsf + c.ntiles), dim3(256),
+        hipExtLaunchKernelGGL((k_symv6<T, M, false>), dim3(nsf + c.ntiles), dim3(64 * symv_waves<T, M>()),
                               (uint32_t)lds, s, e0, e1, 0u, c.N, c.n3, c.n3pad, c.rhs_cap, j0, nsf,
                               sfr, flip, c.nk, c.pc.invL, c.kvec, c.kcoef, c.rt, c.tk, c.tile_ij,
                               tiles, v, c.part, c.gate);

@@ -77,14 +77,14 @@ __device__ inline void sf_partial_block(int b, int nkb, int N, int n3, int nk, i
 // KPW wave vectors KPW b .. KPW b + KPW - 1 and sums over every bead,
 //   C_k = sum_mu cos(k.r_mu) v_mu,   S_k = sum_mu sin(k.r_mu) v_mu,
 // with k.r_mu = 2 pi n.s_mu (s = r/L of the wrapped position) from sincospi;
-// thread t takes the beads t, t + 256, ... and the sums are combined in a
-// fixed order (an xor tree inside each wave, then the 4 waves in LDS).  The
+// thread t takes the beads t, t + 64 NW, ... and the sums are combined in a
+// fixed order (an xor tree inside each wave, then the NW waves in LDS).  The
 // workgroup then applies 2 m(k) (I - khat khat) (eq. DF, third term) and
 // writes tk[k][j0 + j] = (T^C_k, T^S_k): the sum over beads is complete, so
 // no reduction over bead chunks follows.
 template <int M> constexpr int sf_kpw() { return M <= 2 ? 2 : 1; }
 
-template <int M>
+template <int M, int NW = 4>
 __device__ inline void sf_direct_block(int b, int N, int nk, int rhs_cap, int j0, double invL,
                                        int n3, const KVec *__restrict__ kvec,
                                        const KCoef *__restrict__ kcoef,
@@ -135,7 +135,7 @@ __device__ inline void sf_direct_block(int b, int N, int nk, int rhs_cap, int j0
         if (lane == 0) smem[w * NV + i] = a;
     }
     __syncthreads();
-    // thread (q, j, half) of the first 2 KPW M: the 4 waves in order, then
+    // thread (q, j, half) of the first 2 KPW M: the NW waves in order, then
     // the projection
     if (threadIdx.x < 2 * KPW * M) {
         const int half = threadIdx.x & 1, qj = threadIdx.x >> 1, q = qj / M, j = qj % M;
@@ -145,7 +145,10 @@ __device__ inline void sf_direct_block(int b, int N, int nk, int rhs_cap, int j0
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int i = qj * 6 + 3 * half + c;
-                t[c] = ((smem[i] + smem[NV + i]) + smem[2 * NV + i]) + smem[3 * NV + i];
+                double a = smem[i];
+#pragma unroll
+                for (int w2 = 1; w2 < NW; ++w2) a += smem[w2 * NV + i];
+                t[c] = a;
             }
             const KCoef kc = kcoef[k];
             const double h = kc.hx * t[0] + kc.hy * t[1] + kc.hz * t[2];
