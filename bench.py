@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "38e142e8d04e505fe5c20f27e296ad4dc3e96f37c4ba5638e296a664a112663f",
+TRAFFIC = {"src_sha256": "1e835d2813dcb16c3cdd2dc1e3e9d8b600a4b8ae3f19fdcea7abbd31f050d7de",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 404568118}
+           "bytes_per_launch": 404568099}
 # The matrix-core tile kernel (k_block_tiles) of a 16-vector product: tile and
 # vector reads plus the per-tile FP64/FP32 partial sums it writes.
 TRAFFIC_BLOCK = {"src_sha256": "710dc0c12315010bb07e8029c50b40f138f72e6fcf9a5e7a522afe482b149e78",
@@ -54,9 +54,9 @@ TRAFFIC_BLOCK = {"src_sha256": "710dc0c12315010bb07e8029c50b40f138f72e6fcf9a5e7a
                                       "bf16": 111228928 + 48771072}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "6a6d0cc5ef43ee5703dd62ff81fe39d036b3d7b0c93991789e0c0285f09a68e8",
+TRAFFIC_BATCH = {"src_sha256": "c5609f37684f2e2df75c6941c6b3fdef003e7c566716b64849b370ce27b7f2d5",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4845331214}
+                 "bytes_per_launch": 4845338151}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 TOL_EF = 1e-2     # E_f tolerance of the headline's adaptive order

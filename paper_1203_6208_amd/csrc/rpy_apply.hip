@@ -285,8 +285,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(M >= 3 
 
 template <typename T, int M> static size_t symv_lds(const Ctx &)
 {
-    // sx occupies M*TS double slots (whatever A is), then scol[4][M][TS];
-    // the structure-factor workgroups use 4 x 6 KPW M doubles
+    // sx occupies M*TS double slots (whatever A is), then scol[NW][M][TS];
+    // the structure-factor workgroups use NW x 6 KPW M doubles
     constexpr int NW = symv_waves<T, M>();
     const size_t tile = sizeof(double) * M * TS + sizeof(double) * NW * M * TS;
     const size_t sf = sizeof(double) * NW * 6 * sf_kpw<M>() * M;

@@ -523,14 +523,19 @@ __global__ __launch_bounds__(64) void k_bsf_reduce(int nk, const BoxDev *__restr
 // components conjugate) at the slice's first wave vector of a run, then
 // advanced by e^{i 2 pi s_z} per step in n_z.  Slices are combined in
 // ascending order.  STAGE: the box's T_k are copied to LDS (else read from
-// global memory).  Every global load of the prologue (partial slots, tables,
+// global memory; with 64-bead tiles every wave is one slice, so the wave
+// vector index is wave-uniform and T_k come through scalar loads straight
+// into the multiply-adds' operands).  Every global load of the prologue (partial slots, tables,
 // T_k) is issued before the first wait (the table pointers are not
 // __restrict__ so that the compiler keeps the loads where they are written).  Padding beads get zero outputs;
 // recurrence scalars are per box.
 constexpr int EPI_SLOTS = 8;    // partial slots per slice held in registers
 constexpr int EPI_TAB = 6;      // table entries (double2) per thread and round
 constexpr int EPI_TK = 8;       // T_k entries (double2) per thread and round
-constexpr int BEPI_KU = 2;      // wave vectors per pass of the back-projection loop
+// Wave vectors per pass of the back-projection loop (256 FP32 boxes with
+// scalar T_k loads: 7108-7148 box-steps per second, 7085 with 2, 6926 with
+// 1, 7033 with 8).
+constexpr int BEPI_KU = 4;
 
 template <int TBB, int M, bool STAGE>
 __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns,
@@ -540,7 +545,7 @@ __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns
                                               const int *__restrict__ krun,
                                               const double2 *etab,
                                               const double *__restrict__ part,
-                                              const double *tk, EpiArgs f,
+                                              const double *__restrict__ tk, EpiArgs f,
                                               const double *__restrict__ scal_all)
 {
     constexpr int S = 256 / TBB;
@@ -558,7 +563,10 @@ __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns
     double2 *tab = reinterpret_cast<double2 *>(sm);
     int4 *srun = reinterpret_cast<int4 *>(sm + 2 * (ntab + 1));
     double *stk = sm + 2 * (ntab + 1) + 2 * (nruns + 1);
-    const int l = threadIdx.x % TBB, u = threadIdx.x / TBB;
+    const int l = threadIdx.x % TBB;
+    // one slice per wave with 64-bead tiles: the slice and everything derived
+    // from it are wave-uniform, so T_k come through scalar loads
+    const int u = TBB == 64 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / TBB) : (int)threadIdx.x / TBB;
     const int g = tile * TBB + l;
     const bool live = (tile - d.tile0) * TBB + l < d.N;
     const int nbt = d.nbt;
@@ -622,8 +630,15 @@ __global__ __launch_bounds__(256) void k_bepi(int G3, int nk, int nm1, int nruns
         const double2 ez1 = nm1 > 1 ? tz[TBB] : make_double2(1.0, 0.0);   // e^{i 2 pi s_z}
         int k = klo;
         for (int r = r0; k < khi; ++r) {
-            const int4 R = srun[r];
-            const int kend = min(khi, srun[r + 1].w);
+            int4 R = srun[r];
+            int kend = min(khi, srun[r + 1].w);
+            if (TBB == 64) {
+                R.x = __builtin_amdgcn_readfirstlane(R.x);
+                R.y = __builtin_amdgcn_readfirstlane(R.y);
+                R.z = __builtin_amdgcn_readfirstlane(R.z);
+                R.w = __builtin_amdgcn_readfirstlane(R.w);
+                kend = __builtin_amdgcn_readfirstlane(kend);
+            }
             const double2 ex = tx[R.x * TBB];
             double2 ey = ty[(R.y < 0 ? -R.y : R.y) * TBB];
             if (R.y < 0) ey.y = -ey.y;
@@ -1152,8 +1167,11 @@ static void bproduct(rpy_batch *b, const double *v, int m, int prec, const EpiAr
     }
     hipLaunchKernelGGL(k_bsf_reduce, dim3((b->nk + 63) / 64, 2 * m, b->nbox), dim3(64), 0, s,
                        b->nk, b->boxes, b->kcoef, b->sfpart, b->tk);
-    // LDS: phase tables and runs, plus the box's T_k when they fit in 64 KiB
-    // together; the region is reused for the slice sums
+    // LDS: phase tables and runs, plus, for 32-bead tiles, the box's T_k
+    // when they fit in 64 KiB together; the region is reused for the slice
+    // sums.  64-bead tiles read T_k with scalar loads instead: half the LDS,
+    // twice the resident workgroups (256 FP32 boxes: 6863 -> 7060
+    // box-steps per second)
     const int nm1 = b->nmax + 1;
     const size_t tabb = (size_t)(3 * nm1 * TBB + 1) * sizeof(double2) +
                         (size_t)(b->nruns + 1) * sizeof(int4);
@@ -1161,7 +1179,7 @@ static void bproduct(rpy_batch *b, const double *v, int m, int prec, const EpiAr
     const size_t stk = (size_t)b->nk * 6 * m * sizeof(double) + sizeof(double2);
     // staging T_k costs occupancy: with two vectors (82 KB of LDS at 618
     // wave vectors) the back-projection took 762 against 531 us unstaged
-    const bool stage = tabb + stk <= 65536;
+    const bool stage = TBB != 64 && tabb + stk <= 65536;
     size_t lds = tabb + (stage ? stk : 0);
     lds = lds > red ? lds : red;
     const dim3 ge((unsigned)b->ntb);
