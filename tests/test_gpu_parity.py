@@ -256,26 +256,29 @@ def test_nonfinite_position_reported():
     assert ctx.status() == 0
 
 
+@pytest.mark.parametrize("m", [1, 2])
 @pytest.mark.parametrize("prec,tol", [("f32", 2e-6), ("bf16", 2e-2)])
-def test_precision_forms_n100(n100, prec, tol):
+def test_precision_forms_n100(n100, prec, tol, m):
     """FP32 / BF16 stored real-space part with FP32 accumulation inside each
     tile; error of D.v and of dS against the FP64 oracle within the bound of
     the element rounding (2^-24, 2^-8 relative per element) times the
-    row-norm growth."""
-    _say(f"precision {prec}")
+    row-norm growth.  One vector takes the one-vector tile kernels (for BF16
+    the two-wave form), two vectors the multi-vector ones; N = 100 leaves a
+    ragged second bead tile."""
+    _say(f"precision {prec} m={m}")
     w, pos, D, _ = n100
     ctx = rpy.context_for(w, lowp=prec, max_rhs=4)
     ctx.build(_cuda(pos))
-    v = np.random.default_rng(11).standard_normal((2, w.n, 3))
-    out = ctx.apply(_cuda(v), prec=prec).cpu().numpy().reshape(2, -1)
+    v = np.random.default_rng(11).standard_normal((m, w.n, 3))
+    out = ctx.apply(_cuda(v), prec=prec).cpu().numpy().reshape(m, -1)
     ref = orc_matvec(D, v)
     assert _rel(out, ref) < tol
     lam = np.linalg.eigvalsh(D)
     lo, hi = 0.9 * lam[0], 1.1 * lam[-1]
-    dw = w.noise(m=2)
-    ds = ctx.sqrt_apply(_cuda(dw), 20, lo, hi, prec=prec).cpu().numpy().reshape(2, -1)
+    dw = w.noise(m=m)
+    ds = ctx.sqrt_apply(_cuda(dw), 20, lo, hi, prec=prec).cpu().numpy().reshape(m, -1)
     import oracle
-    ref = oracle.cheb_sqrt(D, dw.reshape(2, -1), 20, lo, hi)
+    ref = oracle.cheb_sqrt(D, dw.reshape(m, -1), 20, lo, hi)
     assert _rel(ds, ref) < 5 * tol
 
 
