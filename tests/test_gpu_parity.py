@@ -259,10 +259,10 @@ def test_nonfinite_position_reported():
 @pytest.mark.parametrize("m", [1, 2])
 @pytest.mark.parametrize("prec,tol", [("f32", 2e-6), ("bf16", 2e-2)])
 def test_precision_forms_n100(n100, prec, tol, m):
-    """FP32 / BF16 stored real-space part with FP32 accumulation inside each
-    tile; error of D.v and of dS against the FP64 oracle within the bound of
-    the element rounding (2^-24, 2^-8 relative per element) times the
-    row-norm growth.  One vector takes the one-vector tile kernels (for BF16
+    """FP32 / BF16 stored real-space part (the tile products of one to four
+    vectors widen each entry and accumulate in FP64); error of D.v and of dS
+    against the FP64 oracle within the bound of the element rounding (2^-24,
+    2^-8 relative per element) times the row-norm growth.  One vector takes the one-vector tile kernels (for BF16
     the two-wave form), two vectors the multi-vector ones; N = 100 leaves a
     ragged second bead tile."""
     _say(f"precision {prec} m={m}")
