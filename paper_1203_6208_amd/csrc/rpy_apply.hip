@@ -550,6 +550,10 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
     else
         kloop(kvec, tk_g + (size_t)j0 * 6, 6 * rhs_cap);
     const double ya = f.scal ? f.scal[2] : 0.0, yb = f.scal ? f.scal[3] : 0.0;
+    // the fused trial, as k_trial_sum: skipped once the order is settled or
+    // below the call's first order
+    const bool trial = f.trial_n > 0 && (f.mode == EPI_CHEB_FIRST || f.mode == EPI_CHEB_NEXT) &&
+                       !f.adapt->done && f.trial_n >= f.adapt->n_start;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
 #pragma unroll
@@ -560,11 +564,13 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
             if (sub == 0) red[w][c][bl] = v;
         }
         __syncthreads();
+        double ta = 0.0, tb2 = 0.0;   // this entry's share of the trial's dot products
         if (eth) {
             double yy = 0.0;
 #pragma unroll
             for (int ww = 0; ww < 16; ++ww) yy += red[ww][ec][eb];
             const size_t o = (size_t)(j0 + j) * n3 + 3 * (size_t)ebead + ec;
+            double vnew = 0.0;   // the vector this epilogue produces
             if (f.mode == EPI_APPLY) {
                 f.vout[o] = yy;
             } else if (f.mode == EPI_CHEB_FIRST) {
@@ -573,14 +579,38 @@ __global__ __launch_bounds__(1024) void k_kspace_epi(int N, int n3, int n3pad, i
                 f.vout[o] = v1;
                 f.acc[o] = 0.5 * f.scal[8] * v0 + f.scal[9] * v1;
                 if (f.dv) f.dv[o] = yy;
+                vnew = v1;
             } else if (f.mode == EPI_CHEB_NEXT) {
                 const double vp = 2.0 * (ya * yy - yb * pv[j]) - pv2[j];
                 f.vout[o] = vp;
                 f.acc[o] = pa[j] + f.scal[8 + f.p] * vp;
+                vnew = vp;
             } else {
                 const double mp = f.scal[8 + f.p] * pa[j] + 2.0 * (ya * yy - yb * pv[j]) - pv2[j];
                 f.vout[o] = mp;
                 f.dv[o] = f.xs * ya * mp;
+            }
+            if (trial) {   // the terms in k_trial_sum's order; V_p from the register
+                const double *vh = f.vhist + o;
+                const double v0 = vh[0];
+                double d = -0.5 * f.scal[8] * v0;
+                for (int q = 0; q < f.trial_n; ++q)
+                    d += f.scal[8 + q] * (q == f.p ? vnew : vh[(size_t)q * f.ps]);
+                f.ds[o] = d;
+                ta = d * d;
+                tb2 = v0 * f.ddw[o];
+            }
+        }
+        if (trial && w == 0) {   // the 3 EPI_BEADS entries are lanes of the first wave
+#pragma unroll
+            for (int o2 = 32; o2 >= 1; o2 >>= 1) {
+                ta += __shfl_xor(ta, o2);
+                tb2 += __shfl_xor(tb2, o2);
+            }
+            if (lane == 0) {
+                double *tp = f.tpart + ((size_t)(j0 + j) * gridDim.x + blockIdx.x) * 2;
+                tp[0] = ta;
+                tp[1] = tb2;
             }
         }
         if (j + 1 < M) __syncthreads();   // red is rewritten by the next vector
@@ -825,6 +855,20 @@ void launch_trial(const Ctx &c, int m, int n, int nmax, double tol, size_t ps,
                        c.scal, c.vhist, ddw, ds, c.tpart);
     hipLaunchKernelGGL(k_trial_check, dim3(1), dim3(1024), 0, s, m, nchunk, n, nmax, tol,
                        c.adapt, c.tpart, c.scal, e_f);
+}
+
+void launch_trial_check(const Ctx &c, int m, int n, int nmax, double tol, double *e_f,
+                        hipStream_t s)
+{
+    const int nchunk = (c.N + EPI_BEADS - 1) / EPI_BEADS;   // k_kspace_epi workgroups
+    hipLaunchKernelGGL(k_trial_check, dim3(1), dim3(1024), 0, s, m, nchunk, n, nmax, tol,
+                       c.adapt, c.tpart, c.scal, e_f);
+}
+
+int trial_chunks(int N)
+{
+    const int a = (3 * N + 255) / 256, b = (N + EPI_BEADS - 1) / EPI_BEADS;
+    return a > b ? a : b;
 }
 
 // E_f = sqrt(|dS.dS - dW.(D dW)| / dW.(D dW)), one workgroup per RHS.

@@ -340,7 +340,7 @@ extern "C" int rpy_create(rpy_ctx **out, const rpy_params *p)
         (rc = dalloc(&c.red, 64)) || (rc = dalloc(&c.flags, 4)) ||
         (rc = dalloc(&c.lanc, 2 * MAX_LANCZOS)) ||
         (rc = dalloc(&c.adapt, 1)) ||
-        (rc = dalloc(&c.tpart, (size_t)c.rhs_cap * ((c.n3 + 255) / 256) * 2)) ||
+        (rc = dalloc(&c.tpart, (size_t)c.rhs_cap * trial_chunks(c.N) * 2)) ||
         (c.cheb_keep > 0 && (rc = dalloc(&c.vhist, (size_t)c.cheb_keep * c.rhs_cap * nv))) ||
         (c.grad && ((rc = dalloc(&c.wgrad, te)) ||
                     (rc = dalloc(&c.xy, (size_t)c.cheb_keep * 2 * nv)) ||
@@ -563,7 +563,10 @@ static int adapt_first(int floor_n, double d_min, double d_max, int nmax)
 // trial run under the gate, so that the kernels of everything past the
 // settled order return at once.  host_first is the first order the device
 // can start from (no trial is enqueued below it).  dS of the settled order
-// ends in out, its E_f in e_f.
+// ends in out, its E_f in e_f.  Where the product ends in k_kspace_epi (tile
+// and matrix-free products; not the block product), that epilogue forms the
+// trial of the order it completes, so that only the check is a launch of
+// its own.
 static void cheb_adapt_run(rpy_ctx *x, int m, int prec, int first, int host_first, int nmax,
                            double tol, double *out, double *e_f, hipStream_t s)
 {
@@ -571,10 +574,13 @@ static void cheb_adapt_run(rpy_ctx *x, int m, int prec, int first, int host_firs
     const size_t ps = (size_t)c.rhs_cap * c.n3;
     double *vh = c.vhist;
     const int *done = &c.adapt->done;
-    auto trial = [&](int n) {
-        if (n >= host_first) launch_trial(c, m, n, nmax, tol, ps, x->ddw, out, e_f, s);
+    auto trial = [&](int n, bool fused) {
+        if (n < host_first) return;
+        if (fused) launch_trial_check(c, m, n, nmax, tol, e_f, s);
+        else launch_trial(c, m, n, nmax, tol, ps, x->ddw, out, e_f, s);
     };
-    if (first == 2) trial(2);
+    const bool fuse = !(c.block && m >= BLOCK_MIN_RHS);
+    if (first == 2) trial(2, false);
     for (int p = first; p < nmax; ++p) {
         EpiArgs f{};
         f.m = m;
@@ -592,10 +598,20 @@ static void cheb_adapt_run(rpy_ctx *x, int m, int prec, int first, int host_firs
         }
         f.pack = p + 1 < nmax;   // V_p is the next product's input
         f.pack_prec = prec;
+        const bool fused = fuse && p + 1 >= host_first;
+        if (fused) {
+            f.trial_n = p + 1;
+            f.adapt = c.adapt;
+            f.vhist = vh;
+            f.ps = ps;
+            f.ddw = x->ddw;
+            f.ds = out;
+            f.tpart = c.tpart;
+        }
         c.gate = p >= host_first ? done : nullptr;   // a trial may have settled the order
         product(x, f.vprev, m, prec, f, s, p > first);
         c.gate = nullptr;
-        trial(p + 1);
+        trial(p + 1, fused);
     }
 }
 

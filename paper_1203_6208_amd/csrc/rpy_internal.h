@@ -437,7 +437,7 @@ struct Ctx {
     int cheb_keep = 0;           // Chebyshev vectors kept for the adaptive order
     double *vhist = nullptr;     // [cheb_keep][rhs_cap][3N]
     AdaptState *adapt = nullptr; // adaptive-order state
-    double *tpart = nullptr;     // [rhs_cap][ceil(3N/256)][2] partial dot products of a trial
+    double *tpart = nullptr;     // [rhs_cap][trial_chunks(N)][2] partial dot products of a trial
     // While set, every product kernel first reads *gate and returns at once
     // if it is non-zero (the products an adaptive call enqueues past the
     // order it may settle at).
@@ -500,6 +500,19 @@ struct EpiArgs {
     double xs;             // EPI_ADJ: dv = xs * ya * vout
     int pack;              // block product: also write vout in the operand layouts of
     int pack_prec;         //   tiles of precision pack_prec (the next product's input)
+    // Adaptive order (k_kspace_epi only): with trial_n > 0 the epilogue also
+    // forms the trial of order trial_n from the vectors it has just written,
+    // as k_trial_sum does -- dS = -c_0/2 V_0 + sum_{q < trial_n} c_q V_q
+    // into ds, and per workgroup the partial sums of dS.dS and V_0.(D dW)
+    // into tpart[j][workgroup][2] -- unless the order is settled or below
+    // the call's first order; k_trial_check then reduces them.
+    int trial_n;
+    const AdaptState *adapt;
+    const double *vhist;   // V_q at vhist + q ps
+    size_t ps;
+    const double *ddw;     // D.dW [m][3N]
+    double *ds;            // dS [m][3N]
+    double *tpart;
 };
 void launch_symv(const Ctx &c, int prec, const double *v, int j0, int mc, hipStream_t s);
 // Block product D.V for 5 <= m <= 16 vectors (c.block): the tile product on
@@ -529,6 +542,14 @@ void launch_cheb_coeffs(const Ctx &c, int n_cheb, int rule, double C, double dmi
 // written), else puts the coefficients of order n + 1 in place.
 void launch_trial(const Ctx &c, int m, int n, int nmax, double tol, size_t ps,
                   const double *ddw, double *ds, double *e_f, hipStream_t s);
+// The same decision when the back-projection epilogue of the product that
+// completed order n formed the trial (EpiArgs::trial_n): only the check.
+void launch_trial_check(const Ctx &c, int m, int n, int nmax, double tol, double *e_f,
+                        hipStream_t s);
+// Partial-sum chunks of a trial per right-hand side: the larger of the
+// separate trial kernel's (256 entries each) and the epilogue's (one per
+// workgroup), which sizes c.tpart.
+int trial_chunks(int N);
 void launch_sqrt_error(const Ctx &c, int m, const double *dw, const double *ddw,
                        const double *ds, double *e_f, hipStream_t s);
 void launch_fill(double *p, double v, size_t n, hipStream_t s);
