@@ -42,21 +42,21 @@ HBM_PEAK_GBS = 8000.0
 # what the L2 fetches over the fabric, Infinity-Cache hits included.  Valid only for the
 # kernel source they were measured on (sha256 of the kernel's source files);
 # otherwise reported as null.
-TRAFFIC = {"src_sha256": "1e835d2813dcb16c3cdd2dc1e3e9d8b600a4b8ae3f19fdcea7abbd31f050d7de",
+TRAFFIC = {"src_sha256": "9708caa00cf7f2dfb4401bcffc1e9d40314e85844f0a5881ae71da0b2507a829",
            "files": ("rpy_apply.hip", "rpy_sf.h", "rpy_internal.h"),
-           "bytes_per_launch": 404568099}
+           "bytes_per_launch": 404568114}
 # The matrix-core tile kernel (k_block_tiles) of a 16-vector product: tile and
 # vector reads plus the per-tile FP64/FP32 partial sums it writes.
-TRAFFIC_BLOCK = {"src_sha256": "710dc0c12315010bb07e8029c50b40f138f72e6fcf9a5e7a522afe482b149e78",
+TRAFFIC_BLOCK = {"src_sha256": "a8c5b8b032e98909eaaa0615d5f4e928507f6de593cdc81e6e8dc0c21f087a7d",
                  "files": ("rpy_block.hip", "rpy_internal.h"),
-                 "bytes_per_launch": {"f64": 420303462 + 97542144,
-                                      "f32": 215974093 + 48771789,
-                                      "bf16": 111228928 + 48771072}}
+                 "bytes_per_launch": {"f64": 420300874 + 97542144,
+                                      "f32": 215952215 + 48771689,
+                                      "bf16": 111220975 + 48771088}}
 # The batched FP32 tile product over the 256-box ensemble (k_bsymv<64, float, 1>),
 # same calibration (FETCH x 2.0, WRITE x 1.0).
-TRAFFIC_BATCH = {"src_sha256": "c5609f37684f2e2df75c6941c6b3fdef003e7c566716b64849b370ce27b7f2d5",
+TRAFFIC_BATCH = {"src_sha256": "3f4d6f7ef76d80f5d4d67d3389d5c42216a1e5d5650dc93e70b33bf6bf01bfda",
                  "files": ("rpy_batch.hip", "rpy_internal.h"),
-                 "bytes_per_launch": 4845338151}
+                 "bytes_per_launch": 4845338478}
 METRIC = "BD steps/s at N=4000 (Ewald-RPY D·F + Chebyshev √D·dW) vs plain FP64"
 BOUNDS_C = 60.0   # C of the paper's bound rule; chosen so that d_min < lambda_min here
 TOL_EF = 1e-2     # E_f tolerance of the headline's adaptive order
